@@ -1,0 +1,237 @@
+"""FP64 CPU oracle for the RT-GuIDE rasterizer (arXiv 2409.18122).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with
+the HIP library under ``paper_2409_18122_amd`` and never imports it.
+
+The arithmetic lives in ``rtg_oracle.c`` (plain C, binary64, OpenMP over
+pixels); this module only marshals numpy arrays.  Float32 inputs are promoted
+exactly to float64.  See the C file's header for which passage of the paper
+each function follows.
+
+Functions: ``project``, ``render``, ``count``, ``keys``, ``loss``, ``score``,
+``adjoint``.  Parity status: every function here is pinned by the
+``-m "not gpu"`` tests (closed forms, invariants, brute force, finite
+differences); see tests/test_oracle_*.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rtg_oracle.c")
+_LIB = os.path.join(_HERE, "librtgo.so")
+
+# Relative widths of the near-threshold bands: a per-pixel decision whose
+# operand lies this close (relative) to its threshold is taken both ways by the
+# oracle, since a binary32 evaluation may legitimately fall on either side.
+EV_ALPHA = 1e-4
+EV_T = 1e-4
+
+
+def build(force: bool = False) -> str:
+    """Compile rtg_oracle.c with gcc (binary64, no FP contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        p = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.rtgo_project.argtypes = [i64] + [p] * 6 + [p] * 8
+        L.rtgo_project.restype = ctypes.c_int
+        L.rtgo_render.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 3 + [p] +
+                                  [ctypes.c_double] * 2 + [p] * 7 + [i64, p, p])
+        L.rtgo_render.restype = i64
+        L.rtgo_count.argtypes = [i64] + [p] * 6 + [ctypes.c_int] * 2 + [p, p]
+        L.rtgo_count.restype = ctypes.c_int
+        L.rtgo_keys.argtypes = [i64] + [p] * 6 + [ctypes.c_int] * 2 + [i64, p, p]
+        L.rtgo_keys.restype = ctypes.c_int
+        L.rtgo_loss.argtypes = [i64, p, p, p, p, ctypes.c_double, p, p]
+        L.rtgo_loss.restype = ctypes.c_double
+        L.rtgo_score.argtypes = [i64] + [p] * 7 + [ctypes.c_int, p, ctypes.c_int, ctypes.c_int, p]
+        L.rtgo_score.restype = ctypes.c_int
+        L.rtgo_adjoint.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 2 + [p] * 10)
+        L.rtgo_adjoint.restype = ctypes.c_int
+        L.rtgo_set_threads.argtypes = [ctypes.c_int]
+        L.rtgo_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def set_threads(n: int) -> None:
+    lib().rtgo_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().rtgo_max_threads())
+
+
+def _d(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _G:
+    """Scene promoted to float64 (kept alive while pointers are in use)."""
+
+    def __init__(self, s):
+        self.n = int(np.asarray(s["opacity"]).shape[0])
+        self.means = _d(s["means"]).reshape(3, self.n)
+        self.ls = _d(s["log_scales"]).reshape(3, self.n)
+        self.q = _d(s["quats"]).reshape(4, self.n)
+        self.o = _d(s["opacity"]).reshape(self.n)
+        self.c = _d(s.get("colors", np.zeros((3, self.n)))).reshape(3, self.n)
+        self.u = _d(s.get("uncert", np.zeros(self.n))).reshape(self.n)
+
+    def geo(self):
+        return [_ptr(self.means), _ptr(self.ls), _ptr(self.q), _ptr(self.o)]
+
+    def all(self):
+        return self.geo() + [_ptr(self.c), _ptr(self.u)]
+
+
+def cam_array(cam):
+    R = np.asarray(cam["R"], dtype=np.float64).reshape(9)
+    T = np.asarray(cam["T"], dtype=np.float64).reshape(3)
+    return _d([cam["width"], cam["height"], cam["fx"], cam["fy"], cam["cx"], cam["cy"],
+               *R, *T])
+
+
+def set_array(settings):
+    """Settings are taken at their binary32 values, as the library receives them."""
+    f = lambda k: float(np.float32(settings[k]))
+    return _d([f("T_min"), f("alpha_min"), f("alpha_max"), f("z_near"), f("eps2d")])
+
+
+def project(scene, cam, settings):
+    g = _G(scene)
+    n = g.n
+    out = {
+        "valid": np.zeros(n, np.int32), "mean2d": np.zeros((2, n)),
+        "cov2d": np.zeros((3, n)), "conic": np.zeros((3, n)),
+        "depth": np.zeros(n), "depth_bits": np.zeros(n, np.uint32),
+        "half": np.zeros((2, n)), "box": np.zeros((4, n), np.int32),
+    }
+    ca, sa = cam_array(cam), set_array(settings)
+    lib().rtgo_project(n, *g.geo(), _ptr(ca), _ptr(sa),
+                       *[_ptr(out[k]) for k in ("valid", "mean2d", "cov2d", "conic",
+                                                "depth", "depth_bits", "half", "box")])
+    out["valid"] = out["valid"].astype(bool)
+    return out
+
+
+def render(scene, cam, settings, mode="tiled", tile=None, roi=None,
+           ev_alpha=EV_ALPHA, ev_t=EV_T, alt_cap=None):
+    """Render one camera. Returns dict with rgb (3,H,W), depth, alpha, unc,
+    T (H,W), ncontrib, nevents (H,W int32) and the alternatives of event pixels:
+    alt_pix (m,), alt_val (m, 4, 6) over (r, g, b, depth, alpha, unc)."""
+    g = _G(scene)
+    W, H = int(cam["width"]), int(cam["height"])
+    P = W * H
+    tw, th = tile if tile is not None else (settings.get("tile_w", 16), settings.get("tile_h", 16))
+    m = {"brute": 0, "tiled": 1}[mode]
+    ca, sa = cam_array(cam), set_array(settings)
+    roi_a = None if roi is None else np.ascontiguousarray(np.asarray(roi, np.int32))
+    rgb = np.zeros((3, H, W)); dep = np.zeros((H, W)); alp = np.zeros((H, W))
+    unc = np.zeros((H, W)); T = np.ones((H, W))
+    nc = np.zeros((H, W), np.int32); ne = np.zeros((H, W), np.int32)
+    cap = alt_cap if alt_cap is not None else max(1024, P // 50)
+    apix = np.zeros(cap, np.int64); aval = np.zeros((cap, 4, 6))
+    nalt = lib().rtgo_render(g.n, *g.all(), _ptr(ca), _ptr(sa), m, int(tw), int(th), _ptr(roi_a),
+                             float(ev_alpha), float(ev_t), _ptr(rgb), _ptr(dep), _ptr(alp),
+                             _ptr(unc), _ptr(T), _ptr(nc), _ptr(ne), cap, _ptr(apix), _ptr(aval))
+    if nalt < 0:
+        raise MemoryError("oracle render failed")
+    k = min(int(nalt), cap)
+    return {"rgb": rgb, "depth": dep, "alpha": alp, "unc": unc, "T": T,
+            "ncontrib": nc, "nevents": ne, "alt_pix": apix[:k], "alt_val": aval[:k],
+            "alt_overflow": int(nalt) > cap}
+
+
+def count(scene, cam, settings, tile=(16, 16)):
+    g = _G(scene)
+    nv = ctypes.c_int64(); npairs = ctypes.c_int64()
+    ca, sa = cam_array(cam), set_array(settings)
+    lib().rtgo_count(g.n, *g.geo(), _ptr(ca), _ptr(sa), int(tile[0]), int(tile[1]),
+                     ctypes.addressof(nv), ctypes.addressof(npairs))
+    return int(nv.value), int(npairs.value)
+
+
+def keys(scene, cams, settings, tile=(16, 16)):
+    """Sorted (tile<<32 | depth bits, Gaussian index) pairs over several cameras,
+    global tile ids offset by the tiles of the preceding cameras."""
+    g = _G(scene)
+    sa = set_array(settings)
+    tw, th = int(tile[0]), int(tile[1])
+    all_k, all_v = [], []
+    base = 0
+    for cam in cams:
+        _, npairs = count(scene, cam, settings, tile)
+        k = np.zeros(npairs, np.uint64); v = np.zeros(npairs, np.uint32)
+        ca = cam_array(cam)
+        lib().rtgo_keys(g.n, *g.geo(), _ptr(ca), _ptr(sa), tw, th, base, _ptr(k), _ptr(v))
+        all_k.append(k); all_v.append(v)
+        base += ((int(cam["width"]) + tw - 1) // tw) * ((int(cam["height"]) + th - 1) // th)
+    return np.concatenate(all_k), np.concatenate(all_v)
+
+
+def loss(rgb, depth, target_rgb, target_depth, w_depth=0.5):
+    rgb = _d(rgb); dep = _d(depth); trgb = _d(target_rgb); tdep = _d(target_depth)
+    P = dep.size
+    grgb = np.zeros_like(rgb); gdep = np.zeros_like(dep)
+    L = lib().rtgo_loss(P, _ptr(rgb), _ptr(dep), _ptr(trgb), _ptr(tdep), float(w_depth),
+                        _ptr(grgb), _ptr(gdep))
+    return float(L), grgb, gdep
+
+
+def score(scene, cams, settings, tile=(16, 16)):
+    g = _G(scene)
+    ca = np.ascontiguousarray(np.concatenate([cam_array(c) for c in cams]))
+    sa = set_array(settings)
+    out = np.zeros(len(cams))
+    rc = lib().rtgo_score(g.n, *g.all(), _ptr(ca), len(cams), _ptr(sa), int(tile[0]),
+                          int(tile[1]), _ptr(out))
+    if rc:
+        raise MemoryError("oracle score failed")
+    return out
+
+
+def adjoint(scene, cam, settings, g_rgb=None, g_depth=None, g_alpha=None, g_unc=None,
+            tile=(16, 16), want_2d=False):
+    """Gradient of sum_p <g_img(p), image(p)> for one camera with respect to
+    means (3,N), log_scales (3,N), quats (4,N), opacity (N,), colors (3,N)."""
+    g = _G(scene)
+    n = g.n
+    out = {"means": np.zeros((3, n)), "log_scales": np.zeros((3, n)),
+           "quats": np.zeros((4, n)), "opacity": np.zeros(n), "colors": np.zeros((3, n))}
+    g2d = np.zeros((n, 10)) if want_2d else None
+    planes = [None if a is None else _d(a) for a in (g_rgb, g_depth, g_alpha, g_unc)]
+    ca, sa = cam_array(cam), set_array(settings)
+    rc = lib().rtgo_adjoint(n, *g.all(), _ptr(ca), _ptr(sa), int(tile[0]), int(tile[1]),
+                            *[_ptr(a) for a in planes],
+                            _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+                            _ptr(out["opacity"]), _ptr(out["colors"]), _ptr(g2d))
+    if rc:
+        raise MemoryError("oracle adjoint failed")
+    if want_2d:
+        out["screen"] = g2d
+    return out

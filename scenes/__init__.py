@@ -1,0 +1,246 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/benchmark and the oracle.
+
+This module only draws random numbers and builds camera poses. It holds none of
+the rasterizer's arithmetic (no projection, compositing, loss or scoring), so
+both sides can take their inputs from it without sharing any of the method.
+
+Conventions
+-----------
+* A scene is a dict of contiguous float32 numpy arrays in planar
+  structure-of-arrays layout: ``means`` (3, N), ``log_scales`` (3, N),
+  ``quats`` (4, N; w, x, y, z), ``opacity`` (N,), ``colors`` (3, N),
+  ``uncert`` (N,).
+* A camera is a dict with ``width``, ``height``, ``fx``, ``fy``, ``cx``,
+  ``cy`` and a pose ``R`` (3x3, camera-to-world, column k is camera axis k in
+  world coordinates) and ``T`` (camera centre in the world) - the pose
+  (R_k, T_k) of the projection in Sec. III (Gaussian Splatting paragraph).
+  Camera axes follow OpenCV: x right, y down, z forward.
+* Random draws use ``numpy.random.default_rng(seed)`` in FP64 in the fixed
+  order means, log-scales, quaternions, opacity, colours, uncertainty, poses,
+  and are then rounded to float32. Perturbations for targets use
+  ``default_rng(seed + 1000)``. ``N(a, b)`` means mean a, standard deviation b.
+
+The five workloads mirror the shapes of the paper's use of the rasterizer: a
+small forward render, a 640x480 mapping step (Sec. III eq. (2)/(4)), batched
+scoring of candidate views (Sec. IV-A eq. (7), "hundreds of viewpoints" in
+Sec. V-A), multi-keyframe mapping, and uneven batched scoring. The paper's
+datasets (iTHOR, MP3D, robot logs) are not available; these seeded scenes
+stand in for them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+F32 = np.float32
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(F32))
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def _unit_quats(rng, n):
+    q = rng.standard_normal((4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    return q
+
+
+def make_camera(width, height, fx, fy, cx, cy, R=None, T=None):
+    R = np.eye(3) if R is None else np.asarray(R, dtype=np.float64)
+    T = np.zeros(3) if T is None else np.asarray(T, dtype=np.float64)
+    return {
+        "width": int(width), "height": int(height),
+        "fx": float(F32(fx)), "fy": float(F32(fy)),
+        "cx": float(F32(cx)), "cy": float(F32(cy)),
+        "R": _f32(R).reshape(3, 3), "T": _f32(T).reshape(3),
+    }
+
+
+def default_intrinsics(width, height):
+    """f = 525 * W / 640 and principal point at the image centre."""
+    f = 525.0 * width / 640.0
+    return f, f, width / 2.0, height / 2.0
+
+
+def yaw_pose(x, y, z, yaw):
+    """Level camera (zero pitch/roll) in a z-up world, looking along yaw."""
+    fwd = np.array([np.cos(yaw), np.sin(yaw), 0.0])
+    right = np.array([np.sin(yaw), -np.cos(yaw), 0.0])
+    down = np.array([0.0, 0.0, -1.0])
+    R = np.stack([right, down, fwd], axis=1)
+    return R, np.array([x, y, z], dtype=np.float64)
+
+
+def random_rotation(rng):
+    """Uniformly distributed rotation matrix (QR of a Gaussian matrix, sign-fixed)."""
+    m = rng.standard_normal((3, 3))
+    q, r = np.linalg.qr(m)
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def _gaussians(rng, n, lo, hi, ls_mean=-3.0, ls_std=0.5, opacity="sigmoid"):
+    lo = np.asarray(lo, dtype=np.float64)[:, None]
+    hi = np.asarray(hi, dtype=np.float64)[:, None]
+    means = lo + (hi - lo) * rng.random((3, n))
+    log_scales = rng.normal(ls_mean, ls_std, (3, n))
+    quats = _unit_quats(rng, n)
+    if opacity == "sigmoid":
+        op = _sigmoid(rng.standard_normal(n))
+    elif opacity == "beta":
+        op = rng.beta(0.5, 0.5, n)
+    else:
+        raise ValueError(opacity)
+    colors = rng.random((3, n))
+    uncert = rng.random(n)
+    return means, log_scales, quats, op, colors, uncert
+
+
+def _pack(means, log_scales, quats, op, colors, uncert):
+    return {
+        "means": _f32(means), "log_scales": _f32(log_scales),
+        "quats": _f32(quats), "opacity": _f32(op),
+        "colors": _f32(colors), "uncert": _f32(uncert),
+    }
+
+
+def _cluster_uncertainty(rng, means, uncert, lo, hi, n_centres=8, frac=0.1):
+    """Mark the frac*N Gaussians nearest any of n_centres random centres as u=1."""
+    lo = np.asarray(lo, dtype=np.float64)[:, None]
+    hi = np.asarray(hi, dtype=np.float64)[:, None]
+    centres = lo + (hi - lo) * rng.random((3, n_centres))
+    d2 = np.full(means.shape[1], np.inf)
+    for k in range(n_centres):
+        d2 = np.minimum(d2, ((means - centres[:, k:k + 1]) ** 2).sum(0))
+    m = int(frac * means.shape[1])
+    idx = np.argsort(d2, kind="stable")[:m]
+    uncert = uncert.copy()
+    uncert[idx] = 1.0
+    return uncert
+
+
+def perturbed(scene, seed):
+    """Target scene: means + N(0, 0.01), colours clip(c + N(0, 0.05), 0, 1)."""
+    rng = np.random.default_rng(seed + 1000)
+    m = scene["means"].astype(np.float64)
+    c = scene["colors"].astype(np.float64)
+    m = m + rng.normal(0.0, 0.01, m.shape)
+    c = np.clip(c + rng.normal(0.0, 0.05, c.shape), 0.0, 1.0)
+    out = dict(scene)
+    out["means"] = _f32(m)
+    out["colors"] = _f32(c)
+    return out
+
+
+ROOM_LO = (-10.0, -10.0, 0.0)
+ROOM_HI = (10.0, 10.0, 4.0)
+
+
+def config1(n=2000, seed=1):
+    """Plain forward: 2,000 Gaussians, one 128x96 camera, identity pose."""
+    rng = np.random.default_rng(seed)
+    g = _pack(*_gaussians(rng, n, (-2, -2, 2), (2, 2, 6)))
+    cams = [make_camera(128, 96, 100.0, 100.0, 64.0, 48.0)]
+    return g, cams
+
+
+def config2(n=200_000, seed=2, width=640, height=480):
+    """Mapping step: 200k Gaussians in a 10 x 4 x 10 m camera-frame box, 640x480."""
+    rng = np.random.default_rng(seed)
+    g = _pack(*_gaussians(rng, n, (-5, -2, 2), (5, 2, 12)))
+    f = 525.0 * width / 640.0
+    cams = [make_camera(width, height, f, f, width / 2.0, height / 2.0)]
+    return g, cams, perturbed(g, seed)
+
+
+def _yaw_poses(rng, n_views, width, height, f=None):
+    fx, fy, cx, cy = default_intrinsics(width, height)
+    if f is not None:
+        fx = fy = f
+    cams = []
+    xy = rng.uniform(-9.5, 9.5, (n_views, 2))
+    yaw = rng.uniform(0.0, 2.0 * np.pi, n_views)
+    for v in range(n_views):
+        R, T = yaw_pose(xy[v, 0], xy[v, 1], 1.0, yaw[v])
+        cams.append(make_camera(width, height, fx, fy, cx, cy, R, T))
+    return cams
+
+
+def config3(n=500_000, seed=3, n_views=64, width=320, height=240):
+    """Batched scoring: 500k Gaussians in a 20x20x4 m room, 64 level poses."""
+    rng = np.random.default_rng(seed)
+    means, ls, q, op, col, unc = _gaussians(rng, n, ROOM_LO, ROOM_HI)
+    unc = _cluster_uncertainty(rng, means, unc, ROOM_LO, ROOM_HI)
+    g = _pack(means, ls, q, op, col, unc)
+    cams = _yaw_poses(rng, n_views, width, height)
+    return g, cams
+
+
+def config4(n=1_000_000, seed=4, n_views=8, width=1280, height=720):
+    """Batched keyframe backward: 1M Gaussians, 8 keyframes of 1280x720."""
+    rng = np.random.default_rng(seed)
+    g = _pack(*_gaussians(rng, n, ROOM_LO, ROOM_HI))
+    cams = _yaw_poses(rng, n_views, width, height, f=1050.0 * width / 1280.0)
+    return g, cams, perturbed(g, seed)
+
+
+RES5 = ((160, 120), (320, 240), (640, 480))
+
+
+def config5(n=2_000_000, seed=5, n_views=256):
+    """Uneven batched scoring: 2M Gaussians, 256 views of mixed resolution."""
+    rng = np.random.default_rng(seed)
+    means, ls, q, op, col, unc = _gaussians(rng, n, ROOM_LO, ROOM_HI,
+                                            ls_mean=-3.5, ls_std=0.7,
+                                            opacity="beta")
+    unc = _cluster_uncertainty(rng, means, unc, ROOM_LO, ROOM_HI)
+    g = _pack(means, ls, q, op, col, unc)
+    res = rng.integers(0, len(RES5), n_views)
+    pos = np.stack([rng.uniform(-9.5, 9.5, n_views),
+                    rng.uniform(-9.5, 9.5, n_views),
+                    rng.uniform(0.2, 3.8, n_views)], axis=1)
+    cams = []
+    for v in range(n_views):
+        w, h = RES5[res[v]]
+        fx, fy, cx, cy = default_intrinsics(w, h)
+        cams.append(make_camera(w, h, fx, fy, cx, cy,
+                                random_rotation(rng), pos[v]))
+    return g, cams
+
+
+def tiny_scene(n, seed, width=32, height=24, depth=(1.5, 4.0), ls=(-2.5, 0.5),
+               opacity="sigmoid"):
+    """Small random scene in front of an identity camera (for brute force)."""
+    rng = np.random.default_rng(seed)
+    f = 0.9 * width
+    zlo, zhi = depth
+    half_w = 0.5 * width / f * zlo
+    half_h = 0.5 * height / f * zlo
+    g = _pack(*_gaussians(rng, n, (-half_w, -half_h, zlo), (half_w, half_h, zhi),
+                          ls_mean=ls[0], ls_std=ls[1], opacity=opacity))
+    cam = make_camera(width, height, f, f, width / 2.0 - 0.5, height / 2.0 - 0.5)
+    return g, [cam]
+
+
+def subset(scene, idx):
+    """Gaussians at positions idx (keeps planar layout)."""
+    out = {}
+    for k, a in scene.items():
+        out[k] = np.ascontiguousarray(a[..., idx])
+    return out
+
+
+def n_gaussians(scene):
+    return int(scene["opacity"].shape[0])
+
+
+DEFAULT_SETTINGS = {
+    "tile_w": 16, "tile_h": 16, "batch": 0,
+    "T_min": 1e-4, "alpha_min": 1.0 / 255.0, "alpha_max": 0.99,
+    "z_near": 0.2, "eps2d": 0.0,
+}
