@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X Gaussian-splatting rasterizer on one GPU.
+
+Step (timed): one mapping iteration on the 640x480 workload with 200k
+Gaussians - projection, depth sort and tile binning, forward compositing,
+L1 loss (colour 1, depth 0.5) and the full backward to the Gaussian
+parameters.  `value` = pixels per second of that step (Mpix/s).
+Alongside: candidate views scored per second, batched (one persistent launch /
+captured graph) vs plain (per-view launches), on the 64-view 320x240 workload
+(500k Gaussians) and the 256-view uneven workload (2M Gaussians); the roofline
+of the dominant kernel; and the FP64 oracle timed on the host cores.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "render+backward Mpix/s and candidate views scored/s, batched vs plain, 1 GPU"
+
+# Algorithmic work per unit ("Roofline"):
+#  forward compositing: 20 FP32 VALU operations per contributing pixel-splat pair;
+#  backward compositing: 55 FP32 VALU operations per contributing pair.
+OPS_PER_PAIR = {"render": 20.0, "render_backward": 55.0}
+# MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s
+# (unpacked FP32; the packed 157.3 TFLOP/s peak counts 2 lanes x FMA = 4 flops).
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-scoring", action="store_true", help="skip the view-scoring workloads")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tile", type=str, default="16x16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the rasterizer "
+              "path has no multi-GPU component in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2409_18122_amd import raster
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    S = dict(scenes.DEFAULT_SETTINGS, tile_w=tw, tile_h=th)
+    ctx = raster.Context(0)
+    dev = torch.device("cuda:0")
+
+    # ------------------------------------------------------- mapping step
+    log("setup: 640x480 mapping workload, 200k Gaussians")
+    g_np, cams, tgt_np = scenes.config2()
+    g = raster.to_device(g_np)
+    tg = raster.to_device(tgt_np)
+    target, tf = raster.render(ctx, tg, cams, S, want=("rgb", "depth"))
+    tf.close()
+    P = cams[0]["width"] * cams[0]["height"]
+    grads = {k: torch.zeros_like(g[k]) for k in raster.GRAD_KEYS}
+
+    def step():
+        f = raster.Frame(ctx, g, cams, S)
+        f.bin_sort()
+        out = f.render(("rgb", "depth"))
+        loss, d_rgb, d_dep = f.loss(out["rgb"], out["depth"], target["rgb"], target["depth"], 0.5)
+        f.backward(d_rgb, d_dep, grads=grads)
+        return f
+
+    for _ in range(args.warmup):
+        step().close()
+    torch.cuda.synchronize()
+    f = step()
+    stats = f.stats()
+    f.close()
+    raster.timing_reset(ctx)
+    raster.timing_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step().close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    raster.timing_enable(ctx, False)
+    kern = raster.timing_read(ctx)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = P / (ms_step * 1e-3) / 1e6
+    log(f"mapping step {ms_step:.3f} ms -> {value:.1f} Mpix/s; stats {stats}")
+    log("kernel ms per step: " + ", ".join(f"{k}={v[0] / args.steps:.3f}" for k, v in kern.items() if v[1]))
+
+    # roofline of the dominant compositing kernel
+    per_step = {k: v[0] / max(v[1], 1) for k, v in kern.items()}
+    dom = max(("render", "render_backward"), key=lambda k: per_step[k])
+    avg_ms = per_step[dom]
+    ops = OPS_PER_PAIR[dom] * stats["contrib_pairs"]
+    achieved = ops / (avg_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+            "peak": round(ALU_PEAK_OPS / 1e12, 2), "unit": "TOP/s", "frac": round(achieved * 1e12 / ALU_PEAK_OPS, 4),
+            "traffic": None, "avg_ms": round(avg_ms, 4), "units": stats["contrib_pairs"],
+            "ops_per_unit": OPS_PER_PAIR[dom]}
+
+    # ------------------------------------------------------- view scoring
+    views = {}
+    if not args.no_scoring:
+        log("setup: 64-view 320x240 scoring workload, 500k Gaussians")
+        g3_np, cams3 = scenes.config3()
+        g3 = raster.to_device(g3_np)
+        for persistent, name in ((True, "batched"), (False, "plain")):
+            raster.score_views(ctx, g3, cams3, S, persistent=persistent)
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                raster.score_views(ctx, g3, cams3, S, persistent=persistent)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            views[f"64x320x240_{name}"] = round(len(cams3) / dt, 1)
+            log(f"64 views {name}: {dt * 1e3:.2f} ms")
+        del g3
+        log("setup: 256-view uneven scoring workload, 2M Gaussians")
+        g5_np, cams5 = scenes.config5()
+        g5 = raster.to_device(g5_np)
+        gr = raster.ScoreGraph(ctx, g5, 256, 640, 480, S, probe=cams5)
+        gr.launch(cams5)
+        torch.cuda.synchronize()
+        assert gr.status(), "graph capacity overflow"
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gr.launch(cams5)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        assert gr.status()
+        views["256_uneven_graph"] = round(len(cams5) / dt, 1)
+        log(f"256 views graph: {dt * 1e3:.2f} ms")
+        gr.close()
+        raster.score_views(ctx, g5, cams5, S, persistent=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        raster.score_views(ctx, g5, cams5, S, persistent=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        views["256_uneven_batched_eager"] = round(len(cams5) / dt, 1)
+        t0 = time.perf_counter()
+        raster.score_views(ctx, g5, cams5, S, persistent=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        views["256_uneven_plain"] = round(len(cams5) / dt, 1)
+        log(f"256 views: {views}")
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        oracle.set_threads(threads)
+        log(f"oracle baseline on {threads} threads")
+        rt = oracle.render(tgt_np, cams[0], S)
+        trgb = rt["rgb"].astype(np.float32)
+        tdep = rt["depth"].astype(np.float32)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            r = oracle.render(g_np, cams[0], S)
+            _, gr_, gd_ = oracle.loss(r["rgb"], r["depth"], trgb, tdep, 0.5)
+            oracle.adjoint(g_np, cams[0], S, g_rgb=gr_, g_depth=gd_)
+            n += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(n * P / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"{n} full 640x480 mapping steps (render + loss + adjoint) of the 200k-Gaussian "
+                         f"workload, FP64, {dt:.1f} s"}
+        log(f"oracle: {cpu}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mapping step: 200k Gaussians, one 640x480 RGB-D frame (fx=fy=525), "
+                               "forward + L1 RGB + 0.5 L1 depth + backward",
+                   "tile": f"{tw}x{th}", "gaussians": 200000, "pixels": P},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "views_per_s": views,
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items() if v[1]},
+        "frame_stats": stats,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

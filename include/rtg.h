@@ -1,0 +1,241 @@
+/*
+ * rtg.h - C ABI of the MI355X (gfx950) Gaussian-splatting rasterizer used by
+ * RT-GuIDE (arXiv 2409.18122) to build its map and to score candidate views.
+ *
+ * The calls follow the paper's statement of the problem:
+ *   - h(x, G) "synthesises a measurement given a pose and a map" (Sec. III,
+ *     eq. (1)): rtg_project + rtg_bin_sort + rtg_render;
+ *   - the mapping problem argmin_G sum_s L(y_s, h(x_s, G)) (Sec. III eq. (2))
+ *     with the L1 part of the loss of eq. (4): rtg_loss + rtg_render_backward;
+ *   - choosing the next view by the information proxy of Sec. IV-A eq. (7):
+ *     rtg_score_views (one call for many candidate poses).
+ * A pose is (R_k, T_k), the camera rotation and position in the world frame
+ * (Sec. III, Gaussian Splatting paragraph).
+ *
+ * Conventions for every entry point:
+ *   - Pointers to Gaussian parameters, images, gradients and scores are
+ *     DEVICE pointers owned by the caller; the library never frees them.
+ *     Camera and settings structs are HOST pointers, read during the call.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *     stream) and is asynchronous unless a host output is requested; calls
+ *     that size internal buffers synchronise `stream` once or twice (noted).
+ *   - Errors are returned as rtg_status; rtg_last_error() gives a message
+ *     (thread-local). Arguments are validated on the host before any launch.
+ *     Non-finite Gaussian geometry and zero quaternions are not errors: such
+ *     Gaussians are culled.
+ *   - A context is bound to one device and is not thread-safe; use one
+ *     context per host thread / stream.
+ */
+#ifndef RTG_H
+#define RTG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rtg_status;
+#define RTG_OK 0
+#define RTG_ERR_INVALID (-1)     /* bad argument (null pointer, size, tile, NaN camera) */
+#define RTG_ERR_HIP (-2)         /* a HIP runtime call failed (message has the code) */
+#define RTG_ERR_CAPACITY (-3)    /* a fixed-capacity buffer overflowed (graph replay) */
+#define RTG_ERR_OOM (-4)         /* device allocation failed */
+#define RTG_ERR_UNSUPPORTED (-5) /* request outside what this build supports */
+
+/* Pinhole camera with pose (R_k, T_k) of Sec. III.  R is camera-to-world,
+ * row-major (column k = camera axis k in world coordinates), T the camera
+ * centre in the world.  Camera axes: x right, y down, z forward.  Pixel
+ * centres are at integer coordinates: the centre of pixel (u, v) is (u, v). */
+typedef struct rtg_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float T[3];
+} rtg_camera;
+
+/* Rasterizer settings (rtg_default_settings fills the defaults shown).
+ *   tile_w x tile_h: screen tile, one of 8x8, 16x16 (default), 32x8; 0x0
+ *     asks for the tile chosen by rtg_autotune (16x16 if never tuned);
+ *   batch: Gaussians staged per LDS batch; 0 = one per thread of the tile;
+ *   T_min = 1e-4: compositing stops before the Gaussian that would take the
+ *     transmittance below T_min;
+ *   alpha_min = 1/255: a Gaussian whose alpha at a pixel is below it is
+ *     skipped there (and this fixes its screen-space support);
+ *   alpha_max = 0.99: alpha is clamped to it;
+ *   z_near = 0.2: Gaussians with camera depth <= z_near are culled;
+ *   eps2d = 0: added to the diagonal of the 2D covariance;
+ *   max_instances: capacity of (tile, Gaussian) pairs for captured graphs
+ *     (0 = sized by a first eager pass). */
+typedef struct rtg_settings {
+    int32_t tile_w, tile_h;
+    int32_t batch;
+    float T_min, alpha_min, alpha_max, z_near, eps2d;
+    int64_t max_instances;
+} rtg_settings;
+
+/* The Gaussian map (Sec. III: colour, position, size, opacity; the
+ * anisotropic form of the cited 3DGS work), planar structure of arrays of n
+ * float32 entries per component:
+ *   means 3 x n, log_scales 3 x n, quats 4 x n (w, x, y, z; any norm),
+ *   opacity n (activated, in (0, 1]), colors 3 x n, uncert n (per-Gaussian
+ *   uncertainty u_i of Sec. IV-A; may be NULL when no uncertainty image or
+ *   score is requested). */
+typedef struct rtg_gaussians {
+    int64_t n;
+    const float *means, *log_scales, *quats, *opacity, *colors, *uncert;
+} rtg_gaussians;
+
+/* Gradients, same layouts as rtg_gaussians; ADDED to (+=), so several calls
+ * accumulate.  Any pointer may be NULL to skip that group. */
+typedef struct rtg_grads {
+    float *d_means, *d_log_scales, *d_quats, *d_opacity, *d_colors;
+} rtg_grads;
+
+typedef struct rtg_ctx rtg_ctx;
+typedef struct rtg_frame rtg_frame;
+typedef struct rtg_graph rtg_graph;
+
+/* Message of the last error on this thread ("" if none). */
+const char *rtg_last_error(void);
+
+/* Fills *s with the defaults listed above. */
+rtg_status rtg_default_settings(rtg_settings *s);
+
+/* Number of HIP devices (0 when none; never an error). */
+int32_t rtg_device_count(void);
+
+/* Creates a context on `device`.  RTG_ERR_HIP if there is no such device. */
+rtg_status rtg_create(int32_t device, rtg_ctx **out);
+void rtg_destroy(rtg_ctx *ctx);
+
+/* Projection and culling (Sec. III: mu_2D = K R^T (mu - T) / d with the EWA
+ * 2D covariance).  Projects every Gaussian into each of the n_views cameras
+ * and keeps the (view, Gaussian) pairs whose alpha >= alpha_min support
+ * meets the image.  Creates *out, which holds the projected records and
+ * references g's arrays: they must stay valid and unchanged until the frame
+ * is destroyed.  Images of several views are packed view after view (see
+ * rtg_render).  n_views in [1, 1024].  Synchronises `stream` once (to size
+ * the record buffer). */
+rtg_status rtg_project(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
+                       int32_t n_views, const rtg_settings *settings, rtg_frame **out,
+                       void *stream);
+
+/* Depth ordering and tile binning (Sec. III: "sorted in increasing order of
+ * depth relative to the camera").  Builds, for every screen tile of every
+ * view, the list of Gaussians whose support meets it, in ascending binary32
+ * camera depth, ties by Gaussian index.  *n_instances (host, nullable)
+ * receives the number of (tile, Gaussian) pairs.  Synchronises `stream`
+ * once (to size the pair buffers). */
+rtg_status rtg_bin_sort(rtg_ctx *ctx, rtg_frame *f, int64_t *n_instances, void *stream);
+
+/* Forward compositing (Sec. III: C(p) = sum_i c_i a_i prod_{j<i} (1 - a_j),
+ * depth with c_i -> d_i): per pixel, RGB, depth (not normalised), alpha
+ * = 1 - T_final and uncertainty sum_i u_i a_i T_i.  Outputs are float32,
+ * planar per view and packed view after view: view v starts at pixel offset
+ * P_0 + ... + P_{v-1} (P = width*height); rgb holds 3 planes per view, so
+ * view v's RGB starts at 3*offset_v.  Any output may be NULL.  Saves the
+ * per-pixel state the backward needs inside the frame.  Requires
+ * rtg_bin_sort first. */
+rtg_status rtg_render(rtg_ctx *ctx, rtg_frame *f, float *rgb, float *depth, float *alpha,
+                      float *unc, void *stream);
+
+/* L1 part of the mapping loss of Sec. III eq. (4):
+ *   L = sum_views (1/P_v) sum_p [ sum_ch |C - C*| + w_depth |D - D*| ]
+ * and dL/dC, dL/dD (sign(0) = 0), all in rtg_render's packed layout.
+ * loss: device pointer to one double (written).  d_rgb/d_depth may be NULL. */
+rtg_status rtg_loss(rtg_ctx *ctx, rtg_frame *f, const float *rgb, const float *depth,
+                    const float *target_rgb, const float *target_depth, float w_depth,
+                    float *d_rgb, float *d_depth, double *loss, void *stream);
+
+/* Reverse mode of rtg_render and rtg_project (the map is "refined through
+ * backpropagation", Sec. IV-A): given dL/d(image) in rtg_render's layout
+ * (d_alpha and d_unc nullable = zero), ADDS dL/d(means, log_scales, raw
+ * quaternion, opacity, colors) into *out, summed over the frame's views.
+ * Threshold decisions (alpha_min, T_min, alpha_max clamp, culling) are
+ * treated as constants.  Requires rtg_render on the same frame first. */
+rtg_status rtg_render_backward(rtg_ctx *ctx, rtg_frame *f, const float *d_rgb,
+                               const float *d_depth, const float *d_alpha,
+                               const float *d_unc, const rtg_grads *out, void *stream);
+
+/* Releases a frame (NULL is a no-op). */
+void rtg_frame_destroy(rtg_frame *f);
+
+/* Copies the frame's binning to caller DEVICE buffers (any may be NULL):
+ *   keys[k] = (global_tile << 32) | binary32 depth bits, vals[k] = Gaussian
+ *   index, for the n_instances pairs in sorted order; ranges[2*t], [2*t+1] =
+ *   [start, end) of global tile t (tiles of view v follow those of views
+ *   0..v-1, row-major inside a view).  Sizes come from rtg_frame_info. */
+rtg_status rtg_frame_export(rtg_ctx *ctx, rtg_frame *f, uint64_t *keys, uint32_t *vals,
+                            uint32_t *ranges, void *stream);
+
+/* Host-side sizes of a frame: [0] records (visible view-Gaussian pairs),
+ * [1] instances (tile-Gaussian pairs, -1 before rtg_bin_sort), [2] total
+ * tiles, [3] total pixels, [4] tile_w, [5] tile_h. */
+rtg_status rtg_frame_info(const rtg_frame *f, int64_t info[6]);
+
+/* View scoring by the rendered form of the trace proxy of Sec. IV-A eq. (7):
+ *   score_v = sum over pixels p of view v of sum_i u_i a_i(p) T_i(p),
+ * i.e. the per-Gaussian uncertainty composited like a colour channel and
+ * summed over the image (binary64).  scores: device array of n_views
+ * doubles.  persistent = 1: all views go through one projection, one sort
+ * and one persistent compositing launch; persistent = 0: a plain loop of
+ * per-view launches (for comparison).  Results are identical either way.
+ * Synchronises `stream` to size buffers. */
+rtg_status rtg_score_views(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
+                           int32_t n_views, const rtg_settings *settings, double *scores,
+                           int32_t persistent, void *stream);
+
+/* Captured scoring pipeline: the whole batched path of rtg_score_views in
+ * one hipGraph with device-side sizes, replayed for new poses.
+ * create: fixes the map g (its arrays must stay valid and unchanged), at
+ * most max_views views, each at most max_width x max_height pixels, and the
+ * settings.  Buffers have fixed capacities: the (tile, Gaussian) pair
+ * capacity is settings->max_instances if > 0, else twice the count measured
+ * by an eager pass over the n_probe `probe` cameras, scaled to max_views
+ * (probe must then be non-NULL).  launch: uploads cams (host, n_views <=
+ * max_views, each within the size limits), replays the graph on `stream` and
+ * copies the n_views scores to the device array `scores`.  status: waits for
+ * the last replay and returns RTG_ERR_CAPACITY if a buffer overflowed during
+ * it (its scores are then invalid; create a graph with larger capacity). */
+rtg_status rtg_score_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, int32_t max_views,
+                                  int32_t max_width, int32_t max_height,
+                                  const rtg_settings *settings, const rtg_camera *probe,
+                                  int32_t n_probe, rtg_graph **out, void *stream);
+rtg_status rtg_score_graph_launch(rtg_graph *gr, const rtg_camera *cams, int32_t n_views,
+                                  double *scores, void *stream);
+rtg_status rtg_score_graph_status(rtg_graph *gr);
+void rtg_score_graph_destroy(rtg_graph *gr);
+
+/* Autotuner: times the candidate tiles {8x8, 16x16, 32x8} (and LDS batch
+ * sizes) for `mode` (0 forward, 1 forward+backward, 2 scoring) on the given
+ * map and cameras, and writes the fastest into settings->tile_w/tile_h/
+ * batch.  Images and gradients do not depend on the choice. */
+rtg_status rtg_autotune(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
+                        int32_t n_views, int32_t mode, rtg_settings *settings, void *stream);
+
+/* Work counters of a rendered frame (host output, synchronises `stream`):
+ *   out[0] records (visible view-Gaussian pairs), out[1] instances
+ *   (tile-Gaussian pairs), out[2] contributing pixel-Gaussian pairs (terms of
+ *   the compositing sums of Sec. III over all pixels), out[3] splat list
+ *   entries walked by the backward (sum over pixels of the position after the
+ *   last contributor).  Requires rtg_render. */
+rtg_status rtg_frame_stats(rtg_ctx *ctx, rtg_frame *f, int64_t out[4], void *stream);
+
+/* Kernel timing for measurement: while enabled, the library brackets its
+ * kernels with HIP events on the stream they are launched on and accumulates
+ * the elapsed time per kernel id:
+ *   0 projection (count + emit), 1 depth sort, 2 tile binning and sort,
+ *   3 forward compositing, 4 loss, 5 backward compositing, 6 projection
+ *   backward, 7 view-scoring compositing (persistent or per-view).
+ * rtg_timing_read waits for pending events and returns the accumulated
+ * milliseconds and launch count of one id; rtg_timing_reset clears all. */
+rtg_status rtg_timing_enable(rtg_ctx *ctx, int32_t on);
+rtg_status rtg_timing_read(rtg_ctx *ctx, int32_t id, double *total_ms, int64_t *count);
+rtg_status rtg_timing_reset(rtg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTG_H */

@@ -1,0 +1,162 @@
+// Internal declarations shared by the gfx950 kernels (rtg_kernels.hip) and the
+// host runtime behind the C ABI (rtg_abi.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtg {
+
+// Per-view camera and layout, resident in device memory.  Camera values are
+// the binary32 inputs promoted to binary64.
+struct ViewDev {
+    double R[9];  // camera-to-world rotation, row-major
+    double T[3];  // camera centre in the world
+    double fx, fy, cx, cy;
+    int32_t W, H, tiles_x, tiles_y;
+    uint32_t tile_off;  // first global tile id of this view
+    uint32_t pad;
+    uint64_t pix_off;   // first pixel of this view in the packed images
+};
+
+// Device-side sizes of a batch of views (read by kernels so that captured
+// graphs can be replayed with other cameras).
+struct Header {
+    uint32_t n_views;
+    uint32_t tiles_total;
+    uint64_t pix_total;
+};
+
+struct SetDev {
+    float T_min, alpha_min, alpha_max, z_near, eps2d;
+};
+
+struct GaussDev {
+    int64_t n;
+    const float *means, *log_scales, *quats, *opacity, *colors, *uncert;
+};
+
+// Projected (view, Gaussian) records, structure of arrays.
+//   geo0 = (mean_x hi, mean_y hi, mean_x lo, mean_y lo): the binary64 mean as
+//          a sum of two binary32 values, so per-pixel offsets are exact;
+//   geo1 = (m00, m10, m11, opacity): the lower-triangular whitening M with
+//          M^T M = log2(e)/2 * Sigma_2D^-1, so that with w = M d the splat is
+//          G = exp2(-|w|^2) = exp(-d^T Sigma_2D^-1 d / 2) (no cancellation
+//          between terms for elongated splats);
+//   q64  = binary64 Sigma_2D^-1 (xx, xy, yy, 0), read only to re-take the
+//          alpha_min decision in binary64 when binary32 alpha is near it;
+//   attr = (r, g, b, camera depth); unc = per-Gaussian uncertainty.
+struct Records {
+    float4* geo0;
+    float4* geo1;
+    double4* q64;
+    float4* attr;
+    float* unc;
+    uint32_t* gid;
+    uint32_t* view;
+    uint2* rect;       // tile rectangle: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
+    uint32_t* dkey;    // binary32 bits of the camera depth (sort key)
+    uint32_t* ntiles;  // tiles covered
+};
+
+// Screen-space gradient per record: 16 floats (one 64-byte line):
+// [0,1] d mean_2D, [2..4] d conic (xx, xy counted as one parameter, yy),
+// [5] d opacity, [6..8] d colour, [9] d depth, rest unused.
+constexpr int G2D_STRIDE = 16;
+
+constexpr int MAX_VIEWS = 1024;
+
+// Status bits written by kernels into a device word.
+constexpr uint32_t FLAG_REC_OVERFLOW = 1u;
+constexpr uint32_t FLAG_INST_OVERFLOW = 2u;
+
+// ---------------------------------------------------------------- launchers
+// All take device pointers and enqueue on `s`.  n_dev arguments are device
+// counters; *_cap are the capacities of the buffers those counts index.
+
+void fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+
+// cnt[i] = visible views of Gaussian i; mask[w * n + i] bit b = view 32w+b.
+void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap,
+                   SetDev st, uint32_t* cnt, uint32_t* mask, hipStream_t s);
+// Writes records at rec_off[i] .. for the visible views of Gaussian i.
+void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap,
+                  SetDev st, int tw, int th, const uint32_t* mask, const uint32_t* rec_off,
+                  uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order, uint32_t* flags,
+                  hipStream_t s);
+
+// Exclusive prefix sum of in[0..n) (n = min(*n_dev, cap)) into out; *total =
+// the full sum.  If gather != NULL the input is in[gather[i]].
+struct ScanWs {
+    uint32_t* partial;  // >= scan_blocks(cap) entries
+};
+int scan_blocks(uint64_t cap);
+void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* n_dev,
+              uint32_t cap, uint32_t* total, ScanWs ws, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on bits [0, nbits) of the key.
+// Result lands in (k1, v1) if the number of 8-bit passes is odd, else (k0, v0);
+// returns 1 or 0 accordingly.
+struct SortWs {
+    uint32_t* hist;     // 256 * sort_blocks(cap)
+    uint32_t* partial;  // scan workspace
+};
+int sort_blocks(uint64_t cap);
+int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
+               uint32_t cap, int nbits, SortWs ws, hipStream_t s);
+
+// Instances of the depth-ordered records: tile keys and record ids.
+void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, Records rec,
+                    const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap,
+                    uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s);
+// ranges[t] = [start, end) over the tile-sorted keys; ranges pre-zeroed here.
+void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap,
+                 uint2* ranges, uint32_t tiles_cap, const uint32_t* flags, hipStream_t s);
+
+struct RenderOut {
+    float *rgb, *depth, *alpha, *unc;
+    float* T_final;      // per pixel
+    uint32_t* n_last;    // per pixel: list position after the last contributor
+    uint32_t* n_contrib; // per pixel: number of contributing splats
+};
+
+// out[0] += sum a[i], out[1] += sum b[i] over i < n (64-bit).
+void sum_u32_pair(const uint32_t* a, const uint32_t* b, uint64_t n, unsigned long long* out, hipStream_t s);
+void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
+                    uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec,
+                    Records rec, SetDev st, RenderOut out, hipStream_t s);
+
+void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
+             const float* trgb, const float* tdepth, float w_depth, float* d_rgb, float* d_depth,
+             double* partial, int partial_cap, double* loss, hipStream_t s);
+
+void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views,
+                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec,
+                     Records rec, SetDev st, const float* T_final, const uint32_t* n_last,
+                     const float* d_rgb, const float* d_depth, const float* d_alpha,
+                     const float* d_unc, float* g2d, hipStream_t s);
+
+void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
+                      const uint32_t* cnt, const uint32_t* rec_view, const float* g2d,
+                      float* d_means, float* d_log_scales, float* d_quats, float* d_opacity,
+                      float* d_colors, hipStream_t s);
+
+// Scoring: per-(view, tile) partial sums of the composited uncertainty.
+// persistent: a fixed grid pulls tiles from an atomic queue (counter must be
+// zeroed; done inside).  Otherwise one workgroup per tile of [tile_begin,
+// tile_begin + n_tiles).
+void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent,
+                 const ViewDev* views, int n_views, const Header* hdr,
+                 uint32_t tile_begin, uint32_t n_tiles, const uint2* ranges,
+                 const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
+                 uint32_t* queue, const uint32_t* flags, hipStream_t s);
+int score_persistent_blocks(int tw, int th);
+void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, const double* partial,
+                  double* scores, hipStream_t s);
+
+void export_pairs(const uint32_t* tile_key, const uint32_t* inst_rec, const uint32_t* K_dev,
+                  Records rec, uint64_t* keys, uint32_t* vals, uint32_t cap, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace rtg

@@ -1,0 +1,1404 @@
+// gfx950 (CDNA4) kernels of the Gaussian-splatting rasterizer used by RT-GuIDE
+// (arXiv 2409.18122): projection and culling, prefix sums, an LSD radix sort,
+// tile binning, front-to-back compositing of RGB / depth / alpha /
+// uncertainty, the L1 mapping loss, the reverse-mode kernels, and the
+// persistent view scorer.
+//
+// The file is compiled without floating-point contraction: every fused
+// multiply-add below is an explicit fmaf/fma, so a value computed in two
+// kernels (a splat's alpha in the forward and the backward, the camera depth
+// used as sort key) is bit-identical in both.
+#include "rtg_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtg {
+
+namespace {
+
+constexpr double LOG2E = 1.4426950408889634;
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ------------------------------------------------------------------ fill
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// ------------------------------------------------------------- projection
+// Sec. III (Gaussian Splatting paragraph): t = R^T (mu - T), d = t_z,
+// mu_2D = (fx t_x / d + cx, fy t_y / d + cy); the 2D covariance is the EWA
+// form J R^T Sigma R J^T of the cited 3DGS work, with Sigma = Rq S^2 Rq^T.
+
+struct GPre {
+    double mu[3];
+    double Rq[9];
+    double s[3];
+    double o, rho2;
+    float mu_f[3];
+    float reach;  // rho * max scale: bound on the support radius in 3D
+};
+
+__device__ inline bool pre_gauss(const GaussDev& g, int64_t i, const SetDev& st, GPre& P) {
+    const int64_t n = g.n;
+    float m0 = g.means[i], m1 = g.means[n + i], m2 = g.means[2 * n + i];
+    float l0 = g.log_scales[i], l1 = g.log_scales[n + i], l2 = g.log_scales[2 * n + i];
+    float q0 = g.quats[i], q1 = g.quats[n + i], q2 = g.quats[2 * n + i], q3 = g.quats[3 * n + i];
+    float op = g.opacity[i];
+    bool fin = isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(l0) && isfinite(l1) &&
+               isfinite(l2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) &&
+               isfinite(op);
+    if (!fin) return false;
+    if (op < st.alpha_min) return false;
+    double w = q0, x = q1, y = q2, z = q3;
+    double qn = sqrt(w * w + x * x + y * y + z * z);
+    if (!(qn > 0.0)) return false;
+    double inv = 1.0 / qn;
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    double xx = x * x, yy = y * y, zz = z * z;
+    double xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+    P.Rq[0] = 1.0 - 2.0 * (yy + zz); P.Rq[1] = 2.0 * (xy - wz);       P.Rq[2] = 2.0 * (xz + wy);
+    P.Rq[3] = 2.0 * (xy + wz);       P.Rq[4] = 1.0 - 2.0 * (xx + zz); P.Rq[5] = 2.0 * (yz - wx);
+    P.Rq[6] = 2.0 * (xz - wy);       P.Rq[7] = 2.0 * (yz + wx);       P.Rq[8] = 1.0 - 2.0 * (xx + yy);
+    P.s[0] = exp((double)l0);
+    P.s[1] = exp((double)l1);
+    P.s[2] = exp((double)l2);
+    P.mu[0] = m0; P.mu[1] = m1; P.mu[2] = m2;
+    P.mu_f[0] = m0; P.mu_f[1] = m1; P.mu_f[2] = m2;
+    P.o = op;
+    P.rho2 = 2.0 * log((double)op / (double)st.alpha_min);
+    double smax = fmax(P.s[0], fmax(P.s[1], P.s[2]));
+    P.reach = (float)(sqrt(P.rho2) * smax);
+    return true;
+}
+
+// Conservative binary32 test: false only if the exact binary64 projection is
+// certain to be culled (behind the near plane, or its support box cannot meet
+// the image).  The half extent of the support box is bounded through
+// Sigma_xx <= s_max^2 |J_row0|^2 = s_max^2 fx^2 / t_z^2 (1 + t_x^2 / t_z^2).
+__device__ inline bool may_be_visible(const GPre& P, const ViewDev& V, const SetDev& st) {
+    float dx = P.mu_f[0] - (float)V.T[0];
+    float dy = P.mu_f[1] - (float)V.T[1];
+    float dz = P.mu_f[2] - (float)V.T[2];
+    float mag = fabsf(dx) + fabsf(dy) + fabsf(dz) + 1.0f;
+    float tz = dx * (float)V.R[2] + dy * (float)V.R[5] + dz * (float)V.R[8];
+    float err = 1e-5f * mag;
+    if (tz + err <= st.z_near) return false;
+    if (tz <= 0.5f * st.z_near) return true;  // let the exact test decide
+    float tx = dx * (float)V.R[0] + dy * (float)V.R[3] + dz * (float)V.R[6];
+    float ty = dx * (float)V.R[1] + dy * (float)V.R[4] + dz * (float)V.R[7];
+    float iz = 1.0f / tz;
+    float ux = tx * iz, uy = ty * iz;
+    float fx = (float)V.fx, fy = (float)V.fy;
+    float ax = fx * ux + (float)V.cx;
+    float ay = fy * uy + (float)V.cy;
+    float rx = P.reach * fx * iz, ry = P.reach * fy * iz;
+    float hx = sqrtf(rx * rx * (1.0f + ux * ux) + 2.0f * (float)sqrt(P.rho2) * st.eps2d + st.eps2d * (float)P.rho2);
+    float hy = sqrtf(ry * ry * (1.0f + uy * uy) + 2.0f * (float)sqrt(P.rho2) * st.eps2d + st.eps2d * (float)P.rho2);
+    float slack_x = 1e-3f * (fabsf(ax - (float)V.cx) + hx) + 1.0f + err * fx * iz * 4.0f;
+    float slack_y = 1e-3f * (fabsf(ay - (float)V.cy) + hy) + 1.0f + err * fy * iz * 4.0f;
+    if (ax + hx + slack_x < 0.0f) return false;
+    if (ax - hx - slack_x > (float)(V.W - 1)) return false;
+    if (ay + hy + slack_y < 0.0f) return false;
+    if (ay - hy - slack_y > (float)(V.H - 1)) return false;
+    return true;
+}
+
+struct GProj {
+    double t[3];
+    double A[9];  // R^T Rq
+    double j0, j2, j4, j5;  // nonzero entries of the perspective Jacobian
+    double cxx, cxy, cyy;
+    double mx, my;
+    int u0, u1, v0, v1;
+};
+
+// Exact binary64 projection.  The camera depth is evaluated in the fixed
+// order ((dx R02 + dy R12) + dz R22): its binary32 rounding is the sort key.
+__device__ inline bool project_exact(const GPre& P, const ViewDev& V, const SetDev& st, GProj& q) {
+    double dx = P.mu[0] - V.T[0];
+    double dy = P.mu[1] - V.T[1];
+    double dz = P.mu[2] - V.T[2];
+    const double* R = V.R;
+    double tx = (dx * R[0] + dy * R[3]) + dz * R[6];
+    double ty = (dx * R[1] + dy * R[4]) + dz * R[7];
+    double tz = (dx * R[2] + dy * R[5]) + dz * R[8];
+    if (!(tz > (double)st.z_near)) return false;
+    q.t[0] = tx; q.t[1] = ty; q.t[2] = tz;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+            q.A[a * 3 + b] = fma(R[0 * 3 + a], P.Rq[0 * 3 + b],
+                                 fma(R[1 * 3 + a], P.Rq[1 * 3 + b], R[2 * 3 + a] * P.Rq[2 * 3 + b]));
+    double iz = 1.0 / tz;
+    q.j0 = V.fx * iz;
+    q.j2 = -V.fx * tx * iz * iz;
+    q.j4 = V.fy * iz;
+    q.j5 = -V.fy * ty * iz * iz;
+    // B = J A scaled by s per column; cov = B S^2 B^T
+    double cxx = 0.0, cxy = 0.0, cyy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        double b0 = fma(q.j0, q.A[0 * 3 + k], q.j2 * q.A[2 * 3 + k]) * P.s[k];
+        double b1 = fma(q.j4, q.A[1 * 3 + k], q.j5 * q.A[2 * 3 + k]) * P.s[k];
+        cxx = fma(b0, b0, cxx);
+        cxy = fma(b0, b1, cxy);
+        cyy = fma(b1, b1, cyy);
+    }
+    cxx += (double)st.eps2d;
+    cyy += (double)st.eps2d;
+    double det = cxx * cyy - cxy * cxy;
+    if (!(det > 0.0) || !isfinite(det)) return false;
+    q.cxx = cxx; q.cxy = cxy; q.cyy = cyy;
+    q.mx = fma(V.fx * tx, iz, V.cx);
+    q.my = fma(V.fy * ty, iz, V.cy);
+    double hx = sqrt(P.rho2 * cxx), hy = sqrt(P.rho2 * cyy);
+    double ulo = ceil(q.mx - hx), uhi = floor(q.mx + hx);
+    double vlo = ceil(q.my - hy), vhi = floor(q.my + hy);
+    if (!(ulo <= uhi) || !(vlo <= vhi)) return false;
+    ulo = fmax(ulo, 0.0);
+    vlo = fmax(vlo, 0.0);
+    uhi = fmin(uhi, (double)(V.W - 1));
+    vhi = fmin(vhi, (double)(V.H - 1));
+    if (ulo > uhi || vlo > vhi) return false;
+    q.u0 = (int)ulo; q.u1 = (int)uhi; q.v0 = (int)vlo; q.v1 = (int)vhi;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_project_count(GaussDev g, const ViewDev* __restrict__ views,
+                                                       const Header* __restrict__ hdr, int words,
+                                                       SetDev st, uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ mask) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    GPre P;
+    bool ok = pre_gauss(g, i, st, P);
+    int nv = (int)hdr->n_views;
+    uint32_t c = 0;
+    for (int w = 0; w < words; w++) {
+        uint32_t vis = 0;
+        int base = 32 * w;
+        if (ok && base < nv) {
+            uint32_t cand = 0;
+            int lim = min(32, nv - base);
+            for (int b = 0; b < lim; b++)
+                if (may_be_visible(P, views[base + b], st)) cand |= 1u << b;
+            while (cand) {
+                int b = __ffs(cand) - 1;
+                cand &= cand - 1;
+                GProj q;
+                if (project_exact(P, views[base + b], st, q)) vis |= 1u << b;
+            }
+        }
+        mask[(int64_t)w * g.n + i] = vis;
+        c += __popc(vis);
+    }
+    cnt[i] = c;
+}
+
+__global__ __launch_bounds__(256) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
+                                                      int words, SetDev st, int tw, int th,
+                                                      const uint32_t* __restrict__ mask,
+                                                      const uint32_t* __restrict__ rec_off,
+                                                      uint32_t rec_cap, Records rec,
+                                                      uint32_t* __restrict__ sortkey,
+                                                      uint32_t* __restrict__ order,
+                                                      uint32_t* __restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    uint32_t pos = rec_off[i];
+    GPre P;
+    bool first = true;
+    const int64_t n = g.n;
+    for (int w = 0; w < words; w++) {
+        uint32_t vis = mask[(int64_t)w * n + i];
+        while (vis) {
+            int b = __ffs(vis) - 1;
+            vis &= vis - 1;
+            if (first) {
+                pre_gauss(g, i, st, P);
+                first = false;
+            }
+            int v = 32 * w + b;
+            const ViewDev& V = views[v];
+            GProj q;
+            project_exact(P, V, st, q);
+            if (pos >= rec_cap) {
+                atomicOr(flags, FLAG_REC_OVERFLOW);
+                return;
+            }
+            float mxh = (float)q.mx, myh = (float)q.my;
+            rec.geo0[pos] = make_float4(mxh, myh, (float)(q.mx - (double)mxh),
+                                        (float)(q.my - (double)myh));
+            double det = q.cxx * q.cyy - q.cxy * q.cxy;
+            // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
+            double c00 = sqrt(q.cxx);
+            double c10 = q.cxy / c00;
+            double c11 = sqrt(det / q.cxx);
+            double sl = sqrt(0.5 * LOG2E);
+            rec.geo1[pos] = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
+                                        (float)P.o);
+            rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
+            float depth = (float)q.t[2];
+            if (g.colors)
+                rec.attr[pos] = make_float4(g.colors[i], g.colors[n + i], g.colors[2 * n + i], depth);
+            else
+                rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
+            rec.unc[pos] = g.uncert ? g.uncert[i] : 0.0f;
+            rec.gid[pos] = (uint32_t)i;
+            rec.view[pos] = (uint32_t)v;
+            uint32_t tx0 = (uint32_t)(q.u0 / tw), tx1 = (uint32_t)(q.u1 / tw);
+            uint32_t ty0 = (uint32_t)(q.v0 / th), ty1 = (uint32_t)(q.v1 / th);
+            rec.rect[pos] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+            rec.dkey[pos] = __float_as_uint(depth);
+            sortkey[pos] = __float_as_uint(depth);
+            rec.ntiles[pos] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            order[pos] = pos;
+            pos++;
+        }
+    }
+}
+
+// -------------------------------------------------------------- prefix sum
+
+constexpr int SC_THREADS = 256;
+constexpr int SC_IPT = 8;
+constexpr int SC_TILE = SC_THREADS * SC_IPT;
+constexpr int SC_MAX_BLOCKS = 1024;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(v, o, 64);
+        if (l >= (uint32_t)o) v += y;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* ws, uint32_t& total) {
+    uint32_t inc = wave_incl_scan(x);
+    int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) ws[wv] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < SC_THREADS / 64; k++) {
+        uint32_t t = ws[k];
+        if (k < wv) base += t;
+        total += t;
+    }
+    __syncthreads();
+    return base + inc - x;
+}
+
+__device__ __forceinline__ void chunk_of(uint32_t n, int nblocks, uint32_t& begin, uint32_t& end) {
+    uint32_t per = (uint32_t)(((uint64_t)n + nblocks - 1) / nblocks);
+    per = (per + SC_TILE - 1) / SC_TILE * SC_TILE;
+    uint64_t b = (uint64_t)blockIdx.x * per;
+    begin = (uint32_t)min<uint64_t>(b, n);
+    end = (uint32_t)min<uint64_t>(b + per, n);
+}
+
+__device__ __forceinline__ uint32_t scan_in(const uint32_t* in, const uint32_t* gather, uint32_t i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                            const uint32_t* __restrict__ gather,
+                                                            const uint32_t* __restrict__ n_dev,
+                                                            uint32_t cap, uint32_t* __restrict__ partial) {
+    __shared__ uint32_t ws[SC_THREADS / 64];
+    uint32_t n = min(*n_dev, cap);
+    uint32_t begin, end;
+    chunk_of(n, gridDim.x, begin, end);
+    uint32_t acc = 0;
+    for (uint32_t i = begin + threadIdx.x; i < end; i += SC_THREADS) acc += scan_in(in, gather, i);
+    uint32_t total;
+    block_excl_scan(acc, ws, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SC_MAX_BLOCKS) void k_scan_partials(uint32_t* __restrict__ partial,
+                                                                 int nblocks, uint32_t* __restrict__ total) {
+    __shared__ uint32_t ws[SC_MAX_BLOCKS / 64];
+    uint32_t x = threadIdx.x < (uint32_t)nblocks ? partial[threadIdx.x] : 0;
+    uint32_t inc = wave_incl_scan(x);
+    int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) ws[wv] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < SC_MAX_BLOCKS / 64; k++) {
+        uint32_t t = ws[k];
+        if (k < wv) base += t;
+        tot += t;
+    }
+    if (threadIdx.x < (uint32_t)nblocks) partial[threadIdx.x] = base + inc - x;
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __restrict__ in,
+                                                          const uint32_t* __restrict__ gather,
+                                                          uint32_t* __restrict__ out,
+                                                          const uint32_t* __restrict__ n_dev, uint32_t cap,
+                                                          const uint32_t* __restrict__ partial) {
+    __shared__ uint32_t ws[SC_THREADS / 64];
+    uint32_t n = min(*n_dev, cap);
+    uint32_t begin, end;
+    chunk_of(n, gridDim.x, begin, end);
+    uint32_t run = partial[blockIdx.x];
+    for (uint32_t t0 = begin; t0 < end; t0 += SC_TILE) {
+        // thread owns SC_IPT consecutive items
+        uint32_t v[SC_IPT];
+        uint32_t first = t0 + threadIdx.x * SC_IPT;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < SC_IPT; j++) {
+            uint32_t idx = first + j;
+            v[j] = idx < end ? scan_in(in, gather, idx) : 0;
+            sum += v[j];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_scan(sum, ws, total) + run;
+#pragma unroll
+        for (int j = 0; j < SC_IPT; j++) {
+            uint32_t idx = first + j;
+            if (idx < end) out[idx] = ex;
+            ex += v[j];
+        }
+        run += total;
+    }
+}
+
+// ------------------------------------------------------------- radix sort
+// Stable LSD sort with 8-bit digits.  A fixed grid of blocks splits the
+// input into equal chunks; per pass: per-block digit histograms (upsweep),
+// an exclusive scan of the digit-major histogram table, and a scatter in
+// which every wave ranks its items with 64-lane ballots (peers with the same
+// digit), preserving input order within the block.
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_IPT = 8;
+constexpr int RS_SEG = 64 * RS_IPT;         // items per wave per tile
+constexpr int RS_TILE = RS_THREADS * RS_IPT;  // items per block per tile
+constexpr int RS_MAX_BLOCKS = 1024;
+
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid) {
+    uint64_t m = valid;
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        uint32_t bit = (d >> b) & 1u;
+        uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
+__device__ __forceinline__ void rs_chunk(uint32_t n, uint32_t& begin, uint32_t& end) {
+    uint32_t per = (uint32_t)(((uint64_t)n + gridDim.x - 1) / gridDim.x);
+    per = (per + RS_TILE - 1) / RS_TILE * RS_TILE;
+    uint64_t b = (uint64_t)blockIdx.x * per;
+    begin = (uint32_t)min<uint64_t>(b, n);
+    end = (uint32_t)min<uint64_t>(b + per, n);
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ n_dev, uint32_t cap,
+                                                           int shift, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[RS_WAVES][256];
+    int tid = threadIdx.x, wv = tid >> 6;
+    for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t n = min(*n_dev, cap);
+    uint32_t begin, end;
+    rs_chunk(n, begin, end);
+    for (uint32_t base = begin + wv * 64; base < end; base += RS_THREADS) {
+        uint32_t idx = base + lane_id();
+        bool valid = idx < end;
+        uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
+        uint64_t vm = __ballot(valid);
+        uint64_t m = digit_peers(d, vm);
+        if (valid && lane_id() == (uint32_t)__builtin_ctzll(m)) h[wv][d] += (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; w++) s += h[w][tid];
+    hist[(uint64_t)tid * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint32_t* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout,
+                                                           const uint32_t* __restrict__ n_dev, uint32_t cap,
+                                                           int shift, const uint32_t* __restrict__ hist) {
+    __shared__ uint32_t wh[RS_WAVES][256];
+    __shared__ uint32_t bbase[256];
+    int tid = threadIdx.x, wv = tid >> 6;
+    uint32_t lane = lane_id();
+    uint32_t n = min(*n_dev, cap);
+    uint32_t begin, end;
+    rs_chunk(n, begin, end);
+    bbase[tid] = hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+    for (uint32_t t0 = begin; t0 < end; t0 += RS_TILE) {
+        for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&wh[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t seg = t0 + wv * RS_SEG;
+        uint32_t k[RS_IPT], v[RS_IPT], pos[RS_IPT];
+#pragma unroll
+        for (int j = 0; j < RS_IPT; j++) {
+            uint32_t idx = seg + j * 64 + lane;
+            bool valid = idx < end;
+            k[j] = valid ? kin[idx] : 0u;
+            v[j] = valid ? vin[idx] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < RS_IPT; j++) {
+            uint32_t idx = seg + j * 64 + lane;
+            bool valid = idx < end;
+            uint32_t d = (k[j] >> shift) & 255u;
+            uint64_t vm = __ballot(valid);
+            uint64_t m = digit_peers(d, vm);
+            uint32_t before = valid ? wh[wv][d] : 0u;
+            pos[j] = before + (uint32_t)__popcll(m & lanemask_lt());
+            if (valid && lane == (uint32_t)__builtin_ctzll(m)) wh[wv][d] = before + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        {
+            uint32_t run = bbase[tid];
+#pragma unroll
+            for (int w = 0; w < RS_WAVES; w++) {
+                uint32_t c = wh[w][tid];
+                wh[w][tid] = run;
+                run += c;
+            }
+            bbase[tid] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RS_IPT; j++) {
+            uint32_t idx = seg + j * 64 + lane;
+            if (idx < end) {
+                uint32_t d = (k[j] >> shift) & 255u;
+                uint32_t dst = wh[wv][d] + pos[j];
+                kout[dst] = k[j];
+                vout[dst] = v[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Scan of the digit-major histogram table (256 * nblocks entries, all
+// present): a single block, sequential over chunks.
+__global__ __launch_bounds__(1024) void k_rs_hist_scan(uint32_t* __restrict__ hist, uint32_t count) {
+    __shared__ uint32_t ws[16];
+    uint32_t run = 0;
+    for (uint32_t t0 = 0; t0 < count; t0 += 1024 * 4) {
+        uint32_t v[4];
+        uint32_t first = t0 + threadIdx.x * 4;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            v[j] = first + j < count ? hist[first + j] : 0u;
+            sum += v[j];
+        }
+        uint32_t inc = wave_incl_scan(sum);
+        int wv = threadIdx.x >> 6;
+        if (lane_id() == 63) ws[wv] = inc;
+        __syncthreads();
+        uint32_t base = 0, tot = 0;
+        for (int w = 0; w < 16; w++) {
+            uint32_t t = ws[w];
+            if (w < wv) base += t;
+            tot += t;
+        }
+        __syncthreads();
+        uint32_t ex = run + base + inc - sum;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (first + j < count) hist[first + j] = ex;
+            ex += v[j];
+        }
+        run += tot;
+    }
+}
+
+// ---------------------------------------------------------------- binning
+
+__global__ __launch_bounds__(256) void k_emit_instances(const uint32_t* __restrict__ order,
+                                                        const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
+                                                        Records rec, const ViewDev* __restrict__ views,
+                                                        const uint32_t* __restrict__ inst_off,
+                                                        uint32_t inst_cap, uint32_t* __restrict__ tile_key,
+                                                        uint32_t* __restrict__ inst_rec,
+                                                        uint32_t* __restrict__ flags) {
+    if (*flags & FLAG_REC_OVERFLOW) return;
+    uint32_t R = min(*R_dev, rec_cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
+        uint32_t r = order[i];
+        uint2 rc = rec.rect[r];
+        const ViewDev& V = views[rec.view[r]];
+        uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
+        uint32_t o = inst_off[i];
+        uint32_t need = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        if ((uint64_t)o + need > inst_cap) {
+            atomicOr(flags, FLAG_INST_OVERFLOW);
+            continue;
+        }
+        uint32_t tbase = V.tile_off;
+        uint32_t ntx = (uint32_t)V.tiles_x;
+        for (uint32_t ty = ty0; ty <= ty1; ty++)
+            for (uint32_t tx = tx0; tx <= tx1; tx++) {
+                tile_key[o] = tbase + ty * ntx + tx;
+                inst_rec[o] = r;
+                o++;
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ key,
+                                                     const uint32_t* __restrict__ K_dev, uint32_t cap,
+                                                     uint2* __restrict__ ranges, uint32_t tiles_cap,
+                                                     const uint32_t* __restrict__ flags) {
+    if (*flags) return;  // an overflowed binning leaves the ranges empty
+    uint32_t K = min(*K_dev, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
+        uint32_t t = key[i];
+        if (t >= tiles_cap) continue;
+        if (i == 0 || key[i - 1] != t) ranges[t].x = i;
+        if (i + 1 == K || key[i + 1] != t) ranges[t].y = i + 1;
+    }
+}
+
+__global__ void k_zero_ranges(uint2* ranges, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        ranges[i] = make_uint2(0u, 0u);
+}
+
+// ------------------------------------------------------------ compositing
+// Sec. III: C(p) = sum_i c_i a_i T_i with T_i = prod_{j<i} (1 - a_j); the
+// depth image replaces c_i by d_i; the uncertainty image by u_i (Sec. IV-A).
+
+__device__ __forceinline__ uint32_t view_of_tile(const ViewDev* views, int nv, uint32_t tile) {
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return (uint32_t)lo;
+}
+
+// alpha of one splat at pixel centre (px, py): G = exp2(-|M d|^2) with
+// d = p - mean (the mean as hi + lo binary32 parts, so d is exact to binary32).
+__device__ __forceinline__ float splat_alpha(float4 g0, float4 g1, float px, float py, float amax, float& G,
+                                             float& dx, float& dy, float& w1, float& w2) {
+    dx = (px - g0.x) - g0.z;
+    dy = (py - g0.y) - g0.w;
+    w1 = g1.x * dx;
+    w2 = fmaf(g1.y, dx, g1.z * dy);
+    float pw = fmaf(w1, w1, w2 * w2);
+    G = fast_exp2(-pw);
+    return fminf(amax, g1.w * G);
+}
+
+// Relative band around alpha_min inside which the skip decision is re-taken
+// in binary64 (far wider than the binary32 error of alpha).
+constexpr float REFINE = 2e-3f;
+
+// The alpha_min test: a splat with alpha < alpha_min at a pixel is skipped
+// there.  Near the threshold the decision is taken in binary64 from the
+// binary64 conic, as the definition states it.
+__device__ __forceinline__ bool splat_kept(float a, float4 g0, float4 g1, const double4* __restrict__ q64,
+                                           uint32_t r, float px, float py, const SetDev& st) {
+    const float amin = st.alpha_min;
+    if (fabsf(a - amin) > REFINE * amin) return a >= amin;
+    const double4 q = q64[r];
+    const double dx = ((double)px - (double)g0.x) - (double)g0.z;
+    const double dy = ((double)py - (double)g0.y) - (double)g0.w;
+    const double pw = (q.x * dx * dx + 2.0 * q.y * dx * dy) + q.z * dy * dy;
+    const double ad = fmin((double)st.alpha_max, (double)g1.w * exp(-0.5 * pw));
+    return ad >= (double)amin;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
+                                                        const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ inst_rec,
+                                                        Records rec, SetDev st, RenderOut out) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 s_g0[NT], s_g1[NT], s_at[NT];
+    __shared__ float s_u[NT];
+    __shared__ uint32_t s_r[NT];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t vi = view_of_tile(views, n_views, tile);
+    const ViewDev& V = views[vi];
+    const int W = V.W, H = V.H;
+    const uint32_t lt = tile - V.tile_off;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
+    const bool inside = u < W && v < H;
+    const float px = (float)u, py = (float)v;
+    const uint2 rg = ranges[tile];
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dd = 0.0f, uu = 0.0f;
+    uint32_t last = 0, ncontrib = 0;
+    bool done = !inside;
+    for (uint32_t b = rg.x; b < rg.y; b += NT) {
+        if (__syncthreads_count(done) == NT) break;
+        uint32_t idx = b + threadIdx.x;
+        if (idx < rg.y) {
+            uint32_t r = inst_rec[idx];
+            s_r[threadIdx.x] = r;
+            s_g0[threadIdx.x] = rec.geo0[r];
+            s_g1[threadIdx.x] = rec.geo1[r];
+            s_at[threadIdx.x] = rec.attr[r];
+            s_u[threadIdx.x] = rec.unc[r];
+        }
+        __syncthreads();
+        int cnt = (int)min<uint32_t>(NT, rg.y - b);
+        if (!done) {
+            for (int k = 0; k < cnt; k++) {
+                float G, dx, dy, w1, w2;
+                const float4 g0 = s_g0[k], g1 = s_g1[k];
+                float a = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
+                if (!splat_kept(a, g0, g1, rec.q64, s_r[k], px, py, st)) continue;
+                float Tn = T * (1.0f - a);
+                if (Tn < st.T_min) {
+                    done = true;
+                    break;
+                }
+                float w = a * T;
+                float4 at = s_at[k];
+                c0 = fmaf(at.x, w, c0);
+                c1 = fmaf(at.y, w, c1);
+                c2 = fmaf(at.z, w, c2);
+                dd = fmaf(at.w, w, dd);
+                uu = fmaf(s_u[k], w, uu);
+                T = Tn;
+                last = b - rg.x + (uint32_t)k + 1;
+                ncontrib++;
+            }
+        }
+    }
+    if (!inside) return;
+    const uint64_t P = (uint64_t)W * H;
+    const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
+    if (out.rgb) {
+        float* base = out.rgb + 3 * V.pix_off + (uint64_t)v * W + u;
+        base[0] = c0;
+        base[P] = c1;
+        base[2 * P] = c2;
+    }
+    if (out.depth) out.depth[pix] = dd;
+    if (out.alpha) out.alpha[pix] = 1.0f - T;
+    if (out.unc) out.unc[pix] = uu;
+    if (out.T_final) out.T_final[pix] = T;
+    if (out.n_last) out.n_last[pix] = last;
+    if (out.n_contrib) out.n_contrib[pix] = ncontrib;
+}
+
+// ----------------------------------------------------------------- loss
+// Sec. III eq. (4), L1 terms: (1/P) sum_p (sum_ch |C - C*| + w_d |D - D*|).
+
+__device__ __forceinline__ float sgnf(float e) { return e > 0.0f ? 1.0f : (e < 0.0f ? -1.0f : 0.0f); }
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ float wave_sum_f(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_loss(const ViewDev* __restrict__ views, const float* __restrict__ rgb,
+                                              const float* __restrict__ depth, const float* __restrict__ trgb,
+                                              const float* __restrict__ tdepth, float w_depth,
+                                              float* __restrict__ d_rgb, float* __restrict__ d_depth,
+                                              double* __restrict__ partial) {
+    __shared__ double ws[4];
+    const ViewDev& V = views[blockIdx.y];
+    const uint64_t P = (uint64_t)V.W * V.H;
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    if (p < P) {
+        const float invP = (float)(1.0 / (double)P);
+        const uint64_t c = 3 * V.pix_off + p;
+        const uint64_t q = V.pix_off + p;
+        float acc = 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            float e = rgb[c + ch * P] - trgb[c + ch * P];
+            acc += fabsf(e);
+            if (d_rgb) d_rgb[c + ch * P] = sgnf(e) * invP;
+        }
+        float e = depth[q] - tdepth[q];
+        if (d_depth) d_depth[q] = w_depth * sgnf(e) * invP;
+        l = ((double)acc + (double)w_depth * (double)fabsf(e)) / (double)P;
+    }
+    l = wave_sum_d(l);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(uint64_t)blockIdx.y * gridDim.x + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int n,
+                                                      double* __restrict__ out) {
+    __shared__ double ws[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+    s = wave_sum_d(s);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// ------------------------------------------------------------ backward
+// Reverse mode of the compositing, walking each tile back to front; the
+// transmittance before splat i is recovered as T_{i+1} / (1 - a_i).
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
+                                                        const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ inst_rec,
+                                                        Records rec, SetDev st,
+                                                        const float* __restrict__ T_final,
+                                                        const uint32_t* __restrict__ n_last,
+                                                        const float* __restrict__ d_rgb,
+                                                        const float* __restrict__ d_depth,
+                                                        const float* __restrict__ d_alpha,
+                                                        const float* __restrict__ d_unc,
+                                                        float* __restrict__ g2d) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 s_g0[NT], s_g1[NT], s_at[NT];
+    __shared__ float s_u[NT];
+    __shared__ uint32_t s_r[NT];
+    __shared__ uint32_t s_max;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t vi = view_of_tile(views, n_views, tile);
+    const ViewDev& V = views[vi];
+    const int W = V.W, H = V.H;
+    const uint32_t lt = tile - V.tile_off;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
+    const bool inside = u < W && v < H;
+    const float px = (float)u, py = (float)v;
+    const uint2 rg = ranges[tile];
+    const uint64_t P = (uint64_t)W * H;
+    const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
+    float T = 1.0f;
+    uint32_t last = 0;
+    float gr = 0.0f, gg = 0.0f, gb = 0.0f, gd = 0.0f, ga = 0.0f, gu = 0.0f;
+    if (inside) {
+        T = T_final[pix];
+        last = n_last[pix];
+        if (d_rgb) {
+            const float* cbase = d_rgb + 3 * V.pix_off + (uint64_t)v * W + u;
+            gr = cbase[0];
+            gg = cbase[P];
+            gb = cbase[2 * P];
+        }
+        gd = d_depth ? d_depth[pix] : 0.0f;
+        ga = d_alpha ? d_alpha[pix] : 0.0f;
+        gu = d_unc ? d_unc[pix] : 0.0f;
+    }
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (last) atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t maxlast = s_max;
+    // suffix sums sum_{j>i} v_j w_j for r, g, b, depth, alpha, uncertainty
+    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S3 = 0.0f, S4 = 0.0f, S5 = 0.0f;
+    const float amax = st.alpha_max;
+    for (int64_t bend = maxlast; bend > 0; bend -= NT) {
+        const int64_t bstart = bend - NT > 0 ? bend - NT : 0;
+        __syncthreads();
+        {
+            int64_t e = bstart + threadIdx.x;
+            if (e < bend) {
+                uint32_t r = inst_rec[rg.x + (uint32_t)e];
+                s_r[threadIdx.x] = r;
+                s_g0[threadIdx.x] = rec.geo0[r];
+                s_g1[threadIdx.x] = rec.geo1[r];
+                s_at[threadIdx.x] = rec.attr[r];
+                s_u[threadIdx.x] = rec.unc[r];
+            }
+        }
+        __syncthreads();
+        for (int k = (int)(bend - bstart) - 1; k >= 0; k--) {
+            const uint32_t pos = (uint32_t)(bstart + k);
+            const float4 g0 = s_g0[k], g1 = s_g1[k];
+            float G, dx, dy, w1, w2;
+            float a = splat_alpha(g0, g1, px, py, amax, G, dx, dy, w1, w2);
+            bool act = inside && pos < last && splat_kept(a, g0, g1, rec.q64, s_r[k], px, py, st);
+            float v_mx = 0.0f, v_my = 0.0f, v_qa = 0.0f, v_qb = 0.0f, v_qc = 0.0f, v_o = 0.0f;
+            float v_c0 = 0.0f, v_c1 = 0.0f, v_c2 = 0.0f, v_d = 0.0f;
+            if (act) {
+                const float4 at = s_at[k];
+                const float ui = s_u[k];
+                const float oma = 1.0f - a;
+                const float inv = 1.0f / oma;
+                const float Ti = T * inv;
+                const float w = a * Ti;
+                float da = gr * (at.x * Ti - S0 * inv);
+                da = fmaf(gg, at.y * Ti - S1 * inv, da);
+                da = fmaf(gb, at.z * Ti - S2 * inv, da);
+                da = fmaf(gd, at.w * Ti - S3 * inv, da);
+                da = fmaf(ga, Ti - S4 * inv, da);
+                da = fmaf(gu, ui * Ti - S5 * inv, da);
+                v_c0 = gr * w;
+                v_c1 = gg * w;
+                v_c2 = gb * w;
+                v_d = gd * w;
+                S0 = fmaf(at.x, w, S0);
+                S1 = fmaf(at.y, w, S1);
+                S2 = fmaf(at.z, w, S2);
+                S3 = fmaf(at.w, w, S3);
+                S4 += w;
+                S5 = fmaf(ui, w, S5);
+                T = Ti;
+                if (g1.w * G <= amax) {
+                    v_o = da * G;
+                    // dL/dpower with power = d^T Q d and G = exp(-power / 2)
+                    const float dpow = -0.5f * G * (da * g1.w);
+                    v_qa = dpow * dx * dx;
+                    v_qb = dpow * 2.0f * dx * dy;
+                    v_qc = dpow * dy * dy;
+                    // d = p - mean: dL/dmean = -dpow * 2 Q d, with Q d = (2 / log2e) M^T w
+                    const float kq = (float)(4.0 / LOG2E);
+                    v_mx = -dpow * kq * fmaf(g1.x, w1, g1.y * w2);
+                    v_my = -dpow * kq * (g1.z * w2);
+                }
+            }
+            if (__ballot(act)) {
+                v_mx = wave_sum_f(v_mx);
+                v_my = wave_sum_f(v_my);
+                v_qa = wave_sum_f(v_qa);
+                v_qb = wave_sum_f(v_qb);
+                v_qc = wave_sum_f(v_qc);
+                v_o = wave_sum_f(v_o);
+                v_c0 = wave_sum_f(v_c0);
+                v_c1 = wave_sum_f(v_c1);
+                v_c2 = wave_sum_f(v_c2);
+                v_d = wave_sum_f(v_d);
+                if (lane_id() == 0) {
+                    float* dst = g2d + (uint64_t)s_r[k] * G2D_STRIDE;
+                    unsafeAtomicAdd(dst + 0, v_mx);
+                    unsafeAtomicAdd(dst + 1, v_my);
+                    unsafeAtomicAdd(dst + 2, v_qa);
+                    unsafeAtomicAdd(dst + 3, v_qb);
+                    unsafeAtomicAdd(dst + 4, v_qc);
+                    unsafeAtomicAdd(dst + 5, v_o);
+                    unsafeAtomicAdd(dst + 6, v_c0);
+                    unsafeAtomicAdd(dst + 7, v_c1);
+                    unsafeAtomicAdd(dst + 8, v_c2);
+                    unsafeAtomicAdd(dst + 9, v_d);
+                }
+            }
+        }
+    }
+}
+
+// Chain rule from the screen-space gradients of a Gaussian's records to its
+// parameters, in binary64, summed over the views that see it.
+__global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* __restrict__ views, SetDev st,
+                                                     const uint32_t* __restrict__ rec_off,
+                                                     const uint32_t* __restrict__ cnt,
+                                                     const uint32_t* __restrict__ rec_view,
+                                                     const float* __restrict__ g2d,
+                                                     float* __restrict__ d_means, float* __restrict__ d_ls,
+                                                     float* __restrict__ d_quats, float* __restrict__ d_op,
+                                                     float* __restrict__ d_col) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    uint32_t c = cnt[i];
+    if (c == 0) return;
+    GPre P;
+    if (!pre_gauss(g, i, st, P)) return;
+    const int64_t n = g.n;
+    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double go = 0.0, gc[3] = {0, 0, 0};
+    uint32_t r0 = rec_off[i];
+    for (uint32_t r = r0; r < r0 + c; r++) {
+        const ViewDev& V = views[rec_view[r]];
+        GProj q;
+        project_exact(P, V, st, q);
+        const float* G2 = g2d + (uint64_t)r * G2D_STRIDE;
+        double gmx = G2[0], gmy = G2[1], gqa = G2[2], gqb = G2[3], gqc = G2[4];
+        go += G2[5];
+        gc[0] += G2[6];
+        gc[1] += G2[7];
+        gc[2] += G2[8];
+        double gdepth = G2[9];
+        // conic gradient (xy as one parameter) -> symmetric matrix gradient
+        double det = q.cxx * q.cyy - q.cxy * q.cxy;
+        double Qxx = q.cyy / det, Qxy = -q.cxy / det, Qyy = q.cxx / det;
+        double Gq00 = gqa, Gq01 = 0.5 * gqb, Gq11 = gqc;
+        // G_cov = -Q G_Q Q
+        double m00 = Gq00 * Qxx + Gq01 * Qxy, m01 = Gq00 * Qxy + Gq01 * Qyy;
+        double m10 = Gq01 * Qxx + Gq11 * Qxy, m11 = Gq01 * Qxy + Gq11 * Qyy;
+        double C00 = -(Qxx * m00 + Qxy * m10);
+        double C01 = -(Qxx * m01 + Qxy * m11);
+        double C11 = -(Qxy * m01 + Qyy * m11);
+        // cov = Bs Bs^T with Bs = J A diag(s)
+        double B0[3], B1[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            B0[k] = fma(q.j0, q.A[0 * 3 + k], q.j2 * q.A[2 * 3 + k]);
+            B1[k] = fma(q.j4, q.A[1 * 3 + k], q.j5 * q.A[2 * 3 + k]);
+        }
+        double GB0[3], GB1[3];  // dL/dB (B = J A)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            double gbs0 = 2.0 * (C00 * B0[k] + C01 * B1[k]) * P.s[k];  // dL/dBs row 0
+            double gbs1 = 2.0 * (C01 * B0[k] + C11 * B1[k]) * P.s[k];
+            gs[k] += gbs0 * B0[k] + gbs1 * B1[k];
+            GB0[k] = gbs0 * P.s[k];
+            GB1[k] = gbs1 * P.s[k];
+        }
+        // B = J A:  G_J = G_B A^T, G_A = J^T G_B
+        double GJ00 = 0, GJ02 = 0, GJ11 = 0, GJ12 = 0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            GJ00 += GB0[k] * q.A[0 * 3 + k];
+            GJ02 += GB0[k] * q.A[2 * 3 + k];
+            GJ11 += GB1[k] * q.A[1 * 3 + k];
+            GJ12 += GB1[k] * q.A[2 * 3 + k];
+        }
+        double GA[9];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            GA[0 * 3 + k] = q.j0 * GB0[k];
+            GA[1 * 3 + k] = q.j4 * GB1[k];
+            GA[2 * 3 + k] = q.j2 * GB0[k] + q.j5 * GB1[k];
+        }
+        // A = R^T Rq:  G_Rq = R G_A
+        const double* R = V.R;
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+                gR[a * 3 + b] += R[a * 3 + 0] * GA[0 * 3 + b] + R[a * 3 + 1] * GA[1 * 3 + b] +
+                                 R[a * 3 + 2] * GA[2 * 3 + b];
+        // camera-frame mean
+        double tx = q.t[0], ty = q.t[1], tz = q.t[2];
+        double iz = 1.0 / tz, iz2 = iz * iz;
+        double gtx = 0, gty = 0, gtz = 0;
+        gtz += GJ00 * (-V.fx * iz2);
+        gtx += GJ02 * (-V.fx * iz2);
+        gtz += GJ02 * (2.0 * V.fx * tx * iz2 * iz);
+        gtz += GJ11 * (-V.fy * iz2);
+        gty += GJ12 * (-V.fy * iz2);
+        gtz += GJ12 * (2.0 * V.fy * ty * iz2 * iz);
+        gtx += gmx * V.fx * iz;
+        gtz -= gmx * V.fx * tx * iz2;
+        gty += gmy * V.fy * iz;
+        gtz -= gmy * V.fy * ty * iz2;
+        gtz += gdepth;
+#pragma unroll
+        for (int a = 0; a < 3; a++) gm[a] += R[a * 3 + 0] * gtx + R[a * 3 + 1] * gty + R[a * 3 + 2] * gtz;
+    }
+    // rotation matrix -> normalised quaternion -> raw quaternion
+    double w = g.quats[i], x = g.quats[n + i], y = g.quats[2 * n + i], z = g.quats[3 * n + i];
+    double qn = sqrt(w * w + x * x + y * y + z * z);
+    double inv = 1.0 / qn;
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+    double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
+                       w * gR[7] - 2.0 * x * gR[8]);
+    double gy = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                       z * gR[7] - 2.0 * y * gR[8]);
+    double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] + y * gR[5] +
+                       x * gR[6] + y * gR[7]);
+    double dot = w * gw + x * gx + y * gy + z * gz;
+    if (d_quats) {
+        d_quats[i] += (float)((gw - w * dot) * inv);
+        d_quats[n + i] += (float)((gx - x * dot) * inv);
+        d_quats[2 * n + i] += (float)((gy - y * dot) * inv);
+        d_quats[3 * n + i] += (float)((gz - z * dot) * inv);
+    }
+    if (d_means) {
+        d_means[i] += (float)gm[0];
+        d_means[n + i] += (float)gm[1];
+        d_means[2 * n + i] += (float)gm[2];
+    }
+    if (d_ls) {
+        d_ls[i] += (float)(gs[0] * P.s[0]);
+        d_ls[n + i] += (float)(gs[1] * P.s[1]);
+        d_ls[2 * n + i] += (float)(gs[2] * P.s[2]);
+    }
+    if (d_op) d_op[i] += (float)go;
+    if (d_col) {
+        d_col[i] += (float)gc[0];
+        d_col[n + i] += (float)gc[1];
+        d_col[2 * n + i] += (float)gc[2];
+    }
+}
+
+// ---------------------------------------------------------------- scoring
+// Rendered form of the trace proxy of Sec. IV-A eq. (7): per view, the sum
+// over pixels of the composited uncertainty sum_i u_i a_i T_i.  Only alpha,
+// transmittance and uncertainty are composited; nothing is written per pixel.
+
+template <int TW, int TH>
+__device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views, int n_views, uint32_t tile,
+                                               const uint2* __restrict__ ranges,
+                                               const uint32_t* __restrict__ inst_rec, const Records& rec,
+                                               const SetDev& st, double* __restrict__ partial,
+                                               float4* s_g0, float4* s_g1, float* s_u, uint32_t* s_r,
+                                               double* ws) {
+    constexpr int NT = TW * TH;
+    const uint32_t vi = view_of_tile(views, n_views, tile);
+    const ViewDev& V = views[vi];
+    const uint32_t lt = tile - V.tile_off;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
+    const bool inside = u < V.W && v < V.H;
+    const float px = (float)u, py = (float)v;
+    const uint2 rg = ranges[tile];
+    float T = 1.0f, uu = 0.0f;
+    bool done = !inside;
+    for (uint32_t b = rg.x; b < rg.y; b += NT) {
+        if (__syncthreads_count(done) == NT) break;
+        uint32_t idx = b + threadIdx.x;
+        if (idx < rg.y) {
+            uint32_t r = inst_rec[idx];
+            s_r[threadIdx.x] = r;
+            s_g0[threadIdx.x] = rec.geo0[r];
+            s_g1[threadIdx.x] = rec.geo1[r];
+            s_u[threadIdx.x] = rec.unc[r];
+        }
+        __syncthreads();
+        int cnt = (int)min<uint32_t>(NT, rg.y - b);
+        if (!done) {
+            for (int k = 0; k < cnt; k++) {
+                float G, dx, dy, w1, w2;
+                const float4 g0 = s_g0[k], g1 = s_g1[k];
+                float a = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
+                if (!splat_kept(a, g0, g1, rec.q64, s_r[k], px, py, st)) continue;
+                float Tn = T * (1.0f - a);
+                if (Tn < st.T_min) {
+                    done = true;
+                    break;
+                }
+                uu = fmaf(s_u[k], a * T, uu);
+                T = Tn;
+            }
+        }
+    }
+    float s = wave_sum_f(uu);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = (double)s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int w = 0; w < NT / 64; w++) acc += ws[w];
+        partial[tile] = acc;
+    }
+    __syncthreads();
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restrict__ views, int n_views,
+                                                         uint32_t tile_begin, const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ inst_rec, Records rec,
+                                                         SetDev st, double* __restrict__ partial) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 s_g0[NT], s_g1[NT];
+    __shared__ float s_u[NT];
+    __shared__ uint32_t s_r[NT];
+    __shared__ double ws[NT / 64];
+    score_one_tile<TW, TH>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial, s_g0,
+                           s_g1, s_u, s_r, ws);
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __restrict__ views,
+                                                              const Header* __restrict__ hdr,
+                                                              const uint2* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ inst_rec, Records rec,
+                                                              SetDev st, double* __restrict__ partial,
+                                                              uint32_t* __restrict__ queue,
+                                                              const uint32_t* __restrict__ flags) {
+    constexpr int NT = TW * TH;
+    if (*flags) return;  // overflowed binning: results are reported invalid
+    __shared__ float4 s_g0[NT], s_g1[NT];
+    __shared__ float s_u[NT];
+    __shared__ uint32_t s_r[NT];
+    __shared__ double ws[NT / 64];
+    __shared__ uint32_t s_item;
+    const uint32_t total = hdr->tiles_total;
+    const int nv = (int)hdr->n_views;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        score_one_tile<TW, TH>(views, nv, item, ranges, inst_rec, rec, st, partial, s_g0, s_g1, s_u, s_r, ws);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_score_reduce(const ViewDev* __restrict__ views,
+                                                      const Header* __restrict__ hdr,
+                                                      const double* __restrict__ partial,
+                                                      double* __restrict__ scores) {
+    __shared__ double ws[4];
+    const uint32_t v = blockIdx.x;
+    if (v >= hdr->n_views) return;
+    const ViewDev& V = views[v];
+    const uint32_t nt = (uint32_t)(V.tiles_x * V.tiles_y);
+    double s = 0.0;
+    for (uint32_t t = threadIdx.x; t < nt; t += 256) s += partial[V.tile_off + t];
+    s = wave_sum_d(s);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) scores[v] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ __launch_bounds__(256) void k_export(const uint32_t* __restrict__ tile_key,
+                                                const uint32_t* __restrict__ inst_rec,
+                                                const uint32_t* __restrict__ K_dev, uint32_t cap, Records rec,
+                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    uint32_t K = min(*K_dev, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
+        uint32_t r = inst_rec[i];
+        if (keys) keys[i] = ((uint64_t)tile_key[i] << 32) | rec.dkey[r];
+        if (vals) vals[i] = rec.gid[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_u32_pair(const uint32_t* __restrict__ a,
+                                                      const uint32_t* __restrict__ b, uint64_t n,
+                                                      unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long ws[2][4];
+    unsigned long long sa = 0, sb = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        sa += a[i];
+        sb += b[i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sa += __shfl_xor(sa, o, 64);
+        sb += __shfl_xor(sb, o, 64);
+    }
+    if (lane_id() == 0) {
+        ws[0][threadIdx.x >> 6] = sa;
+        ws[1][threadIdx.x >> 6] = sb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(out, ws[0][0] + ws[0][1] + ws[0][2] + ws[0][3]);
+        atomicAdd(out + 1, ws[1][0] + ws[1][1] + ws[1][2] + ws[1][3]);
+    }
+}
+
+inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535u * 16u) {
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+// ================================================================ launchers
+
+#define RTG_TILE_DISPATCH(TW_, TH_, CALL)                      \
+    if (tw == 8 && th == 8) {                                  \
+        constexpr int TW_ = 8, TH_ = 8;                        \
+        CALL;                                                  \
+    } else if (tw == 32 && th == 8) {                          \
+        constexpr int TW_ = 32, TH_ = 8;                       \
+        CALL;                                                  \
+    } else {                                                   \
+        constexpr int TW_ = 16, TH_ = 16;                      \
+        CALL;                                                  \
+    }
+
+
+int score_persistent_blocks(int tw, int th) {
+    int per_cu = 0;
+    hipError_t e = hipSuccess;
+    RTG_TILE_DISPATCH(TW, TH,
+                      (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_persistent<TW, TH>,
+                                                                        TW * TH, 0)));
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * device_cu_count();
+}
+
+int device_cu_count() {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cu;
+}
+
+void fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n == 0) return;
+    k_fill_u32<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, v, n);
+}
+
+void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap, SetDev st,
+                   uint32_t* cnt, uint32_t* mask, hipStream_t s) {
+    if (g.n == 0) return;
+    int words = (n_views_cap + 31) / 32;
+    k_project_count<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
+}
+
+void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap, SetDev st,
+                  int tw, int th, const uint32_t* mask, const uint32_t* rec_off, uint32_t rec_cap, Records rec,
+                  uint32_t* sortkey, uint32_t* order, uint32_t* flags, hipStream_t s) {
+    (void)hdr;
+    if (g.n == 0) return;
+    int words = (n_views_cap + 31) / 32;
+    k_project_emit<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, words, st, tw, th, mask, rec_off, rec_cap, rec,
+                                                      sortkey, order, flags);
+}
+
+int scan_blocks(uint64_t cap) {
+    uint64_t b = (cap + SC_TILE - 1) / SC_TILE;
+    if (b < 1) b = 1;
+    if (b > SC_MAX_BLOCKS) b = SC_MAX_BLOCKS;
+    return (int)b;
+}
+
+void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* n_dev, uint32_t cap,
+              uint32_t* total, ScanWs ws, hipStream_t s) {
+    int nb = scan_blocks(cap);
+    k_scan_reduce<<<nb, SC_THREADS, 0, s>>>(in, gather, n_dev, cap, ws.partial);
+    k_scan_partials<<<1, SC_MAX_BLOCKS, 0, s>>>(ws.partial, nb, total);
+    k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, gather, out, n_dev, cap, ws.partial);
+}
+
+int sort_blocks(uint64_t cap) {
+    uint64_t b = (cap + RS_TILE - 1) / RS_TILE;
+    if (b < 1) b = 1;
+    if (b > RS_MAX_BLOCKS) b = RS_MAX_BLOCKS;
+    return (int)b;
+}
+
+int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev, uint32_t cap,
+               int nbits, SortWs ws, hipStream_t s) {
+    int nb = sort_blocks(cap);
+    int passes = (nbits + 7) / 8;
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    for (int p = 0; p < passes; p++) {
+        int shift = 8 * p;
+        k_rs_upsweep<<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, ws.hist);
+        k_rs_hist_scan<<<1, 1024, 0, s>>>(ws.hist, (uint32_t)(256 * nb));
+        k_rs_scatter<<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, ws.hist);
+        uint32_t* t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    return passes & 1;
+}
+
+void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, Records rec,
+                    const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap, uint32_t* tile_key,
+                    uint32_t* inst_rec, uint32_t* flags, hipStream_t s) {
+    k_emit_instances<<<grid_for(rec_cap, 256, 8192), 256, 0, s>>>(order, R_dev, rec_cap, rec, views, inst_off,
+                                                                  inst_cap, tile_key, inst_rec, flags);
+}
+
+void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap, uint2* ranges,
+                 uint32_t tiles_cap, const uint32_t* flags, hipStream_t s) {
+    k_zero_ranges<<<grid_for(tiles_cap, 256, 4096), 256, 0, s>>>(ranges, tiles_cap);
+    k_tile_ranges<<<grid_for(inst_cap, 256, 8192), 256, 0, s>>>(tile_key, K_dev, inst_cap, ranges, tiles_cap,
+                                                                flags);
+}
+
+void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
+                    uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
+                    RenderOut out, hipStream_t s) {
+    (void)batch;
+    if (tiles_total == 0) return;
+    RTG_TILE_DISPATCH(TW, TH, (k_render_fwd<TW, TH><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges,
+                                                                                   inst_rec, rec, st, out)));
+}
+
+void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
+             const float* trgb, const float* tdepth, float w_depth, float* d_rgb, float* d_depth, double* partial,
+             int partial_cap, double* loss, hipStream_t s) {
+    unsigned bx = grid_for((uint64_t)max_pix, 256, 1u << 30);
+    (void)partial_cap;
+    dim3 grid(bx, n_views);
+    k_loss<<<grid, 256, 0, s>>>(views, rgb, depth, trgb, tdepth, w_depth, d_rgb, d_depth, partial);
+    k_sum_partials<<<1, 256, 0, s>>>(partial, (int)(bx * n_views), loss);
+}
+
+void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views,
+                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
+                     const float* T_final, const uint32_t* n_last, const float* d_rgb, const float* d_depth,
+                     const float* d_alpha, const float* d_unc, float* g2d, hipStream_t s) {
+    (void)batch;
+    if (tiles_total == 0) return;
+    RTG_TILE_DISPATCH(TW, TH,
+                      (k_render_bwd<TW, TH><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
+                                                                            T_final, n_last, d_rgb, d_depth,
+                                                                            d_alpha, d_unc, g2d)));
+}
+
+void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
+                      const uint32_t* cnt, const uint32_t* rec_view, const float* g2d, float* d_means,
+                      float* d_log_scales, float* d_quats, float* d_opacity, float* d_colors, hipStream_t s) {
+    if (g.n == 0) return;
+    k_project_bwd<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, st, rec_off, cnt, rec_view, g2d, d_means,
+                                                     d_log_scales, d_quats, d_opacity, d_colors);
+}
+
+void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent, const ViewDev* views,
+                 int n_views, const Header* hdr, uint32_t tile_begin, uint32_t n_tiles,
+                 const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
+                 uint32_t* queue, const uint32_t* flags, hipStream_t s) {
+    (void)batch;
+    if (persistent) {
+        fill_u32(queue, 0u, 1, s);
+        RTG_TILE_DISPATCH(TW, TH,
+                          (k_score_persistent<TW, TH><<<grid_persistent, TW * TH, 0, s>>>(views, hdr, ranges,
+                                                                                          inst_rec, rec, st,
+                                                                                          partial, queue,
+                                                                                          flags)));
+    } else {
+        if (n_tiles == 0) return;
+        RTG_TILE_DISPATCH(TW, TH,
+                          (k_score_plain<TW, TH><<<n_tiles, TW * TH, 0, s>>>(views, n_views, tile_begin, ranges,
+                                                                             inst_rec, rec, st, partial)));
+    }
+}
+
+void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, const double* partial,
+                  double* scores, hipStream_t s) {
+    k_score_reduce<<<n_views_cap, 256, 0, s>>>(views, hdr, partial, scores);
+}
+
+void sum_u32_pair(const uint32_t* a, const uint32_t* b, uint64_t n, unsigned long long* out, hipStream_t s) {
+    if (n == 0) return;
+    k_sum_u32_pair<<<grid_for(n, 256, 2048), 256, 0, s>>>(a, b, n, out);
+}
+
+void export_pairs(const uint32_t* tile_key, const uint32_t* inst_rec, const uint32_t* K_dev, Records rec,
+                  uint64_t* keys, uint32_t* vals, uint32_t cap, hipStream_t s) {
+    k_export<<<grid_for(cap, 256, 8192), 256, 0, s>>>(tile_key, inst_rec, K_dev, cap, rec, keys, vals);
+}
+
+}  // namespace rtg

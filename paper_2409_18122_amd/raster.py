@@ -1,0 +1,332 @@
+"""PyTorch-facing wrappers over the C ABI (device memory and streams only).
+
+Every function here marshals tensors into the library's structs and calls one
+entry point of include/rtg.h; all arithmetic runs in the HIP kernels.
+Tensors must be float32, contiguous and on the context's device.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (Camera, Gaussians, Grads, RtgError, Settings, check, lib, RTG_ERR_CAPACITY)
+
+DEFAULTS = {
+    "tile_w": 16, "tile_h": 16, "batch": 0,
+    "T_min": 1e-4, "alpha_min": 1.0 / 255.0, "alpha_max": 0.99,
+    "z_near": 0.2, "eps2d": 0.0, "max_instances": 0,
+}
+
+GAUSS_KEYS = ("means", "log_scales", "quats", "opacity", "colors", "uncert")
+GRAD_KEYS = ("means", "log_scales", "quats", "opacity", "colors")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or t.dtype not in (torch.float32, torch.float64,
+                                                                   torch.int64, torch.int32):
+        raise ValueError("expected a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_settings(settings=None) -> Settings:
+    s = dict(DEFAULTS)
+    if settings:
+        s.update({k: v for k, v in settings.items() if k in DEFAULTS})
+    return Settings(int(s["tile_w"]), int(s["tile_h"]), int(s["batch"]), float(s["T_min"]),
+                    float(s["alpha_min"]), float(s["alpha_max"]), float(s["z_near"]),
+                    float(s["eps2d"]), int(s["max_instances"]))
+
+
+def make_cameras(cams):
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        R = [float(x) for x in torch.as_tensor(c["R"], dtype=torch.float64).reshape(9)]
+        T = [float(x) for x in torch.as_tensor(c["T"], dtype=torch.float64).reshape(3)]
+        arr[i] = Camera(int(c["width"]), int(c["height"]), float(c["fx"]), float(c["fy"]),
+                        float(c["cx"]), float(c["cy"]), (ctypes.c_float * 9)(*R),
+                        (ctypes.c_float * 3)(*T))
+    return arr
+
+
+def make_gaussians(g) -> Gaussians:
+    n = int(g["opacity"].shape[0])
+    for k in GAUSS_KEYS:
+        t = g.get(k)
+        if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda):
+            raise ValueError(f"gaussian array {k} must be a contiguous float32 CUDA tensor")
+    return Gaussians(n, *[_ptr(g.get(k)) for k in GAUSS_KEYS])
+
+
+def to_device(scene, device="cuda"):
+    """numpy scene (planar float32) -> dict of CUDA tensors."""
+    return {k: torch.as_tensor(v).to(device=device, dtype=torch.float32).contiguous()
+            for k, v in scene.items()}
+
+
+def image_sizes(cams):
+    return [int(c["width"]) * int(c["height"]) for c in cams]
+
+
+class Context:
+    """One library context bound to a device (one per stream)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        check(lib().rtg_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().rtg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def timing_enable(ctx, on=True):
+    check(lib().rtg_timing_enable(ctx.handle, int(bool(on))))
+
+
+def timing_reset(ctx):
+    check(lib().rtg_timing_reset(ctx.handle))
+
+
+def timing_read(ctx):
+    """{kernel name: (total ms, launches)} accumulated since the last reset."""
+    from ._lib import TIMER_IDS
+    out = {}
+    for name, i in TIMER_IDS.items():
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(lib().rtg_timing_read(ctx.handle, i, ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = (float(ms.value), int(n.value))
+    return out
+
+
+class Frame:
+    """Projection of the map into a batch of views, with its binning."""
+
+    def __init__(self, ctx: Context, g, cams, settings=None):
+        self.ctx = ctx
+        self._g = g  # keeps the tensors alive
+        self._gs = make_gaussians(g)
+        self.cams = cams
+        self._cams = make_cameras(cams)
+        self.settings = make_settings(settings)
+        h = ctypes.c_void_p()
+        check(lib().rtg_project(ctx.handle, ctypes.byref(self._gs), self._cams, len(cams),
+                                ctypes.byref(self.settings), ctypes.byref(h), _stream()))
+        self.handle = h
+        self.n_instances = None
+
+    def bin_sort(self):
+        k = ctypes.c_int64()
+        check(lib().rtg_bin_sort(self.ctx.handle, self.handle, ctypes.byref(k), _stream()))
+        self.n_instances = int(k.value)
+        return self.n_instances
+
+    def stats(self):
+        a = (ctypes.c_int64 * 4)()
+        check(lib().rtg_frame_stats(self.ctx.handle, self.handle, a, _stream()))
+        return {"records": a[0], "instances": a[1], "contrib_pairs": a[2], "walked_pairs": a[3]}
+
+    def info(self):
+        a = (ctypes.c_int64 * 6)()
+        check(lib().rtg_frame_info(self.handle, a))
+        return {"records": a[0], "instances": a[1], "tiles": a[2], "pixels": a[3],
+                "tile_w": a[4], "tile_h": a[5]}
+
+    def render(self, want=("rgb", "depth", "alpha", "unc")):
+        P = sum(image_sizes(self.cams))
+        dev = self._g["means"].device
+        out = {}
+        if "rgb" in want:
+            out["rgb"] = torch.empty(3 * P, device=dev, dtype=torch.float32)
+        for k in ("depth", "alpha", "unc"):
+            if k in want:
+                out[k] = torch.empty(P, device=dev, dtype=torch.float32)
+        check(lib().rtg_render(self.ctx.handle, self.handle, _ptr(out.get("rgb")),
+                               _ptr(out.get("depth")), _ptr(out.get("alpha")), _ptr(out.get("unc")),
+                               _stream()))
+        return out
+
+    def loss(self, rgb, depth, target_rgb, target_depth, w_depth=0.5, want_grad=True):
+        dev = rgb.device
+        loss = torch.empty(1, device=dev, dtype=torch.float64)
+        d_rgb = torch.empty_like(rgb) if want_grad else None
+        d_depth = torch.empty_like(depth) if want_grad else None
+        check(lib().rtg_loss(self.ctx.handle, self.handle, _ptr(rgb), _ptr(depth), _ptr(target_rgb),
+                             _ptr(target_depth), float(w_depth), _ptr(d_rgb), _ptr(d_depth),
+                             _ptr(loss), _stream()))
+        return loss, d_rgb, d_depth
+
+    def backward(self, d_rgb, d_depth, d_alpha=None, d_unc=None, grads=None):
+        """Adds dL/dparams into `grads` (dict of tensors shaped like the map)."""
+        if grads is None:
+            grads = {k: torch.zeros_like(self._g[k]) for k in GRAD_KEYS}
+        gr = Grads(*[_ptr(grads.get(k)) for k in GRAD_KEYS])
+        check(lib().rtg_render_backward(self.ctx.handle, self.handle, _ptr(d_rgb), _ptr(d_depth),
+                                        _ptr(d_alpha), _ptr(d_unc), ctypes.byref(gr), _stream()))
+        return grads
+
+    def export(self):
+        """Sorted (tile << 32 | depth bits) keys, Gaussian indices, tile ranges."""
+        inf = self.info()
+        dev = self._g["means"].device
+        K = max(inf["instances"], 0)
+        keys = torch.empty(K, device=dev, dtype=torch.int64)
+        vals = torch.empty(K, device=dev, dtype=torch.int32)
+        ranges = torch.empty(2 * inf["tiles"], device=dev, dtype=torch.int32)
+        check(lib().rtg_frame_export(self.ctx.handle, self.handle, _ptr(keys) if K else None,
+                                     _ptr(vals) if K else None,
+                                     _ptr(ranges) if inf["tiles"] else None, _stream()))
+        return keys, vals, ranges
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rtg_frame_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def render(ctx, g, cams, settings=None, want=("rgb", "depth", "alpha", "unc")):
+    """Forward render of several views; returns (images, frame)."""
+    f = Frame(ctx, g, cams, settings)
+    f.bin_sort()
+    return f.render(want), f
+
+
+class RasterizeFn(torch.autograd.Function):
+    """Differentiable render: (means, log_scales, quats, opacity, colors) ->
+    (rgb, depth, alpha, unc), packed per view; uncertainty has no gradient."""
+
+    @staticmethod
+    def forward(fctx, means, log_scales, quats, opacity, colors, uncert, cams, settings, rctx):
+        g = {"means": means.detach(), "log_scales": log_scales.detach(), "quats": quats.detach(),
+             "opacity": opacity.detach(), "colors": colors.detach(),
+             "uncert": None if uncert is None else uncert.detach()}
+        frame = Frame(rctx, g, cams, settings)
+        frame.bin_sort()
+        out = frame.render(("rgb", "depth", "alpha") + (("unc",) if uncert is not None else ()))
+        fctx.frame = frame
+        fctx.has_unc = uncert is not None
+        unc = out.get("unc", torch.zeros_like(out["alpha"]))
+        return out["rgb"], out["depth"], out["alpha"], unc
+
+    @staticmethod
+    def backward(fctx, d_rgb, d_depth, d_alpha, d_unc):
+        frame = fctx.frame
+        grads = frame.backward(d_rgb.contiguous(), d_depth.contiguous(), d_alpha.contiguous(),
+                               d_unc.contiguous() if fctx.has_unc else None)
+        frame.close()
+        fctx.frame = None
+        return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity"],
+                grads["colors"], None, None, None, None)
+
+
+def rasterize(rctx, g, cams, settings=None):
+    return RasterizeFn.apply(g["means"], g["log_scales"], g["quats"], g["opacity"], g["colors"],
+                             g.get("uncert"), cams, settings, rctx)
+
+
+def score_views(ctx, g, cams, settings=None, persistent=True):
+    """Per-view sum of the composited uncertainty (float64 tensor of len(cams))."""
+    gs = make_gaussians(g)
+    cs = make_cameras(cams)
+    st = make_settings(settings)
+    out = torch.empty(len(cams), device=g["means"].device, dtype=torch.float64)
+    check(lib().rtg_score_views(ctx.handle, ctypes.byref(gs), cs, len(cams), ctypes.byref(st),
+                                _ptr(out), int(bool(persistent)), _stream()))
+    return out
+
+
+class ScoreGraph:
+    """The batched scoring pipeline captured once, replayed for new poses."""
+
+    def __init__(self, ctx, g, max_views, max_width, max_height, settings=None, probe=None):
+        self.ctx = ctx
+        self._g = g
+        self._gs = make_gaussians(g)
+        self.settings = make_settings(settings)
+        pr = make_cameras(probe) if probe else None
+        h = ctypes.c_void_p()
+        check(lib().rtg_score_graph_create(ctx.handle, ctypes.byref(self._gs), int(max_views),
+                                           int(max_width), int(max_height),
+                                           ctypes.byref(self.settings), pr,
+                                           len(probe) if probe else 0, ctypes.byref(h), _stream()))
+        self.handle = h
+
+    def launch(self, cams, out=None):
+        cs = make_cameras(cams)
+        if out is None:
+            out = torch.empty(len(cams), device=self._g["means"].device, dtype=torch.float64)
+        check(lib().rtg_score_graph_launch(self.handle, cs, len(cams), _ptr(out), _stream()))
+        return out
+
+    def status(self):
+        code = lib().rtg_score_graph_status(self.handle)
+        if code == RTG_ERR_CAPACITY:
+            return False
+        check(code)
+        return True
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rtg_score_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ctx, g, cams, mode, settings=None):
+    st = make_settings(settings)
+    gs = make_gaussians(g)
+    cs = make_cameras(cams)
+    check(lib().rtg_autotune(ctx.handle, ctypes.byref(gs), cs, len(cams), int(mode),
+                             ctypes.byref(st), _stream()))
+    out = dict(settings or DEFAULTS)
+    out["tile_w"], out["tile_h"], out["batch"] = st.tile_w, st.tile_h, st.batch
+    return out
+
+
+def unpack_images(out, cams):
+    """Split packed per-view outputs into lists of (C, H, W) / (H, W) tensors."""
+    res = []
+    off = 0
+    for c in cams:
+        W, H = int(c["width"]), int(c["height"])
+        P = W * H
+        d = {}
+        if "rgb" in out:
+            d["rgb"] = out["rgb"][3 * off:3 * off + 3 * P].view(3, H, W)
+        for k in ("depth", "alpha", "unc"):
+            if k in out:
+                d[k] = out[k][off:off + P].view(H, W)
+        res.append(d)
+        off += P
+    return res
+
+
+__all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph",
+           "autotune", "to_device", "unpack_images", "RtgError", "DEFAULTS"]

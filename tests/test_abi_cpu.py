@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/rtg.h, and validates arguments before
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(rtg_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2409_18122_amd import _lib
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2409_18122_amd import _lib
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_default_settings(L):
+    from paper_2409_18122_amd._lib import Settings
+    s = Settings()
+    assert L.rtg_default_settings(ctypes.byref(s)) == 0
+    assert (s.tile_w, s.tile_h, s.batch) == (16, 16, 0)
+    assert s.T_min == pytest.approx(1e-4) and s.alpha_max == pytest.approx(0.99)
+    assert s.alpha_min == pytest.approx(1 / 255) and s.z_near == pytest.approx(0.2)
+    assert L.rtg_default_settings(None) == -1
+
+
+def test_no_device_is_reported(L):
+    h = ctypes.c_void_p()
+    n = L.rtg_device_count()
+    if n == 0:
+        assert L.rtg_create(0, ctypes.byref(h)) == -2
+        assert b"no HIP device" in L.rtg_last_error()
+    assert L.rtg_create(-1, ctypes.byref(h)) == -2
+    assert L.rtg_create(0, None) == -1
+
+
+def test_null_arguments_rejected_on_host(L):
+    from paper_2409_18122_amd._lib import Camera, Gaussians, Settings
+    out = ctypes.c_void_p()
+    assert L.rtg_project(None, None, None, 1, None, ctypes.byref(out), None) == -1
+    assert L.rtg_project(None, None, None, 1, None, None, None) == -1
+    assert L.rtg_bin_sort(None, None, None, None) == -1
+    assert L.rtg_render(None, None, None, None, None, None, None) == -1
+    assert L.rtg_loss(None, None, None, None, None, None, 0.5, None, None, None, None) == -1
+    assert L.rtg_render_backward(None, None, None, None, None, None, None, None) == -1
+    assert L.rtg_score_views(None, None, None, 1, None, None, 1, None) == -1
+    assert L.rtg_score_graph_create(None, None, 1, 1, 1, None, None, 0, ctypes.byref(out), None) == -1
+    assert L.rtg_score_graph_launch(None, None, 1, None, None) == -1
+    assert L.rtg_score_graph_status(None) == -1
+    assert L.rtg_frame_export(None, None, None, None, None, None) == -1
+    info = (ctypes.c_int64 * 6)()
+    assert L.rtg_frame_info(None, info) == -1
+    assert L.rtg_autotune(None, None, None, 1, 0, None, None) == -1
+    assert len(L.rtg_last_error()) > 0
+    # destroy functions accept NULL
+    L.rtg_destroy(None)
+    L.rtg_frame_destroy(None)
+    L.rtg_score_graph_destroy(None)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_2409_18122_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_librtg.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()
