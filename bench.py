@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--no-scoring", action="store_true", help="skip the view-scoring workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=str, default="16x16")
+    ap.add_argument("--sweep-tiles", action="store_true", help="also time the step at every tile shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the rasterizer "
@@ -102,6 +103,32 @@ def main():
     log(f"mapping step {ms_step:.3f} ms -> {value:.1f} Mpix/s; stats {stats}")
     log("kernel ms per step: " + ", ".join(f"{k}={v[0] / args.steps:.3f}" for k, v in kern.items() if v[1]))
 
+    if args.sweep_tiles:
+        for tile in ((8, 8), (16, 16), (32, 8)):
+            S2 = dict(S, tile_w=tile[0], tile_h=tile[1])
+
+            def step2():
+                f = raster.Frame(ctx, g, cams, S2)
+                f.bin_sort()
+                out = f.render(("rgb", "depth"))
+                loss, d_rgb, d_dep = f.loss(out["rgb"], out["depth"], target["rgb"], target["depth"], 0.5)
+                f.backward(d_rgb, d_dep, grads=grads)
+                return f
+            for _ in range(2):
+                step2().close()
+            raster.timing_reset(ctx)
+            raster.timing_enable(ctx, True)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(10):
+                step2().close()
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            raster.timing_enable(ctx, False)
+            kk = raster.timing_read(ctx)
+            log(f"tile {tile}: {(tb - ta) * 100:.3f} ms/step; " +
+                ", ".join(f"{k}={v[0] / 10:.3f}" for k, v in kk.items() if v[1]))
+
     # roofline of the dominant compositing kernel
     per_step = {k: v[0] / max(v[1], 1) for k, v in kern.items()}
     dom = max(("render", "render_backward"), key=lambda k: per_step[k])
@@ -148,6 +175,12 @@ def main():
         views["256_uneven_graph"] = round(len(cams5) / dt, 1)
         log(f"256 views graph: {dt * 1e3:.2f} ms")
         gr.close()
+        f5 = raster.Frame(ctx, g5, cams5, S)
+        f5.bin_sort()
+        f5.render(("alpha",))
+        st5 = f5.stats()
+        f5.close()
+        log(f"256-view frame stats: {st5}")
         raster.score_views(ctx, g5, cams5, S, persistent=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -385,7 +385,7 @@ rtg_status frame_setup(rtg_frame* f, int views_cap, hipStream_t s) {
     RTG_TRY(f->cnt.ensure(ctx, sizeof(uint32_t) * std::max<int64_t>(n, 1)));
     RTG_TRY(f->rec_off.ensure(ctx, sizeof(uint32_t) * std::max<int64_t>(n, 1)));
     RTG_TRY(f->mask.ensure(ctx, sizeof(uint32_t) * std::max<int64_t>(n, 1) * words));
-    RTG_TRY(f->scan_ws.ensure(ctx, sizeof(uint32_t) * 1024));
+    RTG_TRY(f->scan_ws.ensure(ctx, sizeof(uint32_t) * 1088));
     return RTG_OK;
 }
 
@@ -486,7 +486,7 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
     }
     const uint32_t kc = std::max<uint32_t>(f->inst_cap, 1);
     Timer tm(f->ctx, 2, s);
-    emit_instances(f->sorted_order(), f->ctr(C_REC), rc, f->records(), f->views.as<ViewDev>(),
+    emit_instances(f->sorted_order(), f->ctr(C_REC), rc, f->ctr(C_INST), f->records(), f->views.as<ViewDev>(),
                    f->inst_off.as<uint32_t>(), f->inst_cap, f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(),
                    f->ctr(C_FLAGS), s);
     int tbits = bits_for(std::max<uint32_t>(f->tiles_cap, 2));

@@ -99,15 +99,15 @@ void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const u
 // returns 1 or 0 accordingly.
 struct SortWs {
     uint32_t* hist;     // 256 * sort_blocks(cap)
-    uint32_t* partial;  // scan workspace
+    uint32_t* partial;  // scan workspace: >= 1024 + 1 entries
 };
 int sort_blocks(uint64_t cap);
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
                uint32_t cap, int nbits, SortWs ws, hipStream_t s);
 
 // Instances of the depth-ordered records: tile keys and record ids.
-void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, Records rec,
-                    const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap,
+void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, const uint32_t* K_dev,
+                    Records rec, const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap,
                     uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s);
 // ranges[t] = [start, end) over the tile-sorted keys; ranges pre-zeroed here.
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap,

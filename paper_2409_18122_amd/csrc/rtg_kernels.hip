@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace rtg {
 
 namespace {
@@ -351,9 +353,10 @@ __global__ __launch_bounds__(SC_MAX_BLOCKS) void k_scan_partials(uint32_t* __res
     if (threadIdx.x == 0 && total) *total = tot;
 }
 
-__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* __restrict__ in,
+// in and out may be the same array (each item is read and written by one thread).
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
                                                           const uint32_t* __restrict__ gather,
-                                                          uint32_t* __restrict__ out,
+                                                          uint32_t* out,
                                                           const uint32_t* __restrict__ n_dev, uint32_t cap,
                                                           const uint32_t* __restrict__ partial) {
     __shared__ uint32_t ws[SC_THREADS / 64];
@@ -542,34 +545,66 @@ __global__ __launch_bounds__(1024) void k_rs_hist_scan(uint32_t* __restrict__ hi
 
 // ---------------------------------------------------------------- binning
 
-__global__ __launch_bounds__(256) void k_emit_instances(const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
-                                                        Records rec, const ViewDev* __restrict__ views,
-                                                        const uint32_t* __restrict__ inst_off,
-                                                        uint32_t inst_cap, uint32_t* __restrict__ tile_key,
-                                                        uint32_t* __restrict__ inst_rec,
-                                                        uint32_t* __restrict__ flags) {
+// One thread per (tile, splat) pair.  A block covers EM_ITEMS consecutive
+// pairs; the depth-ordered records spanning them are found by one binary
+// search over the pair offsets, their offsets staged in LDS, and each thread
+// locates its record there.  Pairs of one record are its tile rectangle in
+// row-major order, so output is written in depth order with coalesced stores.
+constexpr int EM_THREADS = 256;
+constexpr int EM_ITEMS = EM_THREADS * 4;
+
+__device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint32_t x) {
+    // largest i < n with a[i] <= x (a[0] == 0 <= x)
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
+                                                               const uint32_t* __restrict__ K_dev, Records rec,
+                                                               const ViewDev* __restrict__ views,
+                                                               const uint32_t* __restrict__ inst_off,
+                                                               uint32_t inst_cap, uint32_t* __restrict__ tile_key,
+                                                               uint32_t* __restrict__ inst_rec,
+                                                               uint32_t* __restrict__ flags) {
+    __shared__ uint32_t s_off[EM_ITEMS + 1];
+    __shared__ uint32_t s_lo, s_n;
     if (*flags & FLAG_REC_OVERFLOW) return;
-    uint32_t R = min(*R_dev, rec_cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
-        uint32_t r = order[i];
-        uint2 rc = rec.rect[r];
-        const ViewDev& V = views[rec.view[r]];
-        uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
-        uint32_t o = inst_off[i];
-        uint32_t need = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-        if ((uint64_t)o + need > inst_cap) {
-            atomicOr(flags, FLAG_INST_OVERFLOW);
-            continue;
+    const uint32_t R = min(*R_dev, rec_cap);
+    const uint32_t Kall = *K_dev;
+    if (threadIdx.x == 0 && blockIdx.x == 0 && Kall > inst_cap) atomicOr(flags, FLAG_INST_OVERFLOW);
+    const uint32_t K = min(Kall, inst_cap);
+    if (R == 0) return;
+    for (uint32_t k0 = blockIdx.x * EM_ITEMS; k0 < K; k0 += gridDim.x * EM_ITEMS) {
+        const uint32_t k1 = min(k0 + EM_ITEMS, K);  // exclusive
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t lo = last_le(inst_off, R, k0);
+            const uint32_t hi = last_le(inst_off, R, k1 - 1);
+            s_lo = lo;
+            s_n = hi - lo + 1;
         }
-        uint32_t tbase = V.tile_off;
-        uint32_t ntx = (uint32_t)V.tiles_x;
-        for (uint32_t ty = ty0; ty <= ty1; ty++)
-            for (uint32_t tx = tx0; tx <= tx1; tx++) {
-                tile_key[o] = tbase + ty * ntx + tx;
-                inst_rec[o] = r;
-                o++;
-            }
+        __syncthreads();
+        const uint32_t lo = s_lo, nrec = s_n;
+        for (uint32_t i = threadIdx.x; i < nrec; i += EM_THREADS) s_off[i] = inst_off[lo + i];
+        __syncthreads();
+        for (uint32_t k = k0 + threadIdx.x; k < k1; k += EM_THREADS) {
+            const uint32_t j = last_le(s_off, nrec, k);
+            const uint32_t i = lo + j;
+            const uint32_t r = order[i];
+            const uint2 rc = rec.rect[r];
+            const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
+            const uint32_t nx = tx1 - tx0 + 1;
+            const uint32_t li = k - s_off[j];
+            const ViewDev& V = views[rec.view[r]];
+            tile_key[k] = V.tile_off + (ty0 + li / nx) * (uint32_t)V.tiles_x + tx0 + li % nx;
+            inst_rec[k] = r;
+        }
     }
 }
 
@@ -777,142 +812,168 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 // Reverse mode of the compositing, walking each tile back to front; the
 // transmittance before splat i is recovered as T_{i+1} / (1 - a_i).
 
+// Sum over the 64 lanes of a wave with DPP moves (result valid in lane 63,
+// returned to every lane).  Rows of 16: quad swaps, rotations by 4 and 8,
+// then row broadcasts 15 and 31 accumulate rows into row 3.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float x) {
+    x += dpp_mov<0xb1>(x);        // quad_perm [1, 0, 3, 2]
+    x += dpp_mov<0x4e>(x);        // quad_perm [2, 3, 0, 1]
+    x += dpp_mov<0x124>(x);       // row_ror 4
+    x += dpp_mov<0x128>(x);       // row_ror 8
+    x += dpp_mov<0x142, 0xa>(x);  // row_bcast 15 into rows 1 and 3
+    x += dpp_mov<0x143, 0xc>(x);  // row_bcast 31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// One wave per tile; each lane owns PPT pixels of the tile (lane + 64 j).
+// Per splat, the lane sums its pixels' contributions, the wave reduces them
+// once with DPP, and one lane adds the 10 totals to the record's gradient.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
-                                                        const uint2* __restrict__ ranges,
-                                                        const uint32_t* __restrict__ inst_rec,
-                                                        Records rec, SetDev st,
-                                                        const float* __restrict__ T_final,
-                                                        const uint32_t* __restrict__ n_last,
-                                                        const float* __restrict__ d_rgb,
-                                                        const float* __restrict__ d_depth,
-                                                        const float* __restrict__ d_alpha,
-                                                        const float* __restrict__ d_unc,
-                                                        float* __restrict__ g2d) {
-    constexpr int NT = TW * TH;
-    __shared__ float4 s_g0[NT], s_g1[NT], s_at[NT];
-    __shared__ float s_u[NT];
-    __shared__ uint32_t s_r[NT];
-    __shared__ uint32_t s_max;
+__global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
+                                                   const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ inst_rec, Records rec, SetDev st,
+                                                   const float* __restrict__ T_final,
+                                                   const uint32_t* __restrict__ n_last,
+                                                   const float* __restrict__ d_rgb, const float* __restrict__ d_depth,
+                                                   const float* __restrict__ d_alpha,
+                                                   const float* __restrict__ d_unc, float* __restrict__ g2d) {
+    constexpr int PPT = TW * TH / 64;
+    constexpr int B = 64;
+    __shared__ float4 s_g0[B], s_g1[B], s_at[B];
+    __shared__ float s_u[B];
+    __shared__ uint32_t s_r[B];
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
     const int W = V.W, H = V.H;
     const uint32_t lt = tile - V.tile_off;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-    const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
-    const bool inside = u < W && v < H;
-    const float px = (float)u, py = (float)v;
     const uint2 rg = ranges[tile];
     const uint64_t P = (uint64_t)W * H;
-    const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
-    float T = 1.0f;
-    uint32_t last = 0;
-    float gr = 0.0f, gg = 0.0f, gb = 0.0f, gd = 0.0f, ga = 0.0f, gu = 0.0f;
-    if (inside) {
-        T = T_final[pix];
-        last = n_last[pix];
-        if (d_rgb) {
-            const float* cbase = d_rgb + 3 * V.pix_off + (uint64_t)v * W + u;
-            gr = cbase[0];
-            gg = cbase[P];
-            gb = cbase[2 * P];
+    const int lane = (int)threadIdx.x;
+
+    float px[PPT], py[PPT], T[PPT];
+    uint32_t last[PPT];
+    float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
+    float S0[PPT], S1[PPT], S2[PPT], S3[PPT], S4[PPT], S5[PPT];
+    uint32_t maxlast = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; j++) {
+        const int li = lane + 64 * j;
+        const int u = tx * TW + li % TW, v = ty * TH + li / TW;
+        px[j] = (float)u;
+        py[j] = (float)v;
+        T[j] = 1.0f;
+        last[j] = 0;
+        gr[j] = gg[j] = gb[j] = gd[j] = ga[j] = gu[j] = 0.0f;
+        S0[j] = S1[j] = S2[j] = S3[j] = S4[j] = S5[j] = 0.0f;
+        if (u < W && v < H) {
+            const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
+            T[j] = T_final[pix];
+            last[j] = n_last[pix];
+            if (d_rgb) {
+                const float* cb = d_rgb + 3 * V.pix_off + (uint64_t)v * W + u;
+                gr[j] = cb[0];
+                gg[j] = cb[P];
+                gb[j] = cb[2 * P];
+            }
+            if (d_depth) gd[j] = d_depth[pix];
+            if (d_alpha) ga[j] = d_alpha[pix];
+            if (d_unc) gu[j] = d_unc[pix];
         }
-        gd = d_depth ? d_depth[pix] : 0.0f;
-        ga = d_alpha ? d_alpha[pix] : 0.0f;
-        gu = d_unc ? d_unc[pix] : 0.0f;
+        maxlast = max(maxlast, last[j]);
     }
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
-    if (last) atomicMax(&s_max, last);
-    __syncthreads();
-    const uint32_t maxlast = s_max;
-    // suffix sums sum_{j>i} v_j w_j for r, g, b, depth, alpha, uncertainty
-    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S3 = 0.0f, S4 = 0.0f, S5 = 0.0f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, o, 64));
     const float amax = st.alpha_max;
-    for (int64_t bend = maxlast; bend > 0; bend -= NT) {
-        const int64_t bstart = bend - NT > 0 ? bend - NT : 0;
+    const float kq = (float)(4.0 / LOG2E);
+
+    for (int64_t bend = maxlast; bend > 0; bend -= B) {
+        const int64_t bstart = bend - B > 0 ? bend - B : 0;
         __syncthreads();
         {
-            int64_t e = bstart + threadIdx.x;
+            const int64_t e = bstart + lane;
             if (e < bend) {
-                uint32_t r = inst_rec[rg.x + (uint32_t)e];
-                s_r[threadIdx.x] = r;
-                s_g0[threadIdx.x] = rec.geo0[r];
-                s_g1[threadIdx.x] = rec.geo1[r];
-                s_at[threadIdx.x] = rec.attr[r];
-                s_u[threadIdx.x] = rec.unc[r];
+                const uint32_t r = inst_rec[rg.x + (uint32_t)e];
+                s_r[lane] = r;
+                s_g0[lane] = rec.geo0[r];
+                s_g1[lane] = rec.geo1[r];
+                s_at[lane] = rec.attr[r];
+                s_u[lane] = rec.unc[r];
             }
         }
         __syncthreads();
         for (int k = (int)(bend - bstart) - 1; k >= 0; k--) {
             const uint32_t pos = (uint32_t)(bstart + k);
-            const float4 g0 = s_g0[k], g1 = s_g1[k];
-            float G, dx, dy, w1, w2;
-            float a = splat_alpha(g0, g1, px, py, amax, G, dx, dy, w1, w2);
-            bool act = inside && pos < last && splat_kept(a, g0, g1, rec.q64, s_r[k], px, py, st);
-            float v_mx = 0.0f, v_my = 0.0f, v_qa = 0.0f, v_qb = 0.0f, v_qc = 0.0f, v_o = 0.0f;
-            float v_c0 = 0.0f, v_c1 = 0.0f, v_c2 = 0.0f, v_d = 0.0f;
-            if (act) {
-                const float4 at = s_at[k];
-                const float ui = s_u[k];
-                const float oma = 1.0f - a;
-                const float inv = 1.0f / oma;
-                const float Ti = T * inv;
+            const float4 g0 = s_g0[k], g1 = s_g1[k], at = s_at[k];
+            const float ui = s_u[k];
+            const uint32_t r = s_r[k];
+            float a_mx = 0.0f, a_my = 0.0f, a_qa = 0.0f, a_qb = 0.0f, a_qc = 0.0f, a_o = 0.0f;
+            float a_c0 = 0.0f, a_c1 = 0.0f, a_c2 = 0.0f, a_d = 0.0f;
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < PPT; j++) {
+                if (pos >= last[j]) continue;
+                float G, dx, dy, w1, w2;
+                const float a = splat_alpha(g0, g1, px[j], py[j], amax, G, dx, dy, w1, w2);
+                if (!splat_kept(a, g0, g1, rec.q64, r, px[j], py[j], st)) continue;
+                any = true;
+                const float inv = 1.0f / (1.0f - a);
+                const float Ti = T[j] * inv;
                 const float w = a * Ti;
-                float da = gr * (at.x * Ti - S0 * inv);
-                da = fmaf(gg, at.y * Ti - S1 * inv, da);
-                da = fmaf(gb, at.z * Ti - S2 * inv, da);
-                da = fmaf(gd, at.w * Ti - S3 * inv, da);
-                da = fmaf(ga, Ti - S4 * inv, da);
-                da = fmaf(gu, ui * Ti - S5 * inv, da);
-                v_c0 = gr * w;
-                v_c1 = gg * w;
-                v_c2 = gb * w;
-                v_d = gd * w;
-                S0 = fmaf(at.x, w, S0);
-                S1 = fmaf(at.y, w, S1);
-                S2 = fmaf(at.z, w, S2);
-                S3 = fmaf(at.w, w, S3);
-                S4 += w;
-                S5 = fmaf(ui, w, S5);
-                T = Ti;
+                float da = gr[j] * (at.x * Ti - S0[j] * inv);
+                da = fmaf(gg[j], at.y * Ti - S1[j] * inv, da);
+                da = fmaf(gb[j], at.z * Ti - S2[j] * inv, da);
+                da = fmaf(gd[j], at.w * Ti - S3[j] * inv, da);
+                da = fmaf(ga[j], Ti - S4[j] * inv, da);
+                da = fmaf(gu[j], ui * Ti - S5[j] * inv, da);
+                a_c0 = fmaf(gr[j], w, a_c0);
+                a_c1 = fmaf(gg[j], w, a_c1);
+                a_c2 = fmaf(gb[j], w, a_c2);
+                a_d = fmaf(gd[j], w, a_d);
+                S0[j] = fmaf(at.x, w, S0[j]);
+                S1[j] = fmaf(at.y, w, S1[j]);
+                S2[j] = fmaf(at.z, w, S2[j]);
+                S3[j] = fmaf(at.w, w, S3[j]);
+                S4[j] += w;
+                S5[j] = fmaf(ui, w, S5[j]);
+                T[j] = Ti;
                 if (g1.w * G <= amax) {
-                    v_o = da * G;
+                    a_o = fmaf(da, G, a_o);
                     // dL/dpower with power = d^T Q d and G = exp(-power / 2)
                     const float dpow = -0.5f * G * (da * g1.w);
-                    v_qa = dpow * dx * dx;
-                    v_qb = dpow * 2.0f * dx * dy;
-                    v_qc = dpow * dy * dy;
+                    a_qa = fmaf(dpow * dx, dx, a_qa);
+                    a_qb = fmaf(dpow * 2.0f * dx, dy, a_qb);
+                    a_qc = fmaf(dpow * dy, dy, a_qc);
                     // d = p - mean: dL/dmean = -dpow * 2 Q d, with Q d = (2 / log2e) M^T w
-                    const float kq = (float)(4.0 / LOG2E);
-                    v_mx = -dpow * kq * fmaf(g1.x, w1, g1.y * w2);
-                    v_my = -dpow * kq * (g1.z * w2);
+                    const float m = -dpow * kq;
+                    a_mx = fmaf(m, fmaf(g1.x, w1, g1.y * w2), a_mx);
+                    a_my = fmaf(m, g1.z * w2, a_my);
                 }
             }
-            if (__ballot(act)) {
-                v_mx = wave_sum_f(v_mx);
-                v_my = wave_sum_f(v_my);
-                v_qa = wave_sum_f(v_qa);
-                v_qb = wave_sum_f(v_qb);
-                v_qc = wave_sum_f(v_qc);
-                v_o = wave_sum_f(v_o);
-                v_c0 = wave_sum_f(v_c0);
-                v_c1 = wave_sum_f(v_c1);
-                v_c2 = wave_sum_f(v_c2);
-                v_d = wave_sum_f(v_d);
-                if (lane_id() == 0) {
-                    float* dst = g2d + (uint64_t)s_r[k] * G2D_STRIDE;
-                    unsafeAtomicAdd(dst + 0, v_mx);
-                    unsafeAtomicAdd(dst + 1, v_my);
-                    unsafeAtomicAdd(dst + 2, v_qa);
-                    unsafeAtomicAdd(dst + 3, v_qb);
-                    unsafeAtomicAdd(dst + 4, v_qc);
-                    unsafeAtomicAdd(dst + 5, v_o);
-                    unsafeAtomicAdd(dst + 6, v_c0);
-                    unsafeAtomicAdd(dst + 7, v_c1);
-                    unsafeAtomicAdd(dst + 8, v_c2);
-                    unsafeAtomicAdd(dst + 9, v_d);
+            if (__ballot(any)) {
+                const float t_mx = wave_sum_dpp(a_mx), t_my = wave_sum_dpp(a_my);
+                const float t_qa = wave_sum_dpp(a_qa), t_qb = wave_sum_dpp(a_qb), t_qc = wave_sum_dpp(a_qc);
+                const float t_o = wave_sum_dpp(a_o);
+                const float t_c0 = wave_sum_dpp(a_c0), t_c1 = wave_sum_dpp(a_c1), t_c2 = wave_sum_dpp(a_c2);
+                const float t_d = wave_sum_dpp(a_d);
+                if (lane == 0) {
+                    float* dst = g2d + (uint64_t)r * G2D_STRIDE;
+                    unsafeAtomicAdd(dst + 0, t_mx);
+                    unsafeAtomicAdd(dst + 1, t_my);
+                    unsafeAtomicAdd(dst + 2, t_qa);
+                    unsafeAtomicAdd(dst + 3, t_qb);
+                    unsafeAtomicAdd(dst + 4, t_qc);
+                    unsafeAtomicAdd(dst + 5, t_o);
+                    unsafeAtomicAdd(dst + 6, t_c0);
+                    unsafeAtomicAdd(dst + 7, t_c1);
+                    unsafeAtomicAdd(dst + 8, t_c2);
+                    unsafeAtomicAdd(dst + 9, t_d);
                 }
             }
         }
@@ -1305,7 +1366,18 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
     for (int p = 0; p < passes; p++) {
         int shift = 8 * p;
         k_rs_upsweep<<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, ws.hist);
-        k_rs_hist_scan<<<1, 1024, 0, s>>>(ws.hist, (uint32_t)(256 * nb));
+        if (nb <= 32) {
+            k_rs_hist_scan<<<1, 1024, 0, s>>>(ws.hist, (uint32_t)(256 * nb));
+        } else {
+            // table of 256 * nb counts: the multi-block scan, in place
+            const uint32_t count = (uint32_t)(256 * nb);
+            int sb = scan_blocks(count);
+            k_fill_u32<<<1, 64, 0, s>>>(ws.partial + SC_MAX_BLOCKS, count, 1);
+            k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.partial + SC_MAX_BLOCKS, count, ws.partial);
+            k_scan_partials<<<1, SC_MAX_BLOCKS, 0, s>>>(ws.partial, sb, nullptr);
+            k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, ws.partial + SC_MAX_BLOCKS, count,
+                                                  ws.partial);
+        }
         k_rs_scatter<<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, ws.hist);
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -1313,11 +1385,12 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
     return passes & 1;
 }
 
-void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, Records rec,
-                    const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap, uint32_t* tile_key,
-                    uint32_t* inst_rec, uint32_t* flags, hipStream_t s) {
-    k_emit_instances<<<grid_for(rec_cap, 256, 8192), 256, 0, s>>>(order, R_dev, rec_cap, rec, views, inst_off,
-                                                                  inst_cap, tile_key, inst_rec, flags);
+void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, const uint32_t* K_dev,
+                    Records rec, const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap,
+                    uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s) {
+    unsigned grid = grid_for(std::max<uint32_t>(inst_cap, 1), EM_ITEMS, 16384);
+    k_emit_instances<<<grid, EM_THREADS, 0, s>>>(order, R_dev, rec_cap, K_dev, rec, views, inst_off, inst_cap,
+                                                 tile_key, inst_rec, flags);
 }
 
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap, uint2* ranges,
@@ -1353,7 +1426,7 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
     (void)batch;
     if (tiles_total == 0) return;
     RTG_TILE_DISPATCH(TW, TH,
-                      (k_render_bwd<TW, TH><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
+                      (k_render_bwd<TW, TH><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
                                                                             T_final, n_last, d_rgb, d_depth,
                                                                             d_alpha, d_unc, g2d)));
 }
