@@ -32,6 +32,22 @@ OPS_PER_PAIR = {"render": 20.0, "render_backward": 55.0}
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by
+# the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
+# only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
+TRAFFIC = {
+    "render_backward": (18661.0 * 2.0 * 1024 + 50712.2 * 1024,
+                        "0c2a7de5a29516ad323e8c5e5337a8ee19188a27c583c9d0fe808cf731601bbe"),
+    "render": (15210.6 * 2.0 * 1024 + 8400.0 * 1024,
+               "0c2a7de5a29516ad323e8c5e5337a8ee19188a27c583c9d0fe808cf731601bbe"),
+}
+
+
+def kernel_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2409_18122_amd", "csrc", "rtg_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -47,6 +63,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=str, default="16x16")
     ap.add_argument("--sweep-tiles", action="store_true", help="also time the step at every tile shape")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the rasterizer "
@@ -63,6 +81,15 @@ def main():
     S = dict(scenes.DEFAULT_SETTINGS, tile_w=tw, tile_h=th)
     ctx = raster.Context(0)
     dev = torch.device("cuda:0")
+
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, device=dev, dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB device-to-device copies")
+        del a, b
 
     # ------------------------------------------------------- mapping step
     log("setup: 640x480 mapping workload, 200k Gaussians")
@@ -137,7 +164,8 @@ def main():
     achieved = ops / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
             "peak": round(ALU_PEAK_OPS / 1e12, 2), "unit": "TOP/s", "frac": round(achieved * 1e12 / ALU_PEAK_OPS, 4),
-            "traffic": None, "avg_ms": round(avg_ms, 4), "units": stats["contrib_pairs"],
+            "traffic": (TRAFFIC[dom][0] if dom in TRAFFIC and TRAFFIC[dom][1] == kernel_source_sha() else None),
+            "avg_ms": round(avg_ms, 4), "units": stats["contrib_pairs"],
             "ops_per_unit": OPS_PER_PAIR[dom]}
 
     # ------------------------------------------------------- view scoring
