@@ -202,6 +202,28 @@ rtg_status rtg_score_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, int32_t 
                                   int32_t max_width, int32_t max_height,
                                   const rtg_settings *settings, const rtg_camera *probe,
                                   int32_t n_probe, rtg_graph **out, void *stream);
+/* Captured mapping iteration for fixed keyframes: the gradient of the
+ * mapping problem of Sec. III eq. (2) with the L1 part of eq. (4), as one
+ * hipGraph replayed once per optimiser iteration.  One replay runs
+ * projection, depth sort and tile binning, forward compositing into rgb and
+ * depth (caller device buffers in rtg_render's packed layout), the loss into
+ * *loss (device double), and the backward, ADDING the gradients into *grads
+ * (device arrays shaped like the map; any group may be NULL).  The map, the
+ * targets, the outputs and the gradient arrays are captured by address: they
+ * must stay allocated, and the map may be updated in place between replays.
+ * Buffer capacities are 1.5x the counts of an eager pass at creation (or
+ * settings->max_instances pairs when > 0);
+ * rtg_map_graph_status reports RTG_ERR_CAPACITY if a later replay overflowed
+ * (its outputs are then invalid and nothing was added to the gradients). */
+rtg_status rtg_map_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
+                                int32_t n_views, const rtg_settings *settings,
+                                const float *target_rgb, const float *target_depth, float w_depth,
+                                float *rgb, float *depth, double *loss, const rtg_grads *grads,
+                                rtg_graph **out, void *stream);
+rtg_status rtg_map_graph_launch(rtg_graph *gr, void *stream);
+rtg_status rtg_map_graph_status(rtg_graph *gr);
+void rtg_map_graph_destroy(rtg_graph *gr);
+
 rtg_status rtg_score_graph_launch(rtg_graph *gr, const rtg_camera *cams, int32_t n_views,
                                   double *scores, void *stream);
 rtg_status rtg_score_graph_status(rtg_graph *gr);
@@ -213,6 +235,39 @@ void rtg_score_graph_destroy(rtg_graph *gr);
  * batch.  Images and gradients do not depend on the choice. */
 rtg_status rtg_autotune(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                         int32_t n_views, int32_t mode, rtg_settings *settings, void *stream);
+
+/* Paper-literal view utility of Sec. IV-B eq. (8), which does not render:
+ *   v(x, g) = 1 when Gaussian g is in the field of view of camera x - its
+ *   camera depth is in (settings->z_near, range] (range: the sensor's
+ *   perception range; no occlusion test) and its projected mean lies inside
+ *   the image, 0 <= u <= W-1, 0 <= v <= H-1;
+ *   H = {g : u_g > lo_hi[1]}, L = {g : u_g < lo_hi[0]};
+ *   n_high[v] = sum_{g in H} v(x_v, g), n_low[v] = sum_{g in L} v(x_v, g),
+ *   sum_u[v] = sum_g u_g v(x_v, g) (the "-sum" variant of Sec. V-A, in 2^-40
+ *   fixed point), xi[v] = n_high[v] - lambda_xi n_low[v].
+ * lo_hi: device array of the two thresholds (see rtg_uncertainty_thresholds).
+ * All outputs are device arrays of n_views entries; any may be NULL.  Only the
+ * means and uncert arrays of g are read.  The visibility decision is taken
+ * in binary64 wherever binary32 cannot decide it. */
+rtg_status rtg_view_utility(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
+                            int32_t n_views, const rtg_settings *settings, float range,
+                            const double *lo_hi, double lambda_xi, int64_t *n_high,
+                            int64_t *n_low, double *sum_u, double *xi, void *stream);
+
+/* Thresholds of the high / low uncertainty sets (Sec. IV-C: half a standard
+ * deviation above and below the mean): lo_hi[0] = mean - k_std sd,
+ * lo_hi[1] = mean + k_std sd over u[0..n), binary64, population standard
+ * deviation, fixed reduction order.  lo_hi: device array of 2 doubles. */
+rtg_status rtg_uncertainty_thresholds(rtg_ctx *ctx, const float *uncert, int64_t n, double k_std,
+                                      double *lo_hi, void *stream);
+
+/* Trajectory selection of Sec. IV-B eq. (10): traj_utility[t] = sum of xi
+ * over the states offsets[t] .. offsets[t+1]-1 (device int32 array of
+ * n_traj + 1 offsets), summed in order; *best (device int32) = the first
+ * trajectory of maximal utility.  traj_utility may be NULL. */
+rtg_status rtg_trajectory_select(rtg_ctx *ctx, const double *xi, const int32_t *offsets,
+                                 int32_t n_traj, double *traj_utility, int32_t *best,
+                                 void *stream);
 
 /* Work counters of a rendered frame (host output, synchronises `stream`):
  *   out[0] records (visible view-Gaussian pairs), out[1] instances
@@ -227,7 +282,8 @@ rtg_status rtg_frame_stats(rtg_ctx *ctx, rtg_frame *f, int64_t out[4], void *str
  * the elapsed time per kernel id:
  *   0 projection (count + emit), 1 depth sort, 2 tile binning and sort,
  *   3 forward compositing, 4 loss, 5 backward compositing, 6 projection
- *   backward, 7 view-scoring compositing (persistent or per-view).
+ *   backward, 7 view-scoring compositing (persistent or per-view; a whole
+ *   scoring-graph replay), 8 a whole mapping-graph replay.
  * rtg_timing_read waits for pending events and returns the accumulated
  * milliseconds and launch count of one id; rtg_timing_reset clears all. */
 rtg_status rtg_timing_enable(rtg_ctx *ctx, int32_t on);

@@ -10,7 +10,7 @@ exactly to float64.  See the C file's header for which passage of the paper
 each function follows.
 
 Functions: ``project``, ``render``, ``count``, ``keys``, ``loss``, ``score``,
-``adjoint``.  Parity status: every function here is pinned by the
+``adjoint``, ``thresholds``, ``view_utility``.  Parity status: every function here is pinned by the
 ``-m "not gpu"`` tests (closed forms, invariants, brute force, finite
 differences); see tests/test_oracle_*.py.
 """
@@ -68,6 +68,10 @@ def lib():
         L.rtgo_score.restype = ctypes.c_int
         L.rtgo_adjoint.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 2 + [p] * 10)
         L.rtgo_adjoint.restype = ctypes.c_int
+        L.rtgo_thresholds.argtypes = [i64, p, ctypes.c_double, p, p]
+        L.rtgo_thresholds.restype = None
+        L.rtgo_view_utility.argtypes = ([i64, p, p, p, ctypes.c_int] + [ctypes.c_double] * 5 + [p] * 4)
+        L.rtgo_view_utility.restype = ctypes.c_int
         L.rtgo_set_threads.argtypes = [ctypes.c_int]
         L.rtgo_max_threads.restype = ctypes.c_int
         _lib = L
@@ -154,7 +158,7 @@ def render(scene, cam, settings, mode="tiled", tile=None, roi=None,
     rgb = np.zeros((3, H, W)); dep = np.zeros((H, W)); alp = np.zeros((H, W))
     unc = np.zeros((H, W)); T = np.ones((H, W))
     nc = np.zeros((H, W), np.int32); ne = np.zeros((H, W), np.int32)
-    cap = alt_cap if alt_cap is not None else max(1024, P // 50)
+    cap = alt_cap if alt_cap is not None else max(4096, P // 8)
     apix = np.zeros(cap, np.int64); aval = np.zeros((cap, 4, 6))
     nalt = lib().rtgo_render(g.n, *g.all(), _ptr(ca), _ptr(sa), m, int(tw), int(th), _ptr(roi_a),
                              float(ev_alpha), float(ev_t), _ptr(rgb), _ptr(dep), _ptr(alp),
@@ -235,3 +239,25 @@ def adjoint(scene, cam, settings, g_rgb=None, g_depth=None, g_alpha=None, g_unc=
     if want_2d:
         out["screen"] = g2d
     return out
+
+
+def thresholds(uncert, k=0.5):
+    """(mean - k std, mean + k std) of the uncertainties (Sec. IV-C: k = 1/2)."""
+    u = _d(uncert).reshape(-1)
+    lo = ctypes.c_double(); hi = ctypes.c_double()
+    lib().rtgo_thresholds(u.size, _ptr(u), float(k), ctypes.addressof(lo), ctypes.addressof(hi))
+    return float(lo.value), float(hi.value)
+
+
+def view_utility(scene, cams, settings, lo, hi, range_=5.0, lam=1.0):
+    """Per-camera (n_high, n_low, sum_u, xi) of the view utility of eq. (8)."""
+    g = _G(scene)
+    ca = np.ascontiguousarray(np.concatenate([cam_array(c) for c in cams]))
+    nv = len(cams)
+    nh = np.zeros(nv, np.int64); nl = np.zeros(nv, np.int64)
+    su = np.zeros(nv); xi = np.zeros(nv)
+    z_near = float(np.float32(settings["z_near"]))
+    lib().rtgo_view_utility(g.n, _ptr(g.means), _ptr(g.u), _ptr(ca), nv, z_near,
+                            float(np.float32(range_)), float(lo), float(hi), float(lam),
+                            _ptr(nh), _ptr(nl), _ptr(su), _ptr(xi))
+    return nh, nl, su, xi

@@ -969,3 +969,67 @@ int rtgo_adjoint(int64_t n, const double *means, const double *ls, const double 
     view_free(&V);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Paper-literal view utility (Sec. IV-B eq. (8), thresholds of Sec. IV-C)  */
+/* ------------------------------------------------------------------------ */
+
+/* Thresholds for the high / low uncertainty sets: mean(u) -/+ k std(u)
+ * (population standard deviation), summed in index order. */
+void rtgo_thresholds(int64_t n, const double *u, double k, double *lo, double *hi)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += u[i];
+    double mean = n > 0 ? s / (double)n : 0.0;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; i++) ss += (u[i] - mean) * (u[i] - mean);
+    double sd = n > 0 ? sqrt(ss / (double)n) : 0.0;
+    *lo = mean - k * sd;
+    *hi = mean + k * sd;
+}
+
+/* Binary visibility v(x, g) of Sec. IV-B: the Gaussian's mean is in the
+ * camera's field of view - camera depth in (z_near, range] (the perception
+ * range; no occlusion test) and projected mean inside the image,
+ * 0 <= mu_2D,x <= W - 1 and 0 <= mu_2D,y <= H - 1 (pixel-centre convention). */
+static int fov_visible(const double *mu, const ocam *c, double z_near, double range)
+{
+    if (!isfinite(mu[0]) || !isfinite(mu[1]) || !isfinite(mu[2])) return 0;
+    double dx = mu[0] - c->T[0], dy = mu[1] - c->T[1], dz = mu[2] - c->T[2];
+    const double *R = c->R;
+    double tx = (dx * R[0] + dy * R[3]) + dz * R[6];
+    double ty = (dx * R[1] + dy * R[4]) + dz * R[7];
+    double tz = (dx * R[2] + dy * R[5]) + dz * R[8];
+    if (!(tz > z_near) || !(tz <= range)) return 0;
+    double mx = c->fx * tx / tz + c->cx;
+    double my = c->fy * ty / tz + c->cy;
+    return mx >= 0.0 && mx <= (double)(c->w - 1) && my >= 0.0 && my <= (double)(c->h - 1);
+}
+
+/* For each of nv cameras: n_high = |{g in FOV : u_g > hi}|, n_low = |{g in
+ * FOV : u_g < lo}|, sum_u = sum of u_g over the FOV (the "-sum" variant of
+ * Sec. V-A), xi = n_high - lambda n_low (eq. (8)). */
+int rtgo_view_utility(int64_t n, const double *means, const double *u, const double *cams, int nv,
+                      double z_near, double range, double lo, double hi, double lambda,
+                      int64_t *n_high, int64_t *n_low, double *sum_u, double *xi)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int v = 0; v < nv; v++) {
+        ocam c;
+        read_cam(cams + 18 * v, &c);
+        int64_t nh = 0, nl = 0;
+        double su = 0.0;
+        for (int64_t i = 0; i < n; i++) {
+            double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+            if (!fov_visible(mu, &c, z_near, range)) continue;
+            if (u[i] > hi) nh++;
+            if (u[i] < lo) nl++;
+            su += u[i];
+        }
+        n_high[v] = nh;
+        n_low[v] = nl;
+        sum_u[v] = su;
+        xi[v] = (double)nh - lambda * (double)nl;
+    }
+    return 0;
+}

@@ -68,13 +68,22 @@ SIGNATURES = {
     "rtg_autotune": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, i32,
                            _c.POINTER(Settings), vp]),
     "rtg_frame_stats": (i32, [vp, vp, _c.POINTER(i64), vp]),
+    "rtg_map_graph_create": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, _c.POINTER(Settings),
+                                   vp, vp, f32, vp, vp, vp, _c.POINTER(Grads), _c.POINTER(vp), vp]),
+    "rtg_map_graph_launch": (i32, [vp, vp]),
+    "rtg_map_graph_status": (i32, [vp]),
+    "rtg_map_graph_destroy": (None, [vp]),
+    "rtg_view_utility": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, _c.POINTER(Settings), f32,
+                               vp, _c.c_double, vp, vp, vp, vp, vp]),
+    "rtg_uncertainty_thresholds": (i32, [vp, vp, i64, _c.c_double, vp, vp]),
+    "rtg_trajectory_select": (i32, [vp, vp, vp, i32, vp, vp, vp]),
     "rtg_timing_enable": (i32, [vp, i32]),
     "rtg_timing_read": (i32, [vp, i32, _c.POINTER(_c.c_double), _c.POINTER(i64)]),
     "rtg_timing_reset": (i32, [vp]),
 }
 
 TIMER_IDS = {"project": 0, "depth_sort": 1, "binning": 2, "render": 3, "loss": 4,
-             "render_backward": 5, "project_backward": 6, "score": 7}
+             "render_backward": 5, "project_backward": 6, "score": 7, "map_graph": 8}
 
 _lib = None
 

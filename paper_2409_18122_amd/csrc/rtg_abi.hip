@@ -124,7 +124,7 @@ struct TuneKey {
     }
 };
 
-constexpr int N_TIMERS = 8;
+constexpr int N_TIMERS = 9;
 
 struct PendingTimer {
     int id;
@@ -347,20 +347,20 @@ struct rtg_frame {
     int order_in_alt = 0, inst_in_alt = 0;
 
     Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist;
-    Buf geo0, geo1, q64, attr, unc, gid, view, rect, dkey, ntiles, skey, skey2, order, order2;
+    Buf geo0, geo1, q64, attr, unc, gid, view, rect, pbox, dkey, ntiles, skey, skey2, order, order2;
     Buf inst_off, tkey, tkey2, irec, irec2, ranges;
     Buf T_final, n_last, g2d, loss_part, score_part;
 
     Records records() const {
         return Records{geo0.as<float4>(), geo1.as<float4>(), q64.as<double4>(), attr.as<float4>(), unc.as<float>(),
-                       gid.as<uint32_t>(),  view.as<uint32_t>(), rect.as<uint2>(), dkey.as<uint32_t>(),
+                       gid.as<uint32_t>(),  view.as<uint32_t>(), rect.as<uint2>(), pbox.as<uint2>(), dkey.as<uint32_t>(),
                        ntiles.as<uint32_t>()};
     }
     uint32_t* sorted_order() const { return order_in_alt ? order2.as<uint32_t>() : order.as<uint32_t>(); }
     uint32_t* sorted_tkey() const { return inst_in_alt ? tkey2.as<uint32_t>() : tkey.as<uint32_t>(); }
     uint32_t* sorted_irec() const { return inst_in_alt ? irec2.as<uint32_t>() : irec.as<uint32_t>(); }
     uint32_t* ctr(int k) const { return counters.as<uint32_t>() + k; }
-    Buf n_contrib, stats;
+    Buf n_contrib, stats, d_img;
 };
 
 namespace {
@@ -408,6 +408,7 @@ rtg_status alloc_records(rtg_frame* f, uint32_t rc) {
     RTG_TRY(f->gid.ensure(ctx, 4 * r));
     RTG_TRY(f->view.ensure(ctx, 4 * r));
     RTG_TRY(f->rect.ensure(ctx, 8 * r));
+    RTG_TRY(f->pbox.ensure(ctx, 8 * r));
     RTG_TRY(f->dkey.ensure(ctx, 4 * r));
     RTG_TRY(f->ntiles.ensure(ctx, 4 * r));
     RTG_TRY(f->skey.ensure(ctx, 4 * r));
@@ -624,7 +625,8 @@ rtg_status rtg_render(rtg_ctx* ctx, rtg_frame* f, float* rgb, float* depth, floa
                 f->n_contrib.as<uint32_t>()};
     Timer tm(ctx, 3, s);
     render_forward(f->st.tile_w, f->st.tile_h, f->st.batch, f->views.as<ViewDev>(), f->n_views,
-                   f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st), o, s);
+                   f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st), o,
+                   nullptr, s);
     RTG_TRY(check_launch("render"));
     f->rendered = true;
     return RTG_OK;
@@ -655,20 +657,20 @@ rtg_status rtg_render_backward(rtg_ctx* ctx, rtg_frame* f, const float* d_rgb, c
     if (d_unc && f->g.n > 0 && !f->g.uncert) return set_err(RTG_ERR_INVALID, "d_unc given but the map has no uncertainty");
     hipStream_t s = (hipStream_t)stream;
     size_t R = std::max<uint32_t>(f->R, 1);
-    RTG_TRY(f->g2d.ensure(ctx, sizeof(float) * G2D_STRIDE * R));
-    fill_u32(f->g2d.as<uint32_t>(), 0u, (uint64_t)G2D_STRIDE * R, s);
+    RTG_TRY(f->g2d.ensure(ctx, sizeof(double) * G2D_STRIDE * R));
+    fill_u32(f->g2d.as<uint32_t>(), 0u, (uint64_t)2 * G2D_STRIDE * R, s);
     {
     Timer tm(ctx, 5, s);
     render_backward(f->st.tile_w, f->st.tile_h, f->st.batch, f->views.as<ViewDev>(), f->n_views,
                     f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
                     f->T_final.as<float>(), f->n_last.as<uint32_t>(), d_rgb, d_depth, d_alpha, d_unc,
-                    f->g2d.as<float>(), s);
+                    f->g2d.as<double>(), nullptr, s);
     }
     RTG_TRY(check_launch("render backward"));
     Timer tm(ctx, 6, s);
     project_backward(to_dev(f->g), f->views.as<ViewDev>(), to_dev(f->st), f->rec_off.as<uint32_t>(),
-                     f->cnt.as<uint32_t>(), f->view.as<uint32_t>(), f->g2d.as<float>(), out->d_means,
-                     out->d_log_scales, out->d_quats, out->d_opacity, out->d_colors, s);
+                     f->cnt.as<uint32_t>(), f->view.as<uint32_t>(), f->g2d.as<double>(), out->d_means,
+                     out->d_log_scales, out->d_quats, out->d_opacity, out->d_colors, nullptr, s);
     return check_launch("projection backward");
 }
 
@@ -805,6 +807,7 @@ extern "C" rtg_status rtg_score_views(rtg_ctx* ctx, const rtg_gaussians* g, cons
 // ================================================================== graph
 
 struct rtg_graph {
+    int kind = 0;  // 0 scoring, 1 mapping
     rtg_ctx* ctx = nullptr;
     std::unique_ptr<rtg_frame> f;
     int max_views = 0, max_w = 0, max_h = 0;
@@ -983,7 +986,7 @@ rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t 
 
 rtg_status rtg_score_graph_launch(rtg_graph* gr, const rtg_camera* cams, int32_t n_views, double* scores,
                                   void* stream) {
-    if (!gr) return set_err(RTG_ERR_INVALID, "graph is NULL");
+    if (!gr || gr->kind != 0) return set_err(RTG_ERR_INVALID, "not a scoring graph");
     RTG_TRY(ctx_ok(gr->ctx));
     RTG_TRY(check_cams(cams, n_views));
     if (n_views > gr->max_views) return set_err(RTG_ERR_INVALID, "n_views %d > graph capacity %d", n_views, gr->max_views);
@@ -1016,6 +1019,146 @@ rtg_status rtg_score_graph_status(rtg_graph* gr) {
 }
 
 void rtg_score_graph_destroy(rtg_graph* gr) { graph_free(gr); }
+
+rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int32_t n_views,
+                                const rtg_settings* settings, const float* target_rgb, const float* target_depth,
+                                float w_depth, float* rgb, float* depth, double* loss, const rtg_grads* grads,
+                                rtg_graph** out, void* stream) {
+    if (!out) return set_err(RTG_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    RTG_TRY(ctx_ok(ctx));
+    RTG_TRY(check_gauss(g, true, false));
+    RTG_TRY(check_cams(cams, n_views));
+    if (!target_rgb || !target_depth || !rgb || !depth || !loss || !grads)
+        return set_err(RTG_ERR_INVALID, "targets, outputs, loss and grads must be non-NULL");
+    if (!std::isfinite(w_depth)) return set_err(RTG_ERR_INVALID, "w_depth is not finite");
+    rtg_settings st;
+    RTG_TRY(resolve_settings(ctx, settings, &st));
+    hipStream_t s = (hipStream_t)stream;
+    // eager pass to size the capacities
+    int64_t R0, K0;
+    {
+        rtg_frame* fp = nullptr;
+        RTG_TRY(new_frame(ctx, g, cams, n_views, &st, &fp, s));
+        std::unique_ptr<rtg_frame> pf(fp);
+        RTG_TRY(enqueue_project(pf.get(), true, s));
+        RTG_TRY(enqueue_bin(pf.get(), true, s));
+        R0 = pf->R;
+        K0 = pf->K;
+    }
+    int64_t rec_cap = std::min<int64_t>(g->n * (int64_t)n_views, R0 + R0 / 2 + 4096);
+    int64_t inst_cap = K0 + K0 / 2 + 16384;
+    if (st.max_instances > 0) {  // explicit capacity
+        inst_cap = st.max_instances;
+        rec_cap = std::min<int64_t>(rec_cap, inst_cap);
+    }
+    rec_cap = std::max<int64_t>(rec_cap, 1);
+    if (inst_cap >= ((int64_t)1 << 31)) return set_err(RTG_ERR_UNSUPPORTED, "capacity above 2^31 pairs");
+
+    rtg_graph* gr = new (std::nothrow) rtg_graph();
+    if (!gr) return set_err(RTG_ERR_OOM, "host allocation failed");
+    gr->kind = 1;
+    gr->ctx = ctx;
+    rtg_frame* fp = nullptr;
+    rtg_status rs = new_frame(ctx, g, cams, n_views, &st, &fp, s);
+    if (rs != RTG_OK) {
+        graph_free(gr);
+        return rs;
+    }
+    gr->f.reset(fp);
+    rtg_frame* f = fp;
+    auto fail = [&](rtg_status code) {
+        graph_free(gr);
+        return code;
+    };
+    const uint64_t P = f->L.hdr.pix_total;
+    const int bx = (f->L.max_pix + 255) / 256;
+    if ((rs = alloc_records(f, (uint32_t)rec_cap)) != RTG_OK) return fail(rs);
+    if ((rs = alloc_instances(f, (uint32_t)inst_cap, f->L.hdr.tiles_total)) != RTG_OK) return fail(rs);
+    if ((rs = ensure_pixel_state(f)) != RTG_OK) return fail(rs);
+    if ((rs = f->g2d.ensure(ctx, sizeof(double) * G2D_STRIDE * (size_t)rec_cap)) != RTG_OK) return fail(rs);
+    if ((rs = f->loss_part.ensure(ctx, sizeof(double) * (size_t)std::max(1, bx * n_views))) != RTG_OK) return fail(rs);
+    if ((rs = f->d_img.ensure(ctx, sizeof(float) * 4 * (size_t)std::max<uint64_t>(P, 1))) != RTG_OK) return fail(rs);
+    f->R = (uint32_t)rec_cap;
+    f->K = inst_cap;
+    hipError_t e;
+    if ((e = hipHostMalloc((void**)&gr->flag_host, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&gr->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        graph_free(gr);
+        return set_err(RTG_ERR_HIP, "graph setup failed: %s", hipGetErrorString(e));
+    }
+    *gr->flag_host = 0;
+    if ((e = hipStreamBeginCapture(gr->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        graph_free(gr);
+        return set_err(RTG_ERR_HIP, "begin capture failed: %s", hipGetErrorString(e));
+    }
+    ctx->capturing = true;
+    hipStream_t cs = gr->cap_stream;
+    float* d_rgb = f->d_img.as<float>();
+    float* d_dep = d_rgb + 3 * P;
+    rs = enqueue_project(f, false, cs);
+    if (rs == RTG_OK) rs = enqueue_bin(f, false, cs);
+    if (rs == RTG_OK) {
+        RenderOut o{rgb, depth, nullptr, nullptr, f->T_final.as<float>(), f->n_last.as<uint32_t>(),
+                    f->n_contrib.as<uint32_t>()};
+        render_forward(st.tile_w, st.tile_h, st.batch, f->views.as<ViewDev>(), n_views, f->L.hdr.tiles_total,
+                       f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(st), o, f->ctr(C_FLAGS), cs);
+        loss_l1(f->views.as<ViewDev>(), n_views, f->L.max_pix, rgb, depth, target_rgb, target_depth, w_depth, d_rgb,
+                d_dep, f->loss_part.as<double>(), bx * n_views, loss, cs);
+        fill_u32(f->g2d.as<uint32_t>(), 0u, (uint64_t)2 * G2D_STRIDE * rec_cap, cs);
+        render_backward(st.tile_w, st.tile_h, st.batch, f->views.as<ViewDev>(), n_views, f->L.hdr.tiles_total,
+                        f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(st), f->T_final.as<float>(),
+                        f->n_last.as<uint32_t>(), d_rgb, d_dep, nullptr, nullptr, f->g2d.as<double>(), f->ctr(C_FLAGS),
+                        cs);
+        project_backward(to_dev(f->g), f->views.as<ViewDev>(), to_dev(st), f->rec_off.as<uint32_t>(),
+                         f->cnt.as<uint32_t>(), f->view.as<uint32_t>(), f->g2d.as<double>(), grads->d_means,
+                         grads->d_log_scales, grads->d_quats, grads->d_opacity, grads->d_colors, f->ctr(C_FLAGS), cs);
+        e = hipMemcpyAsync(gr->flag_host, f->ctr(C_FLAGS), sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
+        if (e != hipSuccess) rs = set_err(RTG_ERR_HIP, "flag copy failed: %s", hipGetErrorString(e));
+        if (rs == RTG_OK) rs = check_launch("mapping graph body");
+    }
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (rs != RTG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_free(gr);
+        return rs;
+    }
+    if (e != hipSuccess) {
+        graph_free(gr);
+        return set_err(RTG_ERR_HIP, "end capture failed: %s", hipGetErrorString(e));
+    }
+    gr->graph = graph;
+    if ((e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        graph_free(gr);
+        return set_err(RTG_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    *out = gr;
+    return RTG_OK;
+}
+
+rtg_status rtg_map_graph_launch(rtg_graph* gr, void* stream) {
+    if (!gr || gr->kind != 1) return set_err(RTG_ERR_INVALID, "not a mapping graph");
+    RTG_TRY(ctx_ok(gr->ctx));
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Timer tm(gr->ctx, 8, s);
+        HIP_TRY(hipGraphLaunch(gr->exec, s));
+    }
+    HIP_TRY(hipEventRecord(gr->done, s));
+    gr->launched = true;
+    return RTG_OK;
+}
+
+rtg_status rtg_map_graph_status(rtg_graph* gr) {
+    if (!gr || gr->kind != 1) return set_err(RTG_ERR_INVALID, "not a mapping graph");
+    return rtg_score_graph_status(gr);
+}
+
+void rtg_map_graph_destroy(rtg_graph* gr) { graph_free(gr); }
 
 // ============================================================== autotune
 
@@ -1092,6 +1235,57 @@ rtg_status rtg_autotune(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* 
     ctx->last_tw = tiles[bi][0];
     ctx->last_th = tiles[bi][1];
     return RTG_OK;
+}
+
+}  // extern "C"
+
+// ========================================================== view utility
+
+extern "C" {
+
+rtg_status rtg_uncertainty_thresholds(rtg_ctx* ctx, const float* uncert, int64_t n, double k_std, double* lo_hi,
+                                      void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (n < 0) return set_err(RTG_ERR_INVALID, "n < 0");
+    if (n > 0 && !uncert) return set_err(RTG_ERR_INVALID, "uncert is NULL");
+    if (!lo_hi) return set_err(RTG_ERR_INVALID, "lo_hi is NULL");
+    if (!std::isfinite(k_std)) return set_err(RTG_ERR_INVALID, "k_std is not finite");
+    Buf scratch;
+    RTG_TRY(scratch.ensure(ctx, sizeof(double) * 520));
+    uncertainty_thresholds(uncert, n, k_std, scratch.as<double>(), lo_hi, (hipStream_t)stream);
+    return check_launch("uncertainty thresholds");
+}
+
+rtg_status rtg_view_utility(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int32_t n_views,
+                            const rtg_settings* settings, float range, const double* lo_hi, double lambda_xi,
+                            int64_t* n_high, int64_t* n_low, double* sum_u, double* xi, void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    RTG_TRY(check_gauss(g, false, true));
+    RTG_TRY(check_cams(cams, n_views));
+    if (!lo_hi) return set_err(RTG_ERR_INVALID, "lo_hi is NULL");
+    if (!(range > 0.0f) || !std::isfinite(range)) return set_err(RTG_ERR_INVALID, "range must be finite and > 0");
+    if (!std::isfinite(lambda_xi)) return set_err(RTG_ERR_INVALID, "lambda_xi is not finite");
+    rtg_settings st;
+    RTG_TRY(resolve_settings(ctx, settings, &st));
+    hipStream_t s = (hipStream_t)stream;
+    Layout L;
+    make_layout(cams, n_views, st.tile_w, st.tile_h, L);
+    Buf views, acc;
+    RTG_TRY(views.ensure(ctx, sizeof(ViewDev) * n_views));
+    RTG_TRY(acc.ensure(ctx, sizeof(unsigned long long) * 3 * n_views));
+    HIP_TRY(hipMemcpyAsync(views.p, L.views.data(), sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+    view_utility(to_dev(*g), views.as<ViewDev>(), n_views, st.z_near, range, lo_hi, acc.as<unsigned long long>(),
+                 lambda_xi, n_high, n_low, sum_u, xi, s);
+    return check_launch("view utility");
+}
+
+rtg_status rtg_trajectory_select(rtg_ctx* ctx, const double* xi, const int32_t* offsets, int32_t n_traj,
+                                 double* traj_utility, int32_t* best, void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (!xi || !offsets || !best) return set_err(RTG_ERR_INVALID, "xi, offsets and best must be non-NULL");
+    if (n_traj < 1) return set_err(RTG_ERR_INVALID, "n_traj = %d < 1", n_traj);
+    trajectory_select(xi, offsets, n_traj, traj_utility, best, (hipStream_t)stream);
+    return check_launch("trajectory select");
 }
 
 }  // extern "C"

@@ -55,13 +55,16 @@ struct Records {
     uint32_t* gid;
     uint32_t* view;
     uint2* rect;       // tile rectangle: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
+    uint2* pbox;       // pixel box of alpha >= alpha_min: x = u0 | u1 << 16, y = v0 | v1 << 16
     uint32_t* dkey;    // binary32 bits of the camera depth (sort key)
     uint32_t* ntiles;  // tiles covered
 };
 
-// Screen-space gradient per record: 16 floats (one 64-byte line):
+// Screen-space gradient per record, binary64, 16 entries (one 128-byte line):
 // [0,1] d mean_2D, [2..4] d conic (xx, xy counted as one parameter, yy),
-// [5] d opacity, [6..8] d colour, [9] d depth, rest unused.
+// [5] d opacity, [6..8] d colour, [9] d depth, rest unused.  Per-tile partial
+// sums are added in binary64 because a splat's mean / conic gradient is a sum
+// of terms of both signs over its footprint that cancel to a small total.
 constexpr int G2D_STRIDE = 16;
 
 constexpr int MAX_VIEWS = 1024;
@@ -73,6 +76,8 @@ constexpr uint32_t FLAG_INST_OVERFLOW = 2u;
 // ---------------------------------------------------------------- launchers
 // All take device pointers and enqueue on `s`.  n_dev arguments are device
 // counters; *_cap are the capacities of the buffers those counts index.
+// `flags` (nullable) is the overflow word of a capacity-sized pipeline: when
+// it is non-zero, kernels that would index past a capacity exit at once.
 
 void fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 
@@ -124,7 +129,7 @@ struct RenderOut {
 void sum_u32_pair(const uint32_t* a, const uint32_t* b, uint64_t n, unsigned long long* out, hipStream_t s);
 void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec,
-                    Records rec, SetDev st, RenderOut out, hipStream_t s);
+                    Records rec, SetDev st, RenderOut out, const uint32_t* flags, hipStream_t s);
 
 void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
              const float* trgb, const float* tdepth, float w_depth, float* d_rgb, float* d_depth,
@@ -134,12 +139,12 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
                      uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec,
                      Records rec, SetDev st, const float* T_final, const uint32_t* n_last,
                      const float* d_rgb, const float* d_depth, const float* d_alpha,
-                     const float* d_unc, float* g2d, hipStream_t s);
+                     const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s);
 
 void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
-                      const uint32_t* cnt, const uint32_t* rec_view, const float* g2d,
+                      const uint32_t* cnt, const uint32_t* rec_view, const double* g2d,
                       float* d_means, float* d_log_scales, float* d_quats, float* d_opacity,
-                      float* d_colors, hipStream_t s);
+                      float* d_colors, const uint32_t* flags, hipStream_t s);
 
 // Scoring: per-(view, tile) partial sums of the composited uncertainty.
 // persistent: a fixed grid pulls tiles from an atomic queue (counter must be
@@ -156,6 +161,16 @@ void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, cons
 
 void export_pairs(const uint32_t* tile_key, const uint32_t* inst_rec, const uint32_t* K_dev,
                   Records rec, uint64_t* keys, uint32_t* vals, uint32_t cap, hipStream_t s);
+
+// Paper-literal view utility: per-view counts of visible high / low
+// uncertainty Gaussians, their uncertainty sum and xi.  acc: 3 * nv u64
+// scratch.  thresholds: scratch of 1 + 512 doubles.
+void view_utility(const GaussDev& g, const ViewDev* views, int nv, float z_near, float range, const double* lo_hi,
+                  unsigned long long* acc, double lambda, int64_t* n_high, int64_t* n_low, double* sum_u, double* xi,
+                  hipStream_t s);
+void uncertainty_thresholds(const float* u, int64_t n, double k, double* scratch, double* lo_hi, hipStream_t s);
+void trajectory_select(const double* xi, const int32_t* offsets, int n_traj, double* util, int32_t* best,
+                       hipStream_t s);
 
 int device_cu_count();
 

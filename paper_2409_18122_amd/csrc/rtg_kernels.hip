@@ -264,6 +264,7 @@ __global__ __launch_bounds__(256) void k_project_emit(GaussDev g, const ViewDev*
             uint32_t tx0 = (uint32_t)(q.u0 / tw), tx1 = (uint32_t)(q.u1 / tw);
             uint32_t ty0 = (uint32_t)(q.v0 / th), ty1 = (uint32_t)(q.v1 / th);
             rec.rect[pos] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+            rec.pbox[pos] = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16), (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
             rec.dkey[pos] = __float_as_uint(depth);
             sortkey[pos] = __float_as_uint(depth);
             rec.ntiles[pos] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
@@ -654,6 +655,31 @@ __device__ __forceinline__ float splat_alpha(float4 g0, float4 g1, float px, flo
     return fminf(amax, g1.w * G);
 }
 
+// Pixel (u, v) inside a splat's support box (outside it, alpha < alpha_min).
+__device__ __forceinline__ bool in_box(uint2 b, int u, int v) {
+    return u >= (int)(b.x & 0xffffu) && u <= (int)(b.x >> 16) && v >= (int)(b.y & 0xffffu) && v <= (int)(b.y >> 16);
+}
+
+// Splat box meets the pixel rectangle [c0, c1] x [r0, r1].
+__device__ __forceinline__ bool box_meets(uint2 b, int c0, int c1, int r0, int r1) {
+    return (int)(b.x & 0xffffu) <= c1 && (int)(b.x >> 16) >= c0 && (int)(b.y & 0xffffu) <= r1 &&
+           (int)(b.y >> 16) >= r0;
+}
+
+// For a staged batch of `cnt` splats, bit k of m[k / 64] is set when splat k's
+// support box meets the calling wave's pixel rectangle (wave-uniform result).
+template <int NT>
+__device__ __forceinline__ void wave_masks(const uint2* s_pb, int cnt, int c0, int c1, int r0, int r1,
+                                           uint64_t (&m)[NT / 64]) {
+    const int lane = (int)lane_id();
+#pragma unroll
+    for (int c = 0; c < NT / 64; c++) {
+        const int e = c * 64 + lane;
+        const bool hit = e < cnt && box_meets(s_pb[e], c0, c1, r0, r1);
+        m[c] = __ballot(hit);
+    }
+}
+
 // Relative band around alpha_min inside which the skip decision is re-taken
 // in binary64 (far wider than the binary32 error of alpha).
 constexpr float REFINE = 2e-3f;
@@ -677,11 +703,14 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec,
-                                                        Records rec, SetDev st, RenderOut out) {
+                                                        Records rec, SetDev st, RenderOut out,
+                                                        const uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
+    if (flags && *flags) return;
     __shared__ float4 s_g0[NT], s_g1[NT], s_at[NT];
     __shared__ float s_u[NT];
     __shared__ uint32_t s_r[NT];
+    __shared__ uint2 s_pb[NT];
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -689,6 +718,9 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
     const uint32_t lt = tile - V.tile_off;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
+    // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of the tile)
+    const int wc0 = tx * TW, wc1 = wc0 + TW - 1;
+    const int wr0 = ty * TH + (int)(threadIdx.x >> 6) * (64 / TW), wr1 = wr0 + 64 / TW - 1;
     const bool inside = u < W && v < H;
     const float px = (float)u, py = (float)v;
     const uint2 rg = ranges[tile];
@@ -701,15 +733,23 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
         if (idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
+            s_pb[threadIdx.x] = rec.pbox[r];
             s_g0[threadIdx.x] = rec.geo0[r];
             s_g1[threadIdx.x] = rec.geo1[r];
             s_at[threadIdx.x] = rec.attr[r];
             s_u[threadIdx.x] = rec.unc[r];
         }
         __syncthreads();
-        int cnt = (int)min<uint32_t>(NT, rg.y - b);
-        if (!done) {
-            for (int k = 0; k < cnt; k++) {
+        const int cnt = (int)min<uint32_t>(NT, rg.y - b);
+        uint64_t m[NT / 64];
+        wave_masks<NT>(s_pb, cnt, wc0, wc1, wr0, wr1, m);
+#pragma unroll
+        for (int c = 0; c < NT / 64; c++) {
+            uint64_t mm = m[c];
+            while (mm && !done) {
+                const int k = c * 64 + (int)__builtin_ctzll(mm);
+                mm &= mm - 1;
+                if (!in_box(s_pb[k], u, v)) continue;
                 float G, dx, dy, w1, w2;
                 const float4 g0 = s_g0[k], g1 = s_g1[k];
                 float a = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
@@ -841,12 +881,15 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
                                                    const uint32_t* __restrict__ n_last,
                                                    const float* __restrict__ d_rgb, const float* __restrict__ d_depth,
                                                    const float* __restrict__ d_alpha,
-                                                   const float* __restrict__ d_unc, float* __restrict__ g2d) {
+                                                   const float* __restrict__ d_unc, double* __restrict__ g2d,
+                                                   const uint32_t* __restrict__ flags) {
     constexpr int PPT = TW * TH / 64;
+    if (flags && *flags) return;
     constexpr int B = 64;
     __shared__ float4 s_g0[B], s_g1[B], s_at[B];
     __shared__ float s_u[B];
     __shared__ uint32_t s_r[B];
+    __shared__ uint2 s_pb[B];
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -858,16 +901,19 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
     const int lane = (int)threadIdx.x;
 
     float px[PPT], py[PPT], T[PPT];
+    int ipx[PPT], ipy[PPT];
     uint32_t last[PPT];
     float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
     float S0[PPT], S1[PPT], S2[PPT], S3[PPT], S4[PPT], S5[PPT];
     uint32_t maxlast = 0;
 #pragma unroll
     for (int j = 0; j < PPT; j++) {
-        const int li = lane + 64 * j;
-        const int u = tx * TW + li % TW, v = ty * TH + li / TW;
+        // pixel slot j of a lane is the lane's position in the j-th 8x8 block of the tile
+        const int u = tx * TW + (j % (TW / 8)) * 8 + (lane & 7), v = ty * TH + (j / (TW / 8)) * 8 + (lane >> 3);
         px[j] = (float)u;
         py[j] = (float)v;
+        ipx[j] = u;
+        ipy[j] = v;
         T[j] = 1.0f;
         last[j] = 0;
         gr[j] = gg[j] = gb[j] = gd[j] = ga[j] = gu[j] = 0.0f;
@@ -901,6 +947,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
             if (e < bend) {
                 const uint32_t r = inst_rec[rg.x + (uint32_t)e];
                 s_r[lane] = r;
+                s_pb[lane] = rec.pbox[r];
                 s_g0[lane] = rec.geo0[r];
                 s_g1[lane] = rec.geo1[r];
                 s_at[lane] = rec.attr[r];
@@ -913,12 +960,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
             const float4 g0 = s_g0[k], g1 = s_g1[k], at = s_at[k];
             const float ui = s_u[k];
             const uint32_t r = s_r[k];
+            const uint2 pb = s_pb[k];
             float a_mx = 0.0f, a_my = 0.0f, a_qa = 0.0f, a_qb = 0.0f, a_qc = 0.0f, a_o = 0.0f;
             float a_c0 = 0.0f, a_c1 = 0.0f, a_c2 = 0.0f, a_d = 0.0f;
             bool any = false;
 #pragma unroll
             for (int j = 0; j < PPT; j++) {
-                if (pos >= last[j]) continue;
+                if (pos >= last[j] || !in_box(pb, ipx[j], ipy[j])) continue;
                 float G, dx, dy, w1, w2;
                 const float a = splat_alpha(g0, g1, px[j], py[j], amax, G, dx, dy, w1, w2);
                 if (!splat_kept(a, g0, g1, rec.q64, r, px[j], py[j], st)) continue;
@@ -963,17 +1011,17 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
                 const float t_c0 = wave_sum_dpp(a_c0), t_c1 = wave_sum_dpp(a_c1), t_c2 = wave_sum_dpp(a_c2);
                 const float t_d = wave_sum_dpp(a_d);
                 if (lane == 0) {
-                    float* dst = g2d + (uint64_t)r * G2D_STRIDE;
-                    unsafeAtomicAdd(dst + 0, t_mx);
-                    unsafeAtomicAdd(dst + 1, t_my);
-                    unsafeAtomicAdd(dst + 2, t_qa);
-                    unsafeAtomicAdd(dst + 3, t_qb);
-                    unsafeAtomicAdd(dst + 4, t_qc);
-                    unsafeAtomicAdd(dst + 5, t_o);
-                    unsafeAtomicAdd(dst + 6, t_c0);
-                    unsafeAtomicAdd(dst + 7, t_c1);
-                    unsafeAtomicAdd(dst + 8, t_c2);
-                    unsafeAtomicAdd(dst + 9, t_d);
+                    double* dst = g2d + (uint64_t)r * G2D_STRIDE;
+                    unsafeAtomicAdd(dst + 0, (double)t_mx);
+                    unsafeAtomicAdd(dst + 1, (double)t_my);
+                    unsafeAtomicAdd(dst + 2, (double)t_qa);
+                    unsafeAtomicAdd(dst + 3, (double)t_qb);
+                    unsafeAtomicAdd(dst + 4, (double)t_qc);
+                    unsafeAtomicAdd(dst + 5, (double)t_o);
+                    unsafeAtomicAdd(dst + 6, (double)t_c0);
+                    unsafeAtomicAdd(dst + 7, (double)t_c1);
+                    unsafeAtomicAdd(dst + 8, (double)t_c2);
+                    unsafeAtomicAdd(dst + 9, (double)t_d);
                 }
             }
         }
@@ -986,12 +1034,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
                                                      const uint32_t* __restrict__ rec_off,
                                                      const uint32_t* __restrict__ cnt,
                                                      const uint32_t* __restrict__ rec_view,
-                                                     const float* __restrict__ g2d,
+                                                     const double* __restrict__ g2d,
                                                      float* __restrict__ d_means, float* __restrict__ d_ls,
                                                      float* __restrict__ d_quats, float* __restrict__ d_op,
-                                                     float* __restrict__ d_col) {
+                                                     float* __restrict__ d_col, const uint32_t* __restrict__ flags) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
+    if (flags && *flags) return;
     uint32_t c = cnt[i];
     if (c == 0) return;
     GPre P;
@@ -1004,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
         const ViewDev& V = views[rec_view[r]];
         GProj q;
         project_exact(P, V, st, q);
-        const float* G2 = g2d + (uint64_t)r * G2D_STRIDE;
+        const double* G2 = g2d + (uint64_t)r * G2D_STRIDE;
         double gmx = G2[0], gmy = G2[1], gqa = G2[2], gqb = G2[3], gqc = G2[4];
         go += G2[5];
         gc[0] += G2[6];
@@ -1127,13 +1176,16 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
                                                const uint32_t* __restrict__ inst_rec, const Records& rec,
                                                const SetDev& st, double* __restrict__ partial,
                                                float4* s_g0, float4* s_g1, float* s_u, uint32_t* s_r,
-                                               double* ws) {
+                                               uint2* s_pb, double* ws) {
     constexpr int NT = TW * TH;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
     const uint32_t lt = tile - V.tile_off;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
+    // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of the tile)
+    const int wc0 = tx * TW, wc1 = wc0 + TW - 1;
+    const int wr0 = ty * TH + (int)(threadIdx.x >> 6) * (64 / TW), wr1 = wr0 + 64 / TW - 1;
     const bool inside = u < V.W && v < V.H;
     const float px = (float)u, py = (float)v;
     const uint2 rg = ranges[tile];
@@ -1145,14 +1197,22 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
         if (idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
+            s_pb[threadIdx.x] = rec.pbox[r];
             s_g0[threadIdx.x] = rec.geo0[r];
             s_g1[threadIdx.x] = rec.geo1[r];
             s_u[threadIdx.x] = rec.unc[r];
         }
         __syncthreads();
-        int cnt = (int)min<uint32_t>(NT, rg.y - b);
-        if (!done) {
-            for (int k = 0; k < cnt; k++) {
+        const int cnt = (int)min<uint32_t>(NT, rg.y - b);
+        uint64_t m[NT / 64];
+        wave_masks<NT>(s_pb, cnt, wc0, wc1, wr0, wr1, m);
+#pragma unroll
+        for (int c = 0; c < NT / 64; c++) {
+            uint64_t mm = m[c];
+            while (mm && !done) {
+                const int k = c * 64 + (int)__builtin_ctzll(mm);
+                mm &= mm - 1;
+                if (!in_box(s_pb[k], u, v)) continue;
                 float G, dx, dy, w1, w2;
                 const float4 g0 = s_g0[k], g1 = s_g1[k];
                 float a = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
@@ -1187,9 +1247,10 @@ __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restri
     __shared__ float4 s_g0[NT], s_g1[NT];
     __shared__ float s_u[NT];
     __shared__ uint32_t s_r[NT];
+    __shared__ uint2 s_pb[NT];
     __shared__ double ws[NT / 64];
     score_one_tile<TW, TH>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial, s_g0,
-                           s_g1, s_u, s_r, ws);
+                           s_g1, s_u, s_r, s_pb, ws);
 }
 
 template <int TW, int TH>
@@ -1205,6 +1266,7 @@ __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __r
     __shared__ float4 s_g0[NT], s_g1[NT];
     __shared__ float s_u[NT];
     __shared__ uint32_t s_r[NT];
+    __shared__ uint2 s_pb[NT];
     __shared__ double ws[NT / 64];
     __shared__ uint32_t s_item;
     const uint32_t total = hdr->tiles_total;
@@ -1215,7 +1277,7 @@ __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __r
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= total) break;
-        score_one_tile<TW, TH>(views, nv, item, ranges, inst_rec, rec, st, partial, s_g0, s_g1, s_u, s_r, ws);
+        score_one_tile<TW, TH>(views, nv, item, ranges, inst_rec, rec, st, partial, s_g0, s_g1, s_u, s_r, s_pb, ws);
     }
 }
 
@@ -1273,6 +1335,160 @@ __global__ __launch_bounds__(256) void k_sum_u32_pair(const uint32_t* __restrict
     }
 }
 
+// ------------------------------------------------ view utility of eq. (8)
+// Sec. IV-B: v(x, g) = 1 when the Gaussian is in the field of view (camera
+// depth in (z_near, range], projected mean inside the image, no occlusion);
+// xi = |H visible| - lambda |L visible| with H / L the Gaussians above / below
+// the uncertainty thresholds.  The visibility test runs in binary32 and falls
+// back to the exact binary64 expression within a margin of every border.
+
+constexpr int UT_THREADS = 256;
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40: uncertainty sums in fixed point
+
+__device__ __forceinline__ bool fov_exact(double mx0, double my0, double mz0, const ViewDev& V, double z_near,
+                                          double range) {
+    double dx = mx0 - V.T[0], dy = my0 - V.T[1], dz = mz0 - V.T[2];
+    const double* R = V.R;
+    double tx = (dx * R[0] + dy * R[3]) + dz * R[6];
+    double ty = (dx * R[1] + dy * R[4]) + dz * R[7];
+    double tz = (dx * R[2] + dy * R[5]) + dz * R[8];
+    if (!(tz > z_near) || !(tz <= range)) return false;
+    double mx = V.fx * tx / tz + V.cx;
+    double my = V.fy * ty / tz + V.cy;
+    return mx >= 0.0 && mx <= (double)(V.W - 1) && my >= 0.0 && my <= (double)(V.H - 1);
+}
+
+// 1 visible, 0 not, -1 undecided in binary32
+__device__ __forceinline__ int fov_fast(float x, float y, float z, const ViewDev& V, float z_near, float range) {
+    float dx = x - (float)V.T[0], dy = y - (float)V.T[1], dz = z - (float)V.T[2];
+    float mag = fabsf(dx) + fabsf(dy) + fabsf(dz) + 1.0f;
+    float tx = dx * (float)V.R[0] + dy * (float)V.R[3] + dz * (float)V.R[6];
+    float ty = dx * (float)V.R[1] + dy * (float)V.R[4] + dz * (float)V.R[7];
+    float tz = dx * (float)V.R[2] + dy * (float)V.R[5] + dz * (float)V.R[8];
+    float ez = 1e-5f * mag;
+    if (tz <= z_near - ez || tz > range + ez) return 0;
+    if (tz <= z_near + ez || tz > range - ez) return -1;
+    float mx = (float)V.fx * tx / tz + (float)V.cx;
+    float my = (float)V.fy * ty / tz + (float)V.cy;
+    float m = 1e-3f * (1.0f + fabsf(mx) + fabsf(my)) + 1e-3f * mag * ((float)V.fx + (float)V.fy) / tz;
+    float W1 = (float)(V.W - 1), H1 = (float)(V.H - 1);
+    if (mx < -m || mx > W1 + m || my < -m || my > H1 + m) return 0;
+    if (mx > m && mx < W1 - m && my > m && my < H1 - m) return 1;
+    return -1;
+}
+
+__global__ __launch_bounds__(UT_THREADS) void k_view_utility(GaussDev g, const ViewDev* __restrict__ views, int nv,
+                                                             float z_near, float range,
+                                                             const double* __restrict__ lo_hi,
+                                                             unsigned long long* __restrict__ cnt_h,
+                                                             unsigned long long* __restrict__ cnt_l,
+                                                             unsigned long long* __restrict__ fix_u) {
+    extern __shared__ unsigned long long s_acc[];  // 3 * nv
+    for (int i = threadIdx.x; i < 3 * nv; i += UT_THREADS) s_acc[i] = 0ull;
+    __syncthreads();
+    const double lo = lo_hi[0], hi = lo_hi[1];
+    const int64_t n = g.n;
+    for (int64_t base = (int64_t)blockIdx.x * UT_THREADS; base < n; base += (int64_t)gridDim.x * UT_THREADS) {
+        const int64_t i = base + threadIdx.x;
+        const bool live = i < n;
+        float x = 0.0f, y = 0.0f, z = 0.0f, u = 0.0f;
+        if (live) {
+            x = g.means[i];
+            y = g.means[n + i];
+            z = g.means[2 * n + i];
+            u = g.uncert[i];
+        }
+        const bool ok = live && isfinite(x) && isfinite(y) && isfinite(z);
+        const bool isH = (double)u > hi, isL = (double)u < lo;
+        const unsigned long long fu = (isfinite(u) && u > 0.0f) ? (unsigned long long)((double)u * FIX_SCALE) : 0ull;
+        for (int v = 0; v < nv; v++) {
+            const ViewDev& V = views[v];
+            bool vis = false;
+            if (ok) {
+                int f = fov_fast(x, y, z, V, z_near, range);
+                vis = f < 0 ? fov_exact((double)x, (double)y, (double)z, V, (double)z_near, (double)range) : f == 1;
+            }
+            const uint64_t bh = __ballot(vis && isH), bl = __ballot(vis && isL);
+            unsigned long long su = vis ? fu : 0ull;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) su += __shfl_xor(su, o, 64);
+            if (lane_id() == 0 && (bh | bl | su)) {
+                atomicAdd(&s_acc[3 * v + 0], (unsigned long long)__popcll(bh));
+                atomicAdd(&s_acc[3 * v + 1], (unsigned long long)__popcll(bl));
+                atomicAdd(&s_acc[3 * v + 2], su);
+            }
+        }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < nv; v += UT_THREADS) {
+        if (s_acc[3 * v + 0]) atomicAdd(cnt_h + v, s_acc[3 * v + 0]);
+        if (s_acc[3 * v + 1]) atomicAdd(cnt_l + v, s_acc[3 * v + 1]);
+        if (s_acc[3 * v + 2]) atomicAdd(fix_u + v, s_acc[3 * v + 2]);
+    }
+}
+
+__global__ void k_utility_finish(int nv, const unsigned long long* __restrict__ cnt_h,
+                                 const unsigned long long* __restrict__ cnt_l,
+                                 const unsigned long long* __restrict__ fix_u, double lambda,
+                                 int64_t* __restrict__ n_high, int64_t* __restrict__ n_low,
+                                 double* __restrict__ sum_u, double* __restrict__ xi) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        if (n_high) n_high[v] = (int64_t)cnt_h[v];
+        if (n_low) n_low[v] = (int64_t)cnt_l[v];
+        if (sum_u) sum_u[v] = (double)fix_u[v] / FIX_SCALE;
+        if (xi) xi[v] = (double)cnt_h[v] - lambda * (double)cnt_l[v];
+    }
+}
+
+// mean and population standard deviation of u, binary64, fixed reduction order
+__global__ __launch_bounds__(256) void k_moments(const float* __restrict__ u, int64_t n, int pass,
+                                                 const double* __restrict__ mean_in, double* __restrict__ partial) {
+    __shared__ double ws[4];
+    const double mean = pass ? *mean_in : 0.0;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double d = (double)u[i] - mean;
+        s += pass ? d * d : (double)u[i];
+    }
+    s = wave_sum_d(s);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ void k_moments_finish(const double* __restrict__ partial, int nb, int64_t n, int pass, double k,
+                                 double* __restrict__ mean_io, double* __restrict__ lo_hi) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; b++) s += partial[b];
+    if (pass == 0) {
+        *mean_io = n > 0 ? s / (double)n : 0.0;
+    } else {
+        double sd = n > 0 ? sqrt(s / (double)n) : 0.0;
+        lo_hi[0] = *mean_io - k * sd;
+        lo_hi[1] = *mean_io + k * sd;
+    }
+}
+
+// eq. (10): utility of trajectory t = sum of xi over its states
+// [off[t], off[t+1]) in order; best = first trajectory of maximal utility.
+__global__ void k_traj_select(const double* __restrict__ xi, const int32_t* __restrict__ off, int n_traj,
+                              double* __restrict__ util, int32_t* __restrict__ best) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int b = -1;
+    double bv = 0.0;
+    for (int t = 0; t < n_traj; t++) {
+        double s = 0.0;
+        for (int k = off[t]; k < off[t + 1]; k++) s += xi[k];
+        if (util) util[t] = s;
+        if (b < 0 || s > bv) {
+            b = t;
+            bv = s;
+        }
+    }
+    *best = b;
+}
+
 inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535u * 16u) {
     uint64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -1305,6 +1521,34 @@ int score_persistent_blocks(int tw, int th) {
                                                                         TW * TH, 0)));
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return per_cu * device_cu_count();
+}
+
+void view_utility(const GaussDev& g, const ViewDev* views, int nv, float z_near, float range, const double* lo_hi,
+                  unsigned long long* acc, double lambda, int64_t* n_high, int64_t* n_low, double* sum_u, double* xi,
+                  hipStream_t s) {
+    fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, (uint64_t)6 * nv, s);
+    if (g.n > 0) {
+        unsigned grid = grid_for((uint64_t)g.n, UT_THREADS, 1024);
+        size_t lds = sizeof(unsigned long long) * 3 * (size_t)nv;
+        k_view_utility<<<grid, UT_THREADS, lds, s>>>(g, views, nv, z_near, range, lo_hi, acc, acc + nv, acc + 2 * nv);
+    }
+    k_utility_finish<<<(nv + 255) / 256, 256, 0, s>>>(nv, acc, acc + nv, acc + 2 * nv, lambda, n_high, n_low, sum_u,
+                                                      xi);
+}
+
+void uncertainty_thresholds(const float* u, int64_t n, double k, double* scratch, double* lo_hi, hipStream_t s) {
+    const int nb = (int)grid_for((uint64_t)std::max<int64_t>(n, 1), 256, 512);
+    double* mean = scratch;
+    double* partial = scratch + 1;
+    k_moments<<<nb, 256, 0, s>>>(u, n, 0, mean, partial);
+    k_moments_finish<<<1, 64, 0, s>>>(partial, nb, n, 0, k, mean, lo_hi);
+    k_moments<<<nb, 256, 0, s>>>(u, n, 1, mean, partial);
+    k_moments_finish<<<1, 64, 0, s>>>(partial, nb, n, 1, k, mean, lo_hi);
+}
+
+void trajectory_select(const double* xi, const int32_t* offsets, int n_traj, double* util, int32_t* best,
+                       hipStream_t s) {
+    k_traj_select<<<1, 64, 0, s>>>(xi, offsets, n_traj, util, best);
 }
 
 int device_cu_count() {
@@ -1402,11 +1646,11 @@ void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_
 
 void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
-                    RenderOut out, hipStream_t s) {
+                    RenderOut out, const uint32_t* flags, hipStream_t s) {
     (void)batch;
     if (tiles_total == 0) return;
     RTG_TILE_DISPATCH(TW, TH, (k_render_fwd<TW, TH><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges,
-                                                                                   inst_rec, rec, st, out)));
+                                                                                   inst_rec, rec, st, out, flags)));
 }
 
 void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
@@ -1422,21 +1666,22 @@ void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, c
 void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views,
                      uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
                      const float* T_final, const uint32_t* n_last, const float* d_rgb, const float* d_depth,
-                     const float* d_alpha, const float* d_unc, float* g2d, hipStream_t s) {
+                     const float* d_alpha, const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s) {
     (void)batch;
     if (tiles_total == 0) return;
     RTG_TILE_DISPATCH(TW, TH,
                       (k_render_bwd<TW, TH><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
                                                                             T_final, n_last, d_rgb, d_depth,
-                                                                            d_alpha, d_unc, g2d)));
+                                                                            d_alpha, d_unc, g2d, flags)));
 }
 
 void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
-                      const uint32_t* cnt, const uint32_t* rec_view, const float* g2d, float* d_means,
-                      float* d_log_scales, float* d_quats, float* d_opacity, float* d_colors, hipStream_t s) {
+                      const uint32_t* cnt, const uint32_t* rec_view, const double* g2d, float* d_means,
+                      float* d_log_scales, float* d_quats, float* d_opacity, float* d_colors, const uint32_t* flags,
+                      hipStream_t s) {
     if (g.n == 0) return;
     k_project_bwd<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, st, rec_off, cnt, rec_view, g2d, d_means,
-                                                     d_log_scales, d_quats, d_opacity, d_colors);
+                                                     d_log_scales, d_quats, d_opacity, d_colors, flags);
 }
 
 void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent, const ViewDev* views,

@@ -299,6 +299,90 @@ class ScoreGraph:
             pass
 
 
+class MapGraph:
+    """One mapping iteration (render, L1 loss, backward) on fixed keyframes,
+    captured once and replayed; gradients are added into `grads`."""
+
+    def __init__(self, ctx, g, cams, target_rgb, target_depth, w_depth=0.5, settings=None, grads=None):
+        self.ctx = ctx
+        self._g = g
+        self._gs = make_gaussians(g)
+        self.cams = cams
+        self._cams = make_cameras(cams)
+        self.settings = make_settings(settings)
+        P = sum(image_sizes(cams))
+        dev = g["means"].device
+        self.rgb = torch.empty(3 * P, device=dev, dtype=torch.float32)
+        self.depth = torch.empty(P, device=dev, dtype=torch.float32)
+        self.loss = torch.zeros(1, device=dev, dtype=torch.float64)
+        self.grads = grads if grads is not None else {k: torch.zeros_like(g[k]) for k in GRAD_KEYS}
+        self._targets = (target_rgb, target_depth)
+        gr = Grads(*[_ptr(self.grads.get(k)) for k in GRAD_KEYS])
+        h = ctypes.c_void_p()
+        check(lib().rtg_map_graph_create(ctx.handle, ctypes.byref(self._gs), self._cams, len(cams),
+                                         ctypes.byref(self.settings), _ptr(target_rgb), _ptr(target_depth),
+                                         float(w_depth), _ptr(self.rgb), _ptr(self.depth), _ptr(self.loss),
+                                         ctypes.byref(gr), ctypes.byref(h), _stream()))
+        self.handle = h
+
+    def launch(self):
+        check(lib().rtg_map_graph_launch(self.handle, _stream()))
+        return self.loss
+
+    def status(self):
+        code = lib().rtg_map_graph_status(self.handle)
+        if code == RTG_ERR_CAPACITY:
+            return False
+        check(code)
+        return True
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rtg_map_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def uncertainty_thresholds(ctx, uncert, k_std=0.5):
+    """Device tensor [mean - k sd, mean + k sd] of the uncertainties."""
+    out = torch.empty(2, device=uncert.device, dtype=torch.float64)
+    check(lib().rtg_uncertainty_thresholds(ctx.handle, _ptr(uncert), int(uncert.numel()), float(k_std),
+                                           _ptr(out), _stream()))
+    return out
+
+
+def view_utility(ctx, g, cams, lo_hi, settings=None, range_=5.0, lambda_xi=1.0):
+    """Paper-literal utility per view: dict of n_high, n_low (int64), sum_u, xi (float64)."""
+    gs = make_gaussians(g)
+    cs = make_cameras(cams)
+    st = make_settings(settings)
+    dev = g["means"].device
+    V = len(cams)
+    out = {"n_high": torch.empty(V, device=dev, dtype=torch.int64),
+           "n_low": torch.empty(V, device=dev, dtype=torch.int64),
+           "sum_u": torch.empty(V, device=dev, dtype=torch.float64),
+           "xi": torch.empty(V, device=dev, dtype=torch.float64)}
+    check(lib().rtg_view_utility(ctx.handle, ctypes.byref(gs), cs, V, ctypes.byref(st), float(range_),
+                                 _ptr(lo_hi), float(lambda_xi), _ptr(out["n_high"]), _ptr(out["n_low"]),
+                                 _ptr(out["sum_u"]), _ptr(out["xi"]), _stream()))
+    return out
+
+
+def trajectory_select(ctx, xi, offsets):
+    """eq. (10): per-trajectory sums of xi over [offsets[t], offsets[t+1]) and the best index."""
+    off = offsets.to(device=xi.device, dtype=torch.int32).contiguous()
+    n = off.numel() - 1
+    util = torch.empty(n, device=xi.device, dtype=torch.float64)
+    best = torch.empty(1, device=xi.device, dtype=torch.int32)
+    check(lib().rtg_trajectory_select(ctx.handle, _ptr(xi), _ptr(off), n, _ptr(util), _ptr(best), _stream()))
+    return util, best
+
+
 def autotune(ctx, g, cams, mode, settings=None):
     st = make_settings(settings)
     gs = make_gaussians(g)
@@ -328,5 +412,5 @@ def unpack_images(out, cams):
     return res
 
 
-__all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph",
+__all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph", "MapGraph",
            "autotune", "to_device", "unpack_images", "RtgError", "DEFAULTS"]

@@ -72,11 +72,26 @@ def test_null_arguments_rejected_on_host(L):
     info = (ctypes.c_int64 * 6)()
     assert L.rtg_frame_info(None, info) == -1
     assert L.rtg_autotune(None, None, None, 1, 0, None, None) == -1
+    assert L.rtg_map_graph_create(None, None, None, 1, None, None, None, 0.5, None, None, None, None,
+                                  ctypes.byref(out), None) == -1
+    assert L.rtg_map_graph_launch(None, None) == -1
+    assert L.rtg_map_graph_status(None) == -1
+    assert L.rtg_view_utility(None, None, None, 1, None, 5.0, None, 1.0, None, None, None, None, None) == -1
+    assert L.rtg_uncertainty_thresholds(None, None, 0, 0.5, None, None) == -1
+    assert L.rtg_trajectory_select(None, None, None, 1, None, None, None) == -1
+    stats = (ctypes.c_int64 * 4)()
+    assert L.rtg_frame_stats(None, None, stats, None) == -1
+    assert L.rtg_timing_enable(None, 1) == -1
+    assert L.rtg_timing_reset(None) == -1
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    assert L.rtg_timing_read(None, 0, ctypes.byref(ms), ctypes.byref(n)) == -1
     assert len(L.rtg_last_error()) > 0
     # destroy functions accept NULL
     L.rtg_destroy(None)
     L.rtg_frame_destroy(None)
     L.rtg_score_graph_destroy(None)
+    L.rtg_map_graph_destroy(None)
 
 
 def test_missing_library_fails_loudly(monkeypatch):

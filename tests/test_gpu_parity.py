@@ -330,3 +330,51 @@ def test_invalid_arguments(raster, rctx):
     nan = [dict(cams[0], fx=float("nan"))]
     with pytest.raises(raster.RtgError):
         raster.Frame(rctx, dev, nan, S())
+
+
+# ------------------------------------------------------- captured mapping step
+
+def test_map_graph_matches_eager(raster, rctx):
+    g, cams, target = scenes.config4(n=80_000, n_views=2, width=320, height=180)
+    dev = raster.to_device(g)
+    tdev = raster.to_device(target)
+    timg, tf = raster.render(rctx, tdev, cams, S(), want=("rgb", "depth"))
+    tf.close()
+    say("map graph: eager reference step")
+    f = raster.Frame(rctx, dev, cams, S())
+    f.bin_sort()
+    out = f.render(("rgb", "depth"))
+    loss, d_rgb, d_dep = f.loss(out["rgb"], out["depth"], timg["rgb"], timg["depth"], 0.5)
+    ref = f.backward(d_rgb, d_dep)
+    f.close()
+    say("map graph: capture and replay 3 times")
+    mg = raster.MapGraph(rctx, dev, cams, timg["rgb"], timg["depth"], 0.5, S())
+    for rep in range(3):
+        l = mg.launch()
+        assert mg.status()
+        torch.cuda.synchronize()
+        # eager work between replays
+        _ = (dev["means"] * 1.0).sum().item()
+        assert torch.equal(mg.rgb, out["rgb"]) and torch.equal(mg.depth, out["depth"]), rep
+        assert l.item() == loss.item(), rep
+    for k in ref:
+        a = mg.grads[k].double().cpu().numpy()
+        b = 3.0 * ref[k].double().cpu().numpy()
+        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-300)
+        assert rel <= 1e-5, (k, rel)
+    mg.close()
+
+
+def test_map_graph_capacity_overflow_is_reported(raster, rctx):
+    g, cams, target = scenes.config4(n=20_000, n_views=1, width=160, height=90)
+    dev = raster.to_device(g)
+    tdev = raster.to_device(target)
+    timg, tf = raster.render(rctx, tdev, cams, S(), want=("rgb", "depth"))
+    tf.close()
+    say("map graph with a too small pair capacity")
+    mg = raster.MapGraph(rctx, dev, cams, timg["rgb"], timg["depth"], 0.5, S(max_instances=100))
+    mg.launch()
+    assert mg.status() is False
+    for k in mg.grads:
+        assert not mg.grads[k].any()  # kernels past the overflow exited: nothing added
+    mg.close()
