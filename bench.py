@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-scoring", action="store_true", help="skip the view-scoring workloads")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256-view uneven scoring workload")
+    ap.add_argument("--no-keyframes", action="store_true", help="skip the 8-keyframe 1280x720 mapping workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=str, default="16x16")
     ap.add_argument("--sweep-tiles", action="store_true", help="also time the step at every tile shape")
@@ -189,6 +190,35 @@ def main():
             "avg_ms": round(avg_ms, 4), "units": stats["contrib_pairs"],
             "ops_per_unit": OPS_PER_PAIR[dom]}
 
+    # ------------------------------------------------- 8 keyframes, 1M Gaussians
+    keyframes = None
+    if not args.no_keyframes:
+        log("setup: 8 keyframes 1280x720, 1M Gaussians (tile chosen by the autotuner)")
+        g4_np, cams4, t4_np = scenes.config4()
+        g4 = raster.to_device(g4_np)
+        t4 = raster.to_device(t4_np)
+        S4 = raster.autotune(ctx, g4, cams4, 1, S)
+        timg4, tf4 = raster.render(ctx, t4, cams4, S4, want=("rgb", "depth"))
+        tf4.close()
+        grads4 = {k: torch.zeros_like(g4[k]) for k in raster.GRAD_KEYS}
+        mg4 = raster.MapGraph(ctx, g4, cams4, timg4["rgb"], timg4["depth"], 0.5, S4, grads=grads4)
+        for _ in range(2):
+            mg4.launch()
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mg4.launch()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        assert mg4.status(), "keyframe mapping graph capacity overflow"
+        mg4.close()
+        P4 = sum(c["width"] * c["height"] for c in cams4)
+        keyframes = {"ms_per_step": round(dt * 1e3, 3), "mpix_per_s": round(P4 / dt / 1e6, 1),
+                     "tile": f"{S4['tile_w']}x{S4['tile_h']}", "pixels": P4}
+        log(f"8 keyframes: {keyframes}")
+        del g4, t4, grads4
+
     # ------------------------------------------------------- view scoring
     views = {}
     if not args.no_scoring:
@@ -284,6 +314,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "views_per_s": views,
+        "keyframes_8x1280x720": keyframes,
         "kernel_ms_per_step_eager": {k: round(v[0] / args.steps, 4) for k, v in kern.items() if v[1]},
         "frame_stats": stats,
     }

@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace rtg {
 
@@ -421,9 +422,11 @@ __device__ __forceinline__ void rs_chunk(uint32_t n, uint32_t& begin, uint32_t& 
     end = (uint32_t)min<uint64_t>(b + per, n);
 }
 
+// hist layout: digit-major [d][block] when block_major == 0 (scanned as a
+// whole), block-major [block][d] otherwise (read directly by the scatter).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ n_dev, uint32_t cap,
-                                                           int shift, uint32_t* __restrict__ hist) {
+                                                           int shift, uint32_t* __restrict__ hist, int block_major) {
     __shared__ uint32_t h[RS_WAVES][256];
     int tid = threadIdx.x, wv = tid >> 6;
     for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
@@ -443,7 +446,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
     uint32_t s = 0;
 #pragma unroll
     for (int w = 0; w < RS_WAVES; w++) s += h[w][tid];
-    hist[(uint64_t)tid * gridDim.x + blockIdx.x] = s;
+    if (block_major)
+        hist[(uint64_t)blockIdx.x * 256 + tid] = s;
+    else
+        hist[(uint64_t)tid * gridDim.x + blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
@@ -451,15 +457,37 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_dev, uint32_t cap,
-                                                           int shift, const uint32_t* __restrict__ hist) {
+                                                           int shift, const uint32_t* __restrict__ hist,
+                                                           int block_major) {
     __shared__ uint32_t wh[RS_WAVES][256];
     __shared__ uint32_t bbase[256];
+    __shared__ uint32_t ws[RS_WAVES];
     int tid = threadIdx.x, wv = tid >> 6;
     uint32_t lane = lane_id();
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
     rs_chunk(n, begin, end);
-    bbase[tid] = hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+    if (block_major) {
+        // offset of digit tid for this block = count of smaller digits in all
+        // blocks + count of this digit in earlier blocks
+        uint32_t tot = 0, pre = 0;
+#pragma unroll 8
+        for (uint32_t b = 0; b < gridDim.x; b++) {
+            const uint32_t c = hist[(uint64_t)b * 256 + tid];
+            tot += c;
+            if (b < blockIdx.x) pre += c;
+        }
+        uint32_t inc = wave_incl_scan(tot);
+        if (lane == 63) ws[wv] = inc;
+        __syncthreads();
+        uint32_t base = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; w++)
+            if (w < wv) base += ws[w];
+        bbase[tid] = base + inc - tot + pre;
+    } else {
+        bbase[tid] = hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+    }
     for (uint32_t t0 = begin; t0 < end; t0 += RS_TILE) {
         for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&wh[0][0])[i] = 0;
         __syncthreads();
@@ -506,41 +534,6 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
             }
         }
         __syncthreads();
-    }
-}
-
-// Scan of the digit-major histogram table (256 * nblocks entries, all
-// present): a single block, sequential over chunks.
-__global__ __launch_bounds__(1024) void k_rs_hist_scan(uint32_t* __restrict__ hist, uint32_t count) {
-    __shared__ uint32_t ws[16];
-    uint32_t run = 0;
-    for (uint32_t t0 = 0; t0 < count; t0 += 1024 * 4) {
-        uint32_t v[4];
-        uint32_t first = t0 + threadIdx.x * 4;
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            v[j] = first + j < count ? hist[first + j] : 0u;
-            sum += v[j];
-        }
-        uint32_t inc = wave_incl_scan(sum);
-        int wv = threadIdx.x >> 6;
-        if (lane_id() == 63) ws[wv] = inc;
-        __syncthreads();
-        uint32_t base = 0, tot = 0;
-        for (int w = 0; w < 16; w++) {
-            uint32_t t = ws[w];
-            if (w < wv) base += t;
-            tot += t;
-        }
-        __syncthreads();
-        uint32_t ex = run + base + inc - sum;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            if (first + j < count) hist[first + j] = ex;
-            ex += v[j];
-        }
-        run += tot;
     }
 }
 
@@ -680,6 +673,18 @@ __device__ __forceinline__ void wave_masks(const uint2* s_pb, int cnt, int c0, i
     }
 }
 
+// Next two set bits of a wave-uniform mask (k1 < 0 if only one is left).
+__device__ __forceinline__ void pop2(uint64_t& mm, int base, int& k0, int& k1) {
+    k0 = base + (int)__builtin_ctzll(mm);
+    mm &= mm - 1;
+    if (mm) {
+        k1 = base + (int)__builtin_ctzll(mm);
+        mm &= mm - 1;
+    } else {
+        k1 = -1;
+    }
+}
+
 // Relative band around alpha_min inside which the skip decision is re-taken
 // in binary64 (far wider than the binary32 error of alpha).
 constexpr float REFINE = 2e-3f;
@@ -747,28 +752,41 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
         for (int c = 0; c < NT / 64; c++) {
             uint64_t mm = m[c];
             while (mm && !done) {
-                const int k = c * 64 + (int)__builtin_ctzll(mm);
-                mm &= mm - 1;
-                if (!in_box(s_pb[k], u, v)) continue;
-                float G, dx, dy, w1, w2;
-                const float4 g0 = s_g0[k], g1 = s_g1[k];
-                float a = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
-                if (!splat_kept(a, g0, g1, rec.q64, s_r[k], px, py, st)) continue;
-                float Tn = T * (1.0f - a);
-                if (Tn < st.T_min) {
-                    done = true;
-                    break;
+                // two splats per step: their alphas are independent of T
+                int ks[2];
+                pop2(mm, c * 64, ks[0], ks[1]);
+                float as[2];
+                bool ok[2];
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const int k = ks[q] < 0 ? ks[0] : ks[q];
+                    float G, dx, dy, w1, w2;
+                    const float4 g0 = s_g0[k], g1 = s_g1[k];
+                    as[q] = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
+                    ok[q] = ks[q] >= 0 && in_box(s_pb[k], u, v) &&
+                            splat_kept(as[q], g0, g1, rec.q64, s_r[k], px, py, st);
                 }
-                float w = a * T;
-                float4 at = s_at[k];
-                c0 = fmaf(at.x, w, c0);
-                c1 = fmaf(at.y, w, c1);
-                c2 = fmaf(at.z, w, c2);
-                dd = fmaf(at.w, w, dd);
-                uu = fmaf(s_u[k], w, uu);
-                T = Tn;
-                last = b - rg.x + (uint32_t)k + 1;
-                ncontrib++;
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    if (!ok[q] || done) continue;
+                    const int k = ks[q];
+                    const float a = as[q];
+                    const float Tn = T * (1.0f - a);
+                    if (Tn < st.T_min) {
+                        done = true;
+                        continue;
+                    }
+                    const float w = a * T;
+                    const float4 at = s_at[k];
+                    c0 = fmaf(at.x, w, c0);
+                    c1 = fmaf(at.y, w, c1);
+                    c2 = fmaf(at.z, w, c2);
+                    dd = fmaf(at.w, w, dd);
+                    uu = fmaf(s_u[k], w, uu);
+                    T = Tn;
+                    last = b - rg.x + (uint32_t)k + 1;
+                    ncontrib++;
+                }
             }
         }
     }
@@ -870,26 +888,33 @@ __device__ __forceinline__ float wave_sum_dpp(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-// One wave per tile; each lane owns PPT pixels of the tile (lane + 64 j).
-// Per splat, the lane sums its pixels' contributions, the wave reduces them
-// once with DPP, and one lane adds the 10 totals to the record's gradient.
-template <int TW, int TH>
-__global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
-                                                   const uint2* __restrict__ ranges,
-                                                   const uint32_t* __restrict__ inst_rec, Records rec, SetDev st,
-                                                   const float* __restrict__ T_final,
-                                                   const uint32_t* __restrict__ n_last,
-                                                   const float* __restrict__ d_rgb, const float* __restrict__ d_depth,
-                                                   const float* __restrict__ d_alpha,
-                                                   const float* __restrict__ d_unc, double* __restrict__ g2d,
-                                                   const uint32_t* __restrict__ flags) {
-    constexpr int PPT = TW * TH / 64;
+// NW waves per tile; the tile's 8x8 pixel blocks are dealt to the waves in
+// row-major order (PPT blocks each) and a lane owns one pixel per block.
+// Splats are staged per batch for the whole workgroup; a wave skips a splat
+// whose support box misses all of its blocks (a wave-uniform test).  Per
+// splat, the lane sums its pixels' contributions, the wave reduces them once
+// with DPP and one lane adds the 10 totals to the record's binary64 gradient.
+template <int TW, int TH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
+                                                        const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ inst_rec, Records rec,
+                                                        SetDev st, const float* __restrict__ T_final,
+                                                        const uint32_t* __restrict__ n_last,
+                                                        const float* __restrict__ d_rgb,
+                                                        const float* __restrict__ d_depth,
+                                                        const float* __restrict__ d_alpha,
+                                                        const float* __restrict__ d_unc, double* __restrict__ g2d,
+                                                        const uint32_t* __restrict__ flags) {
+    constexpr int NB8 = TW * TH / 64;
+    constexpr int PPT = NB8 / NW;
+    constexpr int B = 64 * NW;
+    static_assert(PPT >= 1 && PPT * NW == NB8, "waves must split the 8x8 blocks evenly");
     if (flags && *flags) return;
-    constexpr int B = 64;
     __shared__ float4 s_g0[B], s_g1[B], s_at[B];
     __shared__ float s_u[B];
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
+    __shared__ uint32_t s_max;
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -898,18 +923,24 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const uint2 rg = ranges[tile];
     const uint64_t P = (uint64_t)W * H;
-    const int lane = (int)threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
 
     float px[PPT], py[PPT], T[PPT];
     int ipx[PPT], ipy[PPT];
     uint32_t last[PPT];
     float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
     float S0[PPT], S1[PPT], S2[PPT], S3[PPT], S4[PPT], S5[PPT];
-    uint32_t maxlast = 0;
+    uint32_t mylast = 0;
+    int wc0 = 1 << 30, wc1 = -1, wr0 = 1 << 30, wr1 = -1;  // the wave's pixel rectangle
 #pragma unroll
     for (int j = 0; j < PPT; j++) {
-        // pixel slot j of a lane is the lane's position in the j-th 8x8 block of the tile
-        const int u = tx * TW + (j % (TW / 8)) * 8 + (lane & 7), v = ty * TH + (j / (TW / 8)) * 8 + (lane >> 3);
+        const int blk = wave * PPT + j;
+        const int bx0 = tx * TW + (blk % (TW / 8)) * 8, by0 = ty * TH + (blk / (TW / 8)) * 8;
+        wc0 = min(wc0, bx0);
+        wc1 = max(wc1, bx0 + 7);
+        wr0 = min(wr0, by0);
+        wr1 = max(wr1, by0 + 7);
+        const int u = bx0 + (lane & 7), v = by0 + (lane >> 3);
         px[j] = (float)u;
         py[j] = (float)v;
         ipx[j] = u;
@@ -932,10 +963,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
             if (d_alpha) ga[j] = d_alpha[pix];
             if (d_unc) gu[j] = d_unc[pix];
         }
-        maxlast = max(maxlast, last[j]);
+        mylast = max(mylast, last[j]);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, o, 64));
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (mylast) atomicMax(&s_max, mylast);
+    __syncthreads();
+    const uint32_t maxlast = s_max;
     const float amax = st.alpha_max;
     const float kq = (float)(4.0 / LOG2E);
 
@@ -943,24 +977,25 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDev* __restrict__ v
         const int64_t bstart = bend - B > 0 ? bend - B : 0;
         __syncthreads();
         {
-            const int64_t e = bstart + lane;
+            const int64_t e = bstart + threadIdx.x;
             if (e < bend) {
                 const uint32_t r = inst_rec[rg.x + (uint32_t)e];
-                s_r[lane] = r;
-                s_pb[lane] = rec.pbox[r];
-                s_g0[lane] = rec.geo0[r];
-                s_g1[lane] = rec.geo1[r];
-                s_at[lane] = rec.attr[r];
-                s_u[lane] = rec.unc[r];
+                s_r[threadIdx.x] = r;
+                s_pb[threadIdx.x] = rec.pbox[r];
+                s_g0[threadIdx.x] = rec.geo0[r];
+                s_g1[threadIdx.x] = rec.geo1[r];
+                s_at[threadIdx.x] = rec.attr[r];
+                s_u[threadIdx.x] = rec.unc[r];
             }
         }
         __syncthreads();
         for (int k = (int)(bend - bstart) - 1; k >= 0; k--) {
+            const uint2 pb = s_pb[k];
+            if (!box_meets(pb, wc0, wc1, wr0, wr1)) continue;  // wave-uniform
             const uint32_t pos = (uint32_t)(bstart + k);
             const float4 g0 = s_g0[k], g1 = s_g1[k], at = s_at[k];
             const float ui = s_u[k];
             const uint32_t r = s_r[k];
-            const uint2 pb = s_pb[k];
             float a_mx = 0.0f, a_my = 0.0f, a_qa = 0.0f, a_qb = 0.0f, a_qc = 0.0f, a_o = 0.0f;
             float a_c0 = 0.0f, a_c1 = 0.0f, a_c2 = 0.0f, a_d = 0.0f;
             bool any = false;
@@ -1210,20 +1245,31 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
         for (int c = 0; c < NT / 64; c++) {
             uint64_t mm = m[c];
             while (mm && !done) {
-                const int k = c * 64 + (int)__builtin_ctzll(mm);
-                mm &= mm - 1;
-                if (!in_box(s_pb[k], u, v)) continue;
-                float G, dx, dy, w1, w2;
-                const float4 g0 = s_g0[k], g1 = s_g1[k];
-                float a = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
-                if (!splat_kept(a, g0, g1, rec.q64, s_r[k], px, py, st)) continue;
-                float Tn = T * (1.0f - a);
-                if (Tn < st.T_min) {
-                    done = true;
-                    break;
+                int ks[2];
+                pop2(mm, c * 64, ks[0], ks[1]);
+                float as[2];
+                bool ok[2];
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const int k = ks[q] < 0 ? ks[0] : ks[q];
+                    float G, dx, dy, w1, w2;
+                    const float4 g0 = s_g0[k], g1 = s_g1[k];
+                    as[q] = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
+                    ok[q] = ks[q] >= 0 && in_box(s_pb[k], u, v) &&
+                            splat_kept(as[q], g0, g1, rec.q64, s_r[k], px, py, st);
                 }
-                uu = fmaf(s_u[k], a * T, uu);
-                T = Tn;
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    if (!ok[q] || done) continue;
+                    const float a = as[q];
+                    const float Tn = T * (1.0f - a);
+                    if (Tn < st.T_min) {
+                        done = true;
+                        continue;
+                    }
+                    uu = fmaf(s_u[ks[q]], a * T, uu);
+                    T = Tn;
+                }
             }
         }
     }
@@ -1607,12 +1653,11 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
     int nb = sort_blocks(cap);
     int passes = (nbits + 7) / 8;
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    const int fused = nb <= 128;
     for (int p = 0; p < passes; p++) {
         int shift = 8 * p;
-        k_rs_upsweep<<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, ws.hist);
-        if (nb <= 32) {
-            k_rs_hist_scan<<<1, 1024, 0, s>>>(ws.hist, (uint32_t)(256 * nb));
-        } else {
+        k_rs_upsweep<<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, ws.hist, fused);
+        if (!fused) {
             // table of 256 * nb counts: the multi-block scan, in place
             const uint32_t count = (uint32_t)(256 * nb);
             int sb = scan_blocks(count);
@@ -1622,7 +1667,7 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
             k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, ws.partial + SC_MAX_BLOCKS, count,
                                                   ws.partial);
         }
-        k_rs_scatter<<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, ws.hist);
+        k_rs_scatter<<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, ws.hist, fused);
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
@@ -1663,16 +1708,48 @@ void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, c
     k_sum_partials<<<1, 256, 0, s>>>(partial, (int)(bx * n_views), loss);
 }
 
-void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views,
-                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
-                     const float* T_final, const uint32_t* n_last, const float* d_rgb, const float* d_depth,
-                     const float* d_alpha, const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s) {
+// Waves per tile for the backward: enough workgroups to fill the chip on
+// frames with few tiles, one wave per tile otherwise (RTG_BWD_WAVES overrides).
+static int backward_waves(int tw, int th, uint32_t tiles) {
+    static int forced = -1;
+    if (forced < 0) {
+        const char* e = getenv("RTG_BWD_WAVES");
+        forced = e ? atoi(e) : 0;
+    }
+    const int nb8 = tw * th / 64;
+    int nw = 1;
+    if (forced == 1 || forced == 2 || forced == 4) nw = forced;
+    else {
+        const uint32_t cu = (uint32_t)std::max(device_cu_count(), 1);
+        if (tiles < 16 * cu) nw = 2;
+    }
+    while (nw > nb8) nw >>= 1;
+    return nw;
+}
+
+void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views, uint32_t tiles_total,
+                     const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, const float* T_final,
+                     const uint32_t* n_last, const float* d_rgb, const float* d_depth, const float* d_alpha,
+                     const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s) {
     (void)batch;
     if (tiles_total == 0) return;
-    RTG_TILE_DISPATCH(TW, TH,
-                      (k_render_bwd<TW, TH><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
-                                                                            T_final, n_last, d_rgb, d_depth,
-                                                                            d_alpha, d_unc, g2d, flags)));
+    const int nw = backward_waves(tw, th, tiles_total);
+#define RTG_BWD_LAUNCH(TW_, TH_, NW_)                                                                          \
+    k_render_bwd<TW_, TH_, NW_><<<tiles_total, 64 * NW_, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,      \
+                                                                  T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, \
+                                                                  g2d, flags)
+    if (tw == 8 && th == 8) {
+        RTG_BWD_LAUNCH(8, 8, 1);
+    } else if (tw == 32 && th == 8) {
+        if (nw == 4) RTG_BWD_LAUNCH(32, 8, 4);
+        else if (nw == 2) RTG_BWD_LAUNCH(32, 8, 2);
+        else RTG_BWD_LAUNCH(32, 8, 1);
+    } else {
+        if (nw == 4) RTG_BWD_LAUNCH(16, 16, 4);
+        else if (nw == 2) RTG_BWD_LAUNCH(16, 16, 2);
+        else RTG_BWD_LAUNCH(16, 16, 1);
+    }
+#undef RTG_BWD_LAUNCH
 }
 
 void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
