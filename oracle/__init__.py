@@ -58,9 +58,9 @@ def lib():
         L.rtgo_render.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 3 + [p] +
                                   [ctypes.c_double] * 2 + [p] * 7 + [i64, p, p])
         L.rtgo_render.restype = i64
-        L.rtgo_count.argtypes = [i64] + [p] * 6 + [ctypes.c_int] * 2 + [p, p]
+        L.rtgo_count.argtypes = [i64] + [p] * 6 + [ctypes.c_int] * 3 + [p, p]
         L.rtgo_count.restype = ctypes.c_int
-        L.rtgo_keys.argtypes = [i64] + [p] * 6 + [ctypes.c_int] * 2 + [i64, p, p]
+        L.rtgo_keys.argtypes = [i64] + [p] * 6 + [ctypes.c_int] * 3 + [i64, p, p]
         L.rtgo_keys.restype = ctypes.c_int
         L.rtgo_loss.argtypes = [i64, p, p, p, p, ctypes.c_double, p, p]
         L.rtgo_loss.restype = ctypes.c_double
@@ -171,28 +171,32 @@ def render(scene, cam, settings, mode="tiled", tile=None, roi=None,
             "alt_overflow": int(nalt) > cap}
 
 
-def count(scene, cam, settings, tile=(16, 16)):
+def count(scene, cam, settings, tile=(16, 16), support=False):
+    """(visible Gaussians, binned pairs).  Pairs are every tile a pixel box
+    meets, or with support=True only tiles with a pixel centre where the
+    Gaussian's alpha >= alpha_min."""
     g = _G(scene)
     nv = ctypes.c_int64(); npairs = ctypes.c_int64()
     ca, sa = cam_array(cam), set_array(settings)
-    lib().rtgo_count(g.n, *g.geo(), _ptr(ca), _ptr(sa), int(tile[0]), int(tile[1]),
+    lib().rtgo_count(g.n, *g.geo(), _ptr(ca), _ptr(sa), int(tile[0]), int(tile[1]), int(bool(support)),
                      ctypes.addressof(nv), ctypes.addressof(npairs))
     return int(nv.value), int(npairs.value)
 
 
-def keys(scene, cams, settings, tile=(16, 16)):
+def keys(scene, cams, settings, tile=(16, 16), support=False):
     """Sorted (tile<<32 | depth bits, Gaussian index) pairs over several cameras,
-    global tile ids offset by the tiles of the preceding cameras."""
+    global tile ids offset by the tiles of the preceding cameras; `support` as
+    in count()."""
     g = _G(scene)
     sa = set_array(settings)
     tw, th = int(tile[0]), int(tile[1])
     all_k, all_v = [], []
     base = 0
     for cam in cams:
-        _, npairs = count(scene, cam, settings, tile)
+        _, npairs = count(scene, cam, settings, tile, support)
         k = np.zeros(npairs, np.uint64); v = np.zeros(npairs, np.uint32)
         ca = cam_array(cam)
-        lib().rtgo_keys(g.n, *g.geo(), _ptr(ca), _ptr(sa), tw, th, base, _ptr(k), _ptr(v))
+        lib().rtgo_keys(g.n, *g.geo(), _ptr(ca), _ptr(sa), tw, th, int(bool(support)), base, _ptr(k), _ptr(v))
         all_k.append(k); all_v.append(v)
         base += ((int(cam["width"]) + tw - 1) // tw) * ((int(cam["height"]) + th - 1) // th)
     return np.concatenate(all_k), np.concatenate(all_v)

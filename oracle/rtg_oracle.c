@@ -591,19 +591,53 @@ int64_t rtgo_render(int64_t n, const double *means, const double *ls, const doub
 }
 
 /* Number of visible Gaussians and of (tile, Gaussian) pairs for one camera. */
+/* Whether Gaussian i's support meets tile (tx, ty): some pixel centre of the
+ * tile, inside its pixel box, where alpha >= alpha_min (the skip test of the
+ * compositing loop).  Pixels of other tiles never composite Gaussian i. */
+static int support_meets_tile(const oview *V, int64_t i, int tx, int ty, int tw, int th)
+{
+    const oproj *p = &V->P[i];
+    int ulo = tx * tw > p->u0 ? tx * tw : p->u0, uhi = tx * tw + tw - 1 < p->u1 ? tx * tw + tw - 1 : p->u1;
+    int vlo = ty * th > p->v0 ? ty * th : p->v0, vhi = ty * th + th - 1 < p->v1 ? ty * th + th - 1 : p->v1;
+    for (int v = vlo; v <= vhi; v++)
+        for (int u = ulo; u <= uhi; u++) {
+            double a, G, dx, dy;
+            int cl;
+            alpha_at(V, i, (double)u, (double)v, &a, &G, &cl, &dx, &dy);
+            if (a >= V->s.alpha_min) return 1;
+        }
+    return 0;
+}
+
+/* Tiles Gaussian i is binned to: every tile its pixel box meets, or with
+ * support != 0 only those its support meets. */
+static int64_t tiles_of(const oview *V, int64_t i, int tw, int th, int support, int ntx, int64_t tile_base,
+                        uint64_t *keys, uint32_t *vals, int64_t k)
+{
+    const oproj *p = &V->P[i];
+    for (int ty = p->v0 / th; ty <= p->v1 / th; ty++)
+        for (int tx = p->u0 / tw; tx <= p->u1 / tw; tx++) {
+            if (support && !support_meets_tile(V, i, tx, ty, tw, th)) continue;
+            if (keys) {
+                keys[k] = ((uint64_t)(tile_base + (int64_t)ty * ntx + tx) << 32) | p->dbits;
+                vals[k] = (uint32_t)i;
+            }
+            k++;
+        }
+    return k;
+}
+
 int rtgo_count(int64_t n, const double *means, const double *ls, const double *q,
-               const double *o, const double *cam, const double *set, int tw, int th,
+               const double *o, const double *cam, const double *set, int tw, int th, int support,
                int64_t *nvis, int64_t *npairs)
 {
     ogauss g;
     gauss_from(&g, n, means, ls, q, o, NULL, NULL);
     oview V;
     if (view_setup(&V, &g, cam, set)) return -1;
+    int ntx = (V.c.w + tw - 1) / tw;
     int64_t k = 0;
-    for (int64_t j = 0; j < V.nvis; j++) {
-        const oproj *p = &V.P[V.order[j]];
-        k += (int64_t)(p->u1 / tw - p->u0 / tw + 1) * (p->v1 / th - p->v0 / th + 1);
-    }
+    for (int64_t j = 0; j < V.nvis; j++) k = tiles_of(&V, V.order[j], tw, th, support, ntx, 0, NULL, NULL, k);
     *nvis = V.nvis;
     *npairs = k;
     view_free(&V);
@@ -611,11 +645,12 @@ int rtgo_count(int64_t n, const double *means, const double *ls, const double *q
 }
 
 /* Sorted binning of one camera: for every visible Gaussian i and every tile
- * (tx, ty) its pixel box meets, the pair key ((tile_base + ty*ntx + tx) << 32
- * | depth_bits) with value i, listed in ascending (key, i) order.  The caller
- * sizes keys/vals from rtgo_count. */
+ * (tx, ty) it is binned to (tiles_of), the pair key
+ * ((tile_base + ty*ntx + tx) << 32 | depth_bits) with value i, listed in
+ * ascending (key, i) order: a stable sort by tile of the depth-ordered pairs.
+ * The caller sizes keys/vals from rtgo_count with the same `support`. */
 int rtgo_keys(int64_t n, const double *means, const double *ls, const double *q,
-              const double *o, const double *cam, const double *set, int tw, int th,
+              const double *o, const double *cam, const double *set, int tw, int th, int support,
               int64_t tile_base, uint64_t *keys, uint32_t *vals)
 {
     ogauss g;
@@ -623,21 +658,28 @@ int rtgo_keys(int64_t n, const double *means, const double *ls, const double *q,
     oview V;
     if (view_setup(&V, &g, cam, set)) return -1;
     int ntx = (V.c.w + tw - 1) / tw;
-    /* tile-major, depth order within a tile: emit tile by tile from the
-     * depth-ordered visible list */
-    otiles T;
-    if (tiles_build(&V, tw, th, &T)) return -1;
-    int64_t nt = (int64_t)T.ntx * T.nty;
+    int nty = (V.c.h + th - 1) / th;
+    int64_t nt = (int64_t)ntx * nty;
+    int64_t total = 0;
+    for (int64_t j = 0; j < V.nvis; j++) total = tiles_of(&V, V.order[j], tw, th, support, ntx, 0, NULL, NULL, total);
+    uint64_t *dk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(total > 0 ? total : 1));
+    uint32_t *dv = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(total > 0 ? total : 1));
+    int64_t *start = (int64_t *)calloc((size_t)(nt + 1), sizeof(int64_t));
+    if (!dk || !dv || !start) return -1;
+    /* pairs in depth order, then a counting sort by tile (stable) */
     int64_t k = 0;
-    for (int64_t t = 0; t < nt; t++)
-        for (int64_t j = T.start[t]; j < T.start[t + 1]; j++) {
-            int64_t i = T.items[j];
-            keys[k] = ((uint64_t)(tile_base + t) << 32) | V.P[i].dbits;
-            vals[k] = (uint32_t)i;
-            k++;
-        }
-    (void)ntx;
-    tiles_free(&T);
+    for (int64_t j = 0; j < V.nvis; j++) k = tiles_of(&V, V.order[j], tw, th, support, ntx, 0, dk, dv, k);
+    for (int64_t m = 0; m < total; m++) start[(dk[m] >> 32) + 1]++;
+    for (int64_t t = 0; t < nt; t++) start[t + 1] += start[t];
+    for (int64_t m = 0; m < total; m++) {
+        int64_t t = (int64_t)(dk[m] >> 32);
+        int64_t at = start[t]++;
+        keys[at] = ((uint64_t)(tile_base + t) << 32) | (dk[m] & 0xffffffffu);
+        vals[at] = dv[m];
+    }
+    free(dk);
+    free(dv);
+    free(start);
     view_free(&V);
     return 0;
 }

@@ -339,6 +339,73 @@ def test_events_reported_near_thresholds():
 
 
 # --------------------------------------------------------------------------
+# Support tiles: a tile is binned only if one of its pixel centres has
+# alpha >= alpha_min (the skip test of Sec. III's compositing loop)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ls,tile", [((-2.0, -2.0, -2.0), (16, 16)), ((-1.2, -3.0, -2.0), (8, 8)),
+                                     ((-3.1, -1.4, -2.5), (32, 8))])
+def test_support_tiles_of_axis_aligned_ellipse(ls, tile):
+    # on the optical axis with identity rotation, Sigma_2D = diag((fx sx/z)^2, (fy sy/z)^2):
+    # the support is the axis-aligned ellipse ((u-cx)/ax)^2 + ((v-cy)/ay)^2 <= 2 ln(o/amin),
+    # and the smallest value over a tile's pixel centres is a sum of per-axis minima
+    z, o = 2.5, 0.6
+    c = cam(w=200, h=150, fx=180.0, fy=170.0, cx=97.3, cy=71.8)
+    g = one_gaussian((0, 0, z), ls, opacity=o)
+    ax = 180.0 * math.exp(ls[0]) / z
+    ay = 170.0 * math.exp(ls[1]) / z
+    rho2 = 2.0 * math.log(F32(o) / AMIN)
+    tw, th = tile
+    ntx, nty = -(-200 // tw), -(-150 // th)
+    expect = []
+    for ty in range(nty):
+        vs = np.arange(ty * th, min(ty * th + th, 150))
+        my = np.min(((vs - 71.8) / ay) ** 2)
+        for tx in range(ntx):
+            us = np.arange(tx * tw, min(tx * tw + tw, 200))
+            mx = np.min(((us - 97.3) / ax) ** 2)
+            assert abs(mx + my - rho2) > 1e-6  # no tile on the boundary
+            if mx + my <= rho2:
+                expect.append(ty * ntx + tx)
+    k, v = oracle.keys(g, [c], S(), tile, support=True)
+    assert np.array_equal((k >> np.uint64(32)).astype(np.int64), np.array(expect, np.int64))
+    kb, _ = oracle.keys(g, [c], S(), tile)
+    # the pixel box tiles hold the support tiles
+    assert len(kb) >= len(k) and set((kb >> np.uint64(32)).tolist()) >= set(expect)
+    assert oracle.count(g, c, S(), tile, support=True)[1] == len(expect)
+
+
+def test_support_keys_are_the_box_keys_restricted():
+    g, cams = scenes.config1(n=600)
+    idx = np.concatenate([np.arange(600), np.arange(0, 600, 31)])
+    g = scenes.subset(g, idx)
+    for tile in ((16, 16), (8, 8), (32, 8)):
+        kb, vb = oracle.keys(g, cams, S(), tile)
+        ks, vs = oracle.keys(g, cams, S(), tile, support=True)
+        box = (kb >> np.uint64(32)) << np.uint64(32) | vb.astype(np.uint64)
+        sup = (ks >> np.uint64(32)) << np.uint64(32) | vs.astype(np.uint64)
+        keep = np.isin(box, sup)
+        # same order: the support pairs are a subsequence of the box pairs
+        assert keep.sum() == len(ks) and len(ks) < len(kb)
+        assert np.array_equal(kb[keep], ks) and np.array_equal(vb[keep], vs)
+        # rendering from support tiles only is what the tiled render gives:
+        # every pixel that composites Gaussian i lies in one of i's support tiles
+        r = oracle.render(g, cams[0], S(), tile=tile)
+        p = oracle.project(g, cams[0], S())
+        tw, th = tile
+        ntx = -(-cams[0]["width"] // tw)
+        pairs = set(sup.tolist())
+        rng = np.random.default_rng(1)
+        for i in rng.choice(np.nonzero(p["valid"])[0], 40, replace=False):
+            u0, u1, v0, v1 = p["box"][:, i]
+            solo = oracle.render(scenes.subset(g, [i]), cams[0], S(), mode="brute")
+            ys, xs = np.nonzero(solo["alpha"] > 0)
+            for y, x in zip(ys, xs):
+                assert ((y // th) * ntx + x // tw) << 32 | int(i) in pairs
+        assert r["alpha"].max() > 0
+
+
+# --------------------------------------------------------------------------
 # Sorted binning keys: (tile << 32 | binary32 depth bits), ties by index
 # --------------------------------------------------------------------------
 
