@@ -124,7 +124,12 @@ rtg_status rtg_project(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *c
 /* Depth ordering and tile binning (Sec. III: "sorted in increasing order of
  * depth relative to the camera").  Builds, for every screen tile of every
  * view, the list of Gaussians whose support meets it, in ascending binary32
- * camera depth, ties by Gaussian index.  *n_instances (host, nullable)
+ * camera depth, ties by Gaussian index.  A Gaussian is listed in a tile when
+ * its support ellipse {alpha >= alpha_min} reaches the tile's pixel-centre
+ * columns on one of the tile's pixel rows inside its pixel box, by a
+ * conservative binary32 test (every pixel that composites it is kept): a
+ * subset of the tiles its pixel box meets, and at least one tile per visible
+ * Gaussian.  *n_instances (host, nullable)
  * receives the number of (tile, Gaussian) pairs.  Synchronises `stream`
  * once (to size the pair buffers). */
 rtg_status rtg_bin_sort(rtg_ctx *ctx, rtg_frame *f, int64_t *n_instances, void *stream);

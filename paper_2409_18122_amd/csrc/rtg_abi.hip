@@ -286,7 +286,9 @@ rtg_status resolve_settings(rtg_ctx* ctx, const rtg_settings* in, rtg_settings* 
     return RTG_OK;
 }
 
-SetDev to_dev(const rtg_settings& s) { return SetDev{s.T_min, s.alpha_min, s.alpha_max, s.z_near, s.eps2d}; }
+SetDev to_dev(const rtg_settings& s) {
+    return SetDev{s.T_min, s.alpha_min, s.alpha_max, s.z_near, s.eps2d, (float)std::log2((double)s.alpha_min)};
+}
 
 GaussDev to_dev(const rtg_gaussians& g) {
     return GaussDev{g.n, g.means, g.log_scales, g.quats, g.opacity, g.colors, g.uncert};
@@ -488,7 +490,8 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
     const uint32_t kc = std::max<uint32_t>(f->inst_cap, 1);
     Timer tm(f->ctx, 2, s);
     emit_instances(f->sorted_order(), f->ctr(C_REC), rc, f->ctr(C_INST), f->records(), f->views.as<ViewDev>(),
-                   f->inst_off.as<uint32_t>(), f->inst_cap, f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(),
+                   f->inst_off.as<uint32_t>(), f->st.tile_w, f->st.tile_h, to_dev(f->st), f->inst_cap,
+                   f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(),
                    f->ctr(C_FLAGS), s);
     int tbits = bits_for(std::max<uint32_t>(f->tiles_cap, 2));
     f->inst_in_alt = radix_sort(f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(), f->tkey2.as<uint32_t>(),

@@ -29,6 +29,7 @@ struct Header {
 
 struct SetDev {
     float T_min, alpha_min, alpha_max, z_near, eps2d;
+    float log2_amin;  // log2(alpha_min)
 };
 
 struct GaussDev {
@@ -72,6 +73,8 @@ constexpr int MAX_VIEWS = 1024;
 // Status bits written by kernels into a device word.
 constexpr uint32_t FLAG_REC_OVERFLOW = 1u;
 constexpr uint32_t FLAG_INST_OVERFLOW = 2u;
+// Pair emission found fewer support tiles than were counted (never expected).
+constexpr uint32_t FLAG_BIN_MISMATCH = 4u;
 
 // ---------------------------------------------------------------- launchers
 // All take device pointers and enqueue on `s`.  n_dev arguments are device
@@ -110,9 +113,11 @@ int sort_blocks(uint64_t cap);
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
                uint32_t cap, int nbits, SortWs ws, hipStream_t s);
 
-// Instances of the depth-ordered records: tile keys and record ids.
+// Instances of the depth-ordered records: tile keys and record ids, one per
+// tile a record's support meets (tiles tw x th).
 void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, const uint32_t* K_dev,
-                    Records rec, const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap,
+                    Records rec, const ViewDev* views, const uint32_t* inst_off, int tw, int th, SetDev st,
+                    uint32_t inst_cap,
                     uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s);
 // ranges[t] = [start, end) over the tile-sorted keys; ranges pre-zeroed here.
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap,

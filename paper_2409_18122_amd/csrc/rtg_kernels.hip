@@ -180,6 +180,128 @@ __device__ inline bool project_exact(const GPre& P, const ViewDev& V, const SetD
     return true;
 }
 
+
+// ------------------------------------------------------- support extents
+// A splat's support {alpha >= alpha_min} in the whitened form is
+// w1^2 + w2^2 <= log2(o / alpha_min) with w1 = a dx, w2 = b dx + c dy
+// (geo1 = (a, b, c, o), d = pixel - mean): the ellipse with
+// Q = [[a^2 + b^2, b c], [b c, c^2]], det Q = (a c)^2.  On a horizontal
+// slice at offset dy it spans dx = (-B dy +/- sqrt(A l - D dy^2)) / A
+// (A = a^2 + b^2, B = b c, D = det Q).  The right end is concave in dy with
+// its maximum at dy_r = -(b / (a c)) sqrt(l), the left end convex with its
+// minimum at -dy_r, so the x extent over a band of rows is the two slices at
+// the offsets clamped into the band.
+//
+// The test is conservative in binary32: l exceeds log2(o / alpha_min) by the
+// binary64 refinement band of the alpha_min test, by the binary32 rounding of
+// a pixel's own exponent (which grows with |b dx| + c |dy|, bounded here
+// through X and Y, the largest |dx| and |dy| in question) and by a relative
+// 1e-4; the extents are widened by a relative 1e-3 plus 1e-3 pixel.
+// Returns false if the rows [r0, r1] miss the support.
+__device__ __forceinline__ bool support_span(float4 g0, float4 g1, float log2_amin, float X, int r0, int r1,
+                                             float& xl, float& xr) {
+    const float a = g1.x, b = g1.y, c = g1.z;
+    const float mx = g0.x + g0.z, my = g0.y + g0.w;
+    const float dy0 = (float)r0 - my, dy1 = (float)r1 - my;
+    const float Y = fmaxf(fabsf(dy0), fabsf(dy1));
+    const float l = (__builtin_amdgcn_logf(g1.w) - log2_amin) * 1.0001f + 0.004f + 4e-7f * fmaf(fabsf(b), X, c * Y);
+    const float A = fmaf(a, a, b * b);
+    const float ac = a * c;
+    if (!(A > 0.0f) || !(ac > 0.0f) || !(l > 0.0f) || !(A < 3e38f)) {  // not expected: no culling
+        xl = -3e38f;
+        xr = 3e38f;
+        return true;
+    }
+    const float D = ac * ac;
+    const float B = b * c;
+    const float dyr = -b * __builtin_amdgcn_rcpf(ac) * __builtin_amdgcn_sqrtf(l);
+    const float yr = fminf(fmaxf(dyr, dy0), dy1);
+    const float yl = fminf(fmaxf(-dyr, dy0), dy1);
+    const float Al = A * l;
+    const float dr = fmaf(-D * yr, yr, Al);
+    const float dl = fmaf(-D * yl, yl, Al);
+    if (dr < -1e-4f * Al) return false;
+    const float ia = __builtin_amdgcn_rcpf(A);
+    const float R = (__builtin_amdgcn_sqrtf(fmaxf(dr, 0.0f)) - B * yr) * ia;
+    const float L = (-__builtin_amdgcn_sqrtf(fmaxf(dl, 0.0f)) - B * yl) * ia;
+    const float mg = 1e-3f * (fabsf(R) + fabsf(L)) + 1e-3f;
+    xl = mx + L - mg;
+    xr = mx + R + mg;
+    return true;
+}
+
+// Whether a splat's support can reach a pixel of the rectangle [c0, c1] x
+// [r0, r1] (a prefilter; the per-pixel tests decide).
+__device__ __forceinline__ bool support_meets_rect(float4 g0, float4 g1, float log2_amin, int c0, int c1, int r0,
+                                                   int r1) {
+    const float mx = g0.x + g0.z;
+    const float X = fmaxf(fabsf((float)c0 - mx), fabsf((float)c1 - mx));
+    float xl, xr;
+    if (!support_span(g0, g1, log2_amin, X, r0, r1, xl, xr)) return false;
+    return xl <= (float)c1 && xr >= (float)c0;
+}
+
+// Per-record constants of the support rows: on a slice at offset dy the
+// ellipse spans [-sqrt(P - Qc dy^2) - Bc dy, sqrt(P - Qc dy^2) - Bc dy]
+// (P = l / A, Qc = D / A^2, Bc = B / A in the notation of support_span), l
+// taken with X and Y bounding |dx| and |dy| over the whole pixel box.
+struct SupportRows {
+    float mx, my, dyr, P, Qc, Bc;
+    uint32_t pb_x, pb_y;  // pixel box
+    int all;              // 1: no culling (degenerate form, not expected)
+};
+
+// Pair counting and pair emission both call support_setup and support_row,
+// two non-inlined functions, on the same stored record values (geo0, geo1,
+// pixel box), so they agree exactly.
+__device__ __noinline__ SupportRows support_setup(float4 g0, float4 g1, uint2 pb, float log2_amin) {
+    SupportRows S;
+    const float a = g1.x, b = g1.y, c = g1.z;
+    S.mx = g0.x + g0.z;
+    S.my = g0.y + g0.w;
+    S.pb_x = pb.x;
+    S.pb_y = pb.y;
+    const float u0 = (float)(pb.x & 0xffffu), u1 = (float)(pb.x >> 16);
+    const float v0 = (float)(pb.y & 0xffffu), v1 = (float)(pb.y >> 16);
+    const float X = fmaxf(fabsf(u0 - S.mx), fabsf(u1 - S.mx));
+    const float Y = fmaxf(fabsf(v0 - S.my), fabsf(v1 - S.my));
+    const float l = (__builtin_amdgcn_logf(g1.w) - log2_amin) * 1.0001f + 0.004f + 4e-7f * fmaf(fabsf(b), X, c * Y);
+    const float A = fmaf(a, a, b * b);
+    const float ac = a * c;
+    S.all = !(A > 0.0f) || !(ac > 0.0f) || !(l > 0.0f) || !(A < 3e38f);
+    const float ia = __builtin_amdgcn_rcpf(A);
+    S.dyr = -b * __builtin_amdgcn_rcpf(ac) * __builtin_amdgcn_sqrtf(l);
+    S.P = l * ia;
+    S.Qc = (ac * ia) * (ac * ia);
+    S.Bc = (b * c) * ia;
+    return S;
+}
+
+// Tiles of tile row ty (tiles 2^tws x 2^ths) that a record's support meets
+// inside its pixel box, as (first column, count).
+__device__ __noinline__ uint2 support_row(SupportRows S, uint32_t ty, int tws, int ths) {
+    const int u0 = (int)(S.pb_x & 0xffffu), u1 = (int)(S.pb_x >> 16);
+    const int v0 = (int)(S.pb_y & 0xffffu), v1 = (int)(S.pb_y >> 16);
+    const int y0 = max((int)(ty << ths), v0), y1 = min((int)((ty + 1) << ths) - 1, v1);
+    const uint32_t f0 = (uint32_t)u0 >> tws;
+    if (y0 > y1) return make_uint2(f0, 0u);
+    if (S.all) return make_uint2(f0, ((uint32_t)u1 >> tws) - f0 + 1);
+    const float dy0 = (float)y0 - S.my, dy1 = (float)y1 - S.my;
+    const float yr = fminf(fmaxf(S.dyr, dy0), dy1);
+    const float yl = fminf(fmaxf(-S.dyr, dy0), dy1);
+    const float er = fmaf(-S.Qc * yr, yr, S.P);
+    const float el = fmaf(-S.Qc * yl, yl, S.P);
+    if (er < -1e-4f * S.P) return make_uint2(f0, 0u);  // the rows miss the support
+    const float R = __builtin_amdgcn_sqrtf(fmaxf(er, 0.0f)) - S.Bc * yr;
+    const float L = -__builtin_amdgcn_sqrtf(fmaxf(el, 0.0f)) - S.Bc * yl;
+    const float mg = 1e-3f * (fabsf(R) + fabsf(L)) + 1e-3f;
+    const float cl = fmaxf(ceilf(S.mx + L - mg), (float)u0);
+    const float cr = fminf(floorf(S.mx + R + mg), (float)u1);
+    if (!(cl <= cr)) return make_uint2(f0, 0u);
+    const uint32_t first = (uint32_t)cl >> tws;
+    return make_uint2(first, ((uint32_t)cr >> tws) - first + 1);
+}
+
 __global__ __launch_bounds__(256) void k_project_count(GaussDev g, const ViewDev* __restrict__ views,
                                                        const Header* __restrict__ hdr, int words,
                                                        SetDev st, uint32_t* __restrict__ cnt,
@@ -212,7 +334,7 @@ __global__ __launch_bounds__(256) void k_project_count(GaussDev g, const ViewDev
 }
 
 __global__ __launch_bounds__(256) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
-                                                      int words, SetDev st, int tw, int th,
+                                                      int words, SetDev st, int tws, int ths,
                                                       const uint32_t* __restrict__ mask,
                                                       const uint32_t* __restrict__ rec_off,
                                                       uint32_t rec_cap, Records rec,
@@ -243,16 +365,17 @@ __global__ __launch_bounds__(256) void k_project_emit(GaussDev g, const ViewDev*
                 return;
             }
             float mxh = (float)q.mx, myh = (float)q.my;
-            rec.geo0[pos] = make_float4(mxh, myh, (float)(q.mx - (double)mxh),
-                                        (float)(q.my - (double)myh));
+            const float4 g0 = make_float4(mxh, myh, (float)(q.mx - (double)mxh), (float)(q.my - (double)myh));
+            rec.geo0[pos] = g0;
             double det = q.cxx * q.cyy - q.cxy * q.cxy;
             // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
             double c00 = sqrt(q.cxx);
             double c10 = q.cxy / c00;
             double c11 = sqrt(det / q.cxx);
             double sl = sqrt(0.5 * LOG2E);
-            rec.geo1[pos] = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
-                                        (float)P.o);
+            const float4 g1 = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
+                                          (float)P.o);
+            rec.geo1[pos] = g1;
             rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
             float depth = (float)q.t[2];
             if (g.colors)
@@ -262,13 +385,20 @@ __global__ __launch_bounds__(256) void k_project_emit(GaussDev g, const ViewDev*
             rec.unc[pos] = g.uncert ? g.uncert[i] : 0.0f;
             rec.gid[pos] = (uint32_t)i;
             rec.view[pos] = (uint32_t)v;
-            uint32_t tx0 = (uint32_t)(q.u0 / tw), tx1 = (uint32_t)(q.u1 / tw);
-            uint32_t ty0 = (uint32_t)(q.v0 / th), ty1 = (uint32_t)(q.v1 / th);
+            uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
+            uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
             rec.rect[pos] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-            rec.pbox[pos] = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16), (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
+            const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
+                                        (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
+            rec.pbox[pos] = pb;
             rec.dkey[pos] = __float_as_uint(depth);
             sortkey[pos] = __float_as_uint(depth);
-            rec.ntiles[pos] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            // pairs: the tiles the support meets (a subset of the box's
+            // tiles); at least one, so that every record owns a pair
+            uint32_t nt = 0;
+            const SupportRows S = support_setup(g0, g1, pb, st.log2_amin);
+            for (uint32_t ty = ty0; ty <= ty1; ty++) nt += support_row(S, ty, tws, ths).y;
+            rec.ntiles[pos] = max(nt, 1u);
             order[pos] = pos;
             pos++;
         }
@@ -539,13 +669,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
 
 // ---------------------------------------------------------------- binning
 
-// One thread per (tile, splat) pair.  A block covers EM_ITEMS consecutive
-// pairs; the depth-ordered records spanning them are found by one binary
-// search over the pair offsets, their offsets staged in LDS, and each thread
-// locates its record there.  Pairs of one record are its tile rectangle in
-// row-major order, so output is written in depth order with coalesced stores.
+// A block covers EM_ITEMS consecutive pairs and each thread EM_RUN
+// consecutive ones.  The depth-ordered records spanning the block are found
+// by one binary search over the pair offsets and their offsets staged in LDS;
+// a thread locates its first record there, positions a cursor on its first
+// pair (rows are walked once) and advances it pair by pair.  A record whose
+// support meets every tile of its box is enumerated in row-major order
+// directly.  Output is written in depth order, EM_RUN pairs per 16-byte store.
 constexpr int EM_THREADS = 256;
-constexpr int EM_ITEMS = EM_THREADS * 4;
+constexpr int EM_RUN = 4;
+constexpr int EM_ITEMS = EM_THREADS * EM_RUN;
 
 __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint32_t x) {
     // largest i < n with a[i] <= x (a[0] == 0 <= x)
@@ -558,11 +691,81 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint3
     return lo;
 }
 
+// Position within one record's pairs.
+struct PairCursor {
+    uint32_t r, tile_off, tiles_x, tx0, nx, ty0, ty1;
+    bool full;       // every tile of the box
+    SupportRows S;   // when !full
+    uint32_t li;     // pair index within the record (full)
+    uint32_t ty, first, cnt, rem;  // current support row (!full)
+};
+
+// Next row with a nonzero count at or after c.ty; false if none is left.
+__device__ __forceinline__ bool cursor_row(PairCursor& c, int tws, int ths) {
+    for (; c.ty <= c.ty1; c.ty++) {
+        const uint2 fc = support_row(c.S, c.ty, tws, ths);
+        if (fc.y) {
+            c.first = fc.x;
+            c.cnt = fc.y;
+            return true;
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ void cursor_open(PairCursor& c, const Records& rec, const ViewDev* views, uint32_t r,
+                                            uint32_t li, int tws, int ths, float log2_amin, uint32_t* flags) {
+    c.r = r;
+    const uint2 rc = rec.rect[r];
+    c.tx0 = rc.x & 0xffffu;
+    c.nx = (rc.x >> 16) - c.tx0 + 1;
+    c.ty0 = rc.y & 0xffffu;
+    c.ty1 = rc.y >> 16;
+    const ViewDev& V = views[rec.view[r]];
+    c.tile_off = V.tile_off;
+    c.tiles_x = (uint32_t)V.tiles_x;
+    c.full = rec.ntiles[r] == c.nx * (c.ty1 - c.ty0 + 1);
+    c.li = li;
+    if (c.full) return;
+    c.S = support_setup(rec.geo0[r], rec.geo1[r], rec.pbox[r], log2_amin);
+    c.ty = c.ty0;
+    uint32_t rem = li;
+    while (cursor_row(c, tws, ths)) {
+        if (rem < c.cnt) {
+            c.rem = rem;
+            return;
+        }
+        rem -= c.cnt;
+        c.ty++;
+    }
+    // a support that meets no tile still owns one pair, its box's first tile;
+    // anything else would be a counting mismatch
+    if (li != 0) atomicOr(flags, FLAG_BIN_MISMATCH);
+    c.full = true;
+    c.nx = 1;
+    c.li = 0;
+}
+
+__device__ __forceinline__ uint32_t cursor_tile(const PairCursor& c) {
+    if (c.full) return c.tile_off + (c.ty0 + c.li / c.nx) * c.tiles_x + c.tx0 + c.li % c.nx;
+    return c.tile_off + c.ty * c.tiles_x + c.first + c.rem;
+}
+
+__device__ __forceinline__ void cursor_next(PairCursor& c, int tws, int ths) {
+    c.li++;
+    if (c.full) return;
+    if (++c.rem < c.cnt) return;
+    c.rem = 0;
+    c.ty++;
+    cursor_row(c, tws, ths);  // the caller knows the record has another pair
+}
+
 __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* __restrict__ order,
                                                                const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
                                                                const uint32_t* __restrict__ K_dev, Records rec,
                                                                const ViewDev* __restrict__ views,
                                                                const uint32_t* __restrict__ inst_off,
+                                                               int tws, int ths, float log2_amin,
                                                                uint32_t inst_cap, uint32_t* __restrict__ tile_key,
                                                                uint32_t* __restrict__ inst_rec,
                                                                uint32_t* __restrict__ flags) {
@@ -578,6 +781,8 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
         const uint32_t k1 = min(k0 + EM_ITEMS, K);  // exclusive
         __syncthreads();
         if (threadIdx.x == 0) {
+            // every record owns at least one pair, so at most EM_ITEMS records
+            // span the block's pairs
             const uint32_t lo = last_le(inst_off, R, k0);
             const uint32_t hi = last_le(inst_off, R, k1 - 1);
             s_lo = lo;
@@ -587,17 +792,35 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
         const uint32_t lo = s_lo, nrec = s_n;
         for (uint32_t i = threadIdx.x; i < nrec; i += EM_THREADS) s_off[i] = inst_off[lo + i];
         __syncthreads();
-        for (uint32_t k = k0 + threadIdx.x; k < k1; k += EM_THREADS) {
-            const uint32_t j = last_le(s_off, nrec, k);
-            const uint32_t i = lo + j;
-            const uint32_t r = order[i];
-            const uint2 rc = rec.rect[r];
-            const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
-            const uint32_t nx = tx1 - tx0 + 1;
-            const uint32_t li = k - s_off[j];
-            const ViewDev& V = views[rec.view[r]];
-            tile_key[k] = V.tile_off + (ty0 + li / nx) * (uint32_t)V.tiles_x + tx0 + li % nx;
-            inst_rec[k] = r;
+        const uint32_t kb = k0 + threadIdx.x * EM_RUN;
+        if (kb >= k1) continue;
+        uint32_t j = last_le(s_off, nrec, kb);
+        PairCursor c;
+        cursor_open(c, rec, views, order[lo + j], kb - s_off[j], tws, ths, log2_amin, flags);
+        uint32_t tk[EM_RUN], tr[EM_RUN];
+        const int n = (int)min<uint32_t>(EM_RUN, k1 - kb);
+#pragma unroll
+        for (int q = 0; q < EM_RUN; q++) {
+            if (q >= n) break;
+            if (q > 0) {
+                if (j + 1 < nrec && kb + q >= s_off[j + 1]) {
+                    j++;
+                    cursor_open(c, rec, views, order[lo + j], 0, tws, ths, log2_amin, flags);
+                } else {
+                    cursor_next(c, tws, ths);
+                }
+            }
+            tk[q] = cursor_tile(c);
+            tr[q] = c.r;
+        }
+        if (n == EM_RUN) {
+            *reinterpret_cast<uint4*>(tile_key + kb) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+            *reinterpret_cast<uint4*>(inst_rec + kb) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
+        } else {
+            for (int q = 0; q < n; q++) {
+                tile_key[kb + q] = tk[q];
+                inst_rec[kb + q] = tr[q];
+            }
         }
     }
 }
@@ -659,20 +882,28 @@ __device__ __forceinline__ bool box_meets(uint2 b, int c0, int c1, int r0, int r
            (int)(b.y >> 16) >= r0;
 }
 
-// For a staged batch of `cnt` splats, bit k of m[k / 64] is set when splat k's
-// support box meets the calling wave's pixel rectangle (wave-uniform result).
-template <int NT>
-__device__ __forceinline__ void wave_masks(const uint2* s_pb, int cnt, int c0, int c1, int r0, int r1,
+
+// Where the support-ellipse prefilter runs.  It pays in scoring (many
+// elongated splats seen close up from arbitrary poses); on mapping frames
+// the box test alone is faster in the forward and backward passes.
+constexpr bool FWD_ELL = false, BWD_ELL = false, SCORE_ELL = true;
+
+// For a staged batch of `cnt` splats, bit k of m[k / 64] is set when splat k
+// can reach the calling wave's pixel rectangle (wave-uniform result): its box
+// meets the rectangle and, with ELL, so does its support ellipse.
+template <int NT, bool ELL>
+__device__ __forceinline__ void wave_masks(const uint2* s_pb, const float4* s_g0, const float4* s_g1,
+                                           float log2_amin, int cnt, int c0, int c1, int r0, int r1,
                                            uint64_t (&m)[NT / 64]) {
     const int lane = (int)lane_id();
 #pragma unroll
     for (int c = 0; c < NT / 64; c++) {
         const int e = c * 64 + lane;
-        const bool hit = e < cnt && box_meets(s_pb[e], c0, c1, r0, r1);
+        bool hit = e < cnt && box_meets(s_pb[e], c0, c1, r0, r1);
+        if (ELL && hit) hit = support_meets_rect(s_g0[e], s_g1[e], log2_amin, c0, c1, r0, r1);
         m[c] = __ballot(hit);
     }
 }
-
 // Next two set bits of a wave-uniform mask (k1 < 0 if only one is left).
 __device__ __forceinline__ void pop2(uint64_t& mm, int base, int& k0, int& k1) {
     k0 = base + (int)__builtin_ctzll(mm);
@@ -746,8 +977,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(NT, rg.y - b);
-        uint64_t m[NT / 64];
-        wave_masks<NT>(s_pb, cnt, wc0, wc1, wr0, wr1, m);
+        uint64_t m[NT / 64] = {};
+        if (__ballot(!done)) wave_masks<NT, FWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
 #pragma unroll
         for (int c = 0; c < NT / 64; c++) {
             uint64_t mm = m[c];
@@ -890,8 +1121,8 @@ __device__ __forceinline__ float wave_sum_dpp(float x) {
 
 // NW waves per tile; the tile's 8x8 pixel blocks are dealt to the waves in
 // row-major order (PPT blocks each) and a lane owns one pixel per block.
-// Splats are staged per batch for the whole workgroup; a wave skips a splat
-// whose support box misses all of its blocks (a wave-uniform test).  Per
+// Splats are staged per batch for the whole workgroup; a wave visits only
+// the splats whose support can reach its blocks (ballot masks per batch).  Per
 // splat, the lane sums its pixels' contributions, the wave reduces them once
 // with DPP and one lane adds the 10 totals to the record's binary64 gradient.
 template <int TW, int TH, int NW>
@@ -970,6 +1201,9 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
     if (mylast) atomicMax(&s_max, mylast);
     __syncthreads();
     const uint32_t maxlast = s_max;
+    uint32_t wave_last = mylast;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     const float amax = st.alpha_max;
     const float kq = (float)(4.0 / LOG2E);
 
@@ -989,9 +1223,22 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
             }
         }
         __syncthreads();
-        for (int k = (int)(bend - bstart) - 1; k >= 0; k--) {
+        uint64_t m[NW];
+        // splats at or past every lane's last contributor cannot matter
+        const int cnt = (int)(min<int64_t>(bend, (int64_t)wave_last) - bstart);
+        wave_masks<B, BWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
+        // back to front over the splats that can reach this wave's pixels
+        for (int k = B - 1; k >= 0; k--) {
+            {
+                const int c = k >> 6;
+                const uint64_t below = m[c] & (~0ull >> (63 - (k & 63)));  // bits 0 .. k % 64
+                if (!below) {
+                    k = c * 64;  // nothing left in this chunk
+                    continue;
+                }
+                k = c * 64 + 63 - (int)__builtin_clzll(below);
+            }
             const uint2 pb = s_pb[k];
-            if (!box_meets(pb, wc0, wc1, wr0, wr1)) continue;  // wave-uniform
             const uint32_t pos = (uint32_t)(bstart + k);
             const float4 g0 = s_g0[k], g1 = s_g1[k], at = s_at[k];
             const float ui = s_u[k];
@@ -1239,8 +1486,8 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(NT, rg.y - b);
-        uint64_t m[NT / 64];
-        wave_masks<NT>(s_pb, cnt, wc0, wc1, wr0, wr1, m);
+        uint64_t m[NT / 64] = {};
+        if (__ballot(!done)) wave_masks<NT, SCORE_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
 #pragma unroll
         for (int c = 0; c < NT / 64; c++) {
             uint64_t mm = m[c];
@@ -1616,14 +1863,21 @@ void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, i
     k_project_count<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
 }
 
+// log2 of a power-of-two tile side (8, 16 or 32)
+static int ilog2(int x) {
+    int k = 0;
+    while ((1 << (k + 1)) <= x) k++;
+    return k;
+}
+
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap, SetDev st,
                   int tw, int th, const uint32_t* mask, const uint32_t* rec_off, uint32_t rec_cap, Records rec,
                   uint32_t* sortkey, uint32_t* order, uint32_t* flags, hipStream_t s) {
     (void)hdr;
     if (g.n == 0) return;
     int words = (n_views_cap + 31) / 32;
-    k_project_emit<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, words, st, tw, th, mask, rec_off, rec_cap, rec,
-                                                      sortkey, order, flags);
+    k_project_emit<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, words, st, ilog2(tw), ilog2(th), mask, rec_off,
+                                                      rec_cap, rec, sortkey, order, flags);
 }
 
 int scan_blocks(uint64_t cap) {
@@ -1675,11 +1929,11 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
 }
 
 void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, const uint32_t* K_dev,
-                    Records rec, const ViewDev* views, const uint32_t* inst_off, uint32_t inst_cap,
-                    uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s) {
+                    Records rec, const ViewDev* views, const uint32_t* inst_off, int tw, int th, SetDev st,
+                    uint32_t inst_cap, uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s) {
     unsigned grid = grid_for(std::max<uint32_t>(inst_cap, 1), EM_ITEMS, 16384);
-    k_emit_instances<<<grid, EM_THREADS, 0, s>>>(order, R_dev, rec_cap, K_dev, rec, views, inst_off, inst_cap,
-                                                 tile_key, inst_rec, flags);
+    k_emit_instances<<<grid, EM_THREADS, 0, s>>>(order, R_dev, rec_cap, K_dev, rec, views, inst_off, ilog2(tw),
+                                                 ilog2(th), st.log2_amin, inst_cap, tile_key, inst_rec, flags);
 }
 
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap, uint2* ranges,
