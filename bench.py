@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (21086.5 * 2.0 * 1024 + 87564.1 * 1024,
-                        "65b4d30117ad8de57cd7148f54def61f957c2e0e3251227a4452e57569009cfb"),
-    "render": (18496.7 * 2.0 * 1024 + 8400.0 * 1024,
-               "65b4d30117ad8de57cd7148f54def61f957c2e0e3251227a4452e57569009cfb"),
+    "render_backward": (20483.0 * 2.0 * 1024 + 87564.1 * 1024,
+                        "b5243d0e3843fce070f07eb3094553f4325a580b8e24a63371740eb755a977ec"),
+    "render": (20563.4 * 2.0 * 1024 + 8400.0 * 1024,
+               "b5243d0e3843fce070f07eb3094553f4325a580b8e24a63371740eb755a977ec"),
 }
 
 
