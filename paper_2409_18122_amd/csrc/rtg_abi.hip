@@ -431,7 +431,7 @@ rtg_status alloc_instances(rtg_frame* f, uint32_t kc, uint32_t tiles_cap) {
     RTG_TRY(f->irec2.ensure(ctx, 4 * k));
     RTG_TRY(f->ranges.ensure(ctx, 8 * (size_t)std::max<uint32_t>(tiles_cap, 1)));
     uint64_t big = std::max<uint64_t>(std::max<uint64_t>(kc, f->rec_cap), 1);
-    RTG_TRY(f->sort_hist.ensure(ctx, sizeof(uint32_t) * 256 * (size_t)sort_blocks(big)));
+    RTG_TRY(f->sort_hist.ensure(ctx, sizeof(uint32_t) * sort_hist_words(big)));
     f->inst_cap = kc;
     f->tiles_cap = tiles_cap;
     return RTG_OK;
@@ -464,18 +464,24 @@ rtg_status enqueue_project(rtg_frame* f, bool eager, hipStream_t s) {
     return check_launch("projection emit");
 }
 
+// Digit widths of the two sorts (measured): the 32-bit depth keys in 4 passes
+// of 8 bits; tile keys (ceil(log2 tiles) bits) in passes of up to 11 bits,
+// one pass up to 2048 tiles.
+constexpr int DEPTH_SORT_DIGIT = 8;
+constexpr int TILE_SORT_DIGIT = 11;
+
 rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
     const uint32_t rc = std::max<uint32_t>(f->rec_cap, 1);
     SortWs ws{f->sort_hist.as<uint32_t>(), f->scan_ws.as<uint32_t>()};
     if (eager) {
         // the histogram table must fit the larger of the two sorts; size it for the records now
-        RTG_TRY(f->sort_hist.ensure(f->ctx, sizeof(uint32_t) * 256 * (size_t)sort_blocks(rc)));
+        RTG_TRY(f->sort_hist.ensure(f->ctx, sizeof(uint32_t) * sort_hist_words(rc)));
         ws.hist = f->sort_hist.as<uint32_t>();
     }
     {
         Timer tm(f->ctx, 1, s);
         f->order_in_alt = radix_sort(f->skey.as<uint32_t>(), f->order.as<uint32_t>(), f->skey2.as<uint32_t>(),
-                                     f->order2.as<uint32_t>(), f->ctr(C_REC), rc, 32, ws, s);
+                                     f->order2.as<uint32_t>(), f->ctr(C_REC), rc, 32, DEPTH_SORT_DIGIT, ws, s);
     }
     scan_u32(f->ntiles.as<uint32_t>(), f->sorted_order(), f->inst_off.as<uint32_t>(), f->ctr(C_REC), rc,
              f->ctr(C_INST), ScanWs{f->scan_ws.as<uint32_t>()}, s);
@@ -495,7 +501,7 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
                    f->ctr(C_FLAGS), s);
     int tbits = bits_for(std::max<uint32_t>(f->tiles_cap, 2));
     f->inst_in_alt = radix_sort(f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(), f->tkey2.as<uint32_t>(),
-                                f->irec2.as<uint32_t>(), f->ctr(C_INST), kc, tbits, ws, s);
+                                f->irec2.as<uint32_t>(), f->ctr(C_INST), kc, tbits, TILE_SORT_DIGIT, ws, s);
     tile_ranges(f->sorted_tkey(), f->ctr(C_INST), kc, f->ranges.as<uint2>(), f->tiles_cap, f->ctr(C_FLAGS), s);
     return check_launch("tile binning");
 }

@@ -106,12 +106,15 @@ void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const u
 // Result lands in (k1, v1) if the number of 8-bit passes is odd, else (k0, v0);
 // returns 1 or 0 accordingly.
 struct SortWs {
-    uint32_t* hist;     // 256 * sort_blocks(cap)
+    uint32_t* hist;     // sort_hist_words(cap) entries
     uint32_t* partial;  // scan workspace: >= 1024 + 1 entries
 };
-int sort_blocks(uint64_t cap);
+int sort_blocks(uint64_t cap, int db);
+size_t sort_hist_words(uint64_t cap);
+// Stable sort of (key, value) pairs on the low nbits of the keys, in passes of
+// at most max_db (<= 11) bits; returns 1 if the result is in (k1, v1).
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
-               uint32_t cap, int nbits, SortWs ws, hipStream_t s);
+               uint32_t cap, int nbits, int max_db, SortWs ws, hipStream_t s);
 
 // Instances of the depth-ordered records: tile keys and record ids, one per
 // tile a record's support meets (tiles tw x th).

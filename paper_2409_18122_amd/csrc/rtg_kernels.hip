@@ -520,11 +520,13 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
 }
 
 // ------------------------------------------------------------- radix sort
-// Stable LSD sort with 8-bit digits.  A fixed grid of blocks splits the
-// input into equal chunks; per pass: per-block digit histograms (upsweep),
-// an exclusive scan of the digit-major histogram table, and a scatter in
+// Stable LSD sort with digits of up to 11 bits (2048 bins).  A fixed grid of
+// blocks splits the input into equal chunks; per pass: per-block digit
+// histograms (upsweep), the offsets of every (digit, block), and a scatter in
 // which every wave ranks its items with 64-lane ballots (peers with the same
-// digit), preserving input order within the block.
+// digit), preserving input order within the block.  Up to 128 blocks compute
+// their offsets themselves from the block-major histogram table; more blocks
+// scan a digit-major table with the multi-block scan.
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
@@ -532,11 +534,14 @@ constexpr int RS_IPT = 8;
 constexpr int RS_SEG = 64 * RS_IPT;         // items per wave per tile
 constexpr int RS_TILE = RS_THREADS * RS_IPT;  // items per block per tile
 constexpr int RS_MAX_BLOCKS = 1024;
+constexpr int RS_FUSED_BLOCKS = 128;
+constexpr int RS_MAX_DB = 11;
 
+template <int DB>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid) {
     uint64_t m = valid;
 #pragma unroll
-    for (int b = 0; b < 8; b++) {
+    for (int b = 0; b < DB; b++) {
         uint32_t bit = (d >> b) & 1u;
         uint64_t bal = __ballot(bit);
         m &= bit ? bal : ~bal;
@@ -552,14 +557,19 @@ __device__ __forceinline__ void rs_chunk(uint32_t n, uint32_t& begin, uint32_t& 
     end = (uint32_t)min<uint64_t>(b + per, n);
 }
 
+// Digit of this pass: `bits` (<= DB) bits from `shift`.
 // hist layout: digit-major [d][block] when block_major == 0 (scanned as a
 // whole), block-major [block][d] otherwise (read directly by the scatter).
+template <int DB>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ n_dev, uint32_t cap,
-                                                           int shift, uint32_t* __restrict__ hist, int block_major) {
-    __shared__ uint32_t h[RS_WAVES][256];
-    int tid = threadIdx.x, wv = tid >> 6;
-    for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
+                                                           int shift, int bits, uint32_t* __restrict__ hist,
+                                                           int block_major) {
+    constexpr int NB = 1 << DB;
+    __shared__ uint32_t h[RS_WAVES][NB];
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const uint32_t mask = (1u << bits) - 1u;
+    for (int i = tid; i < RS_WAVES * NB; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
@@ -567,59 +577,97 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
     for (uint32_t base = begin + wv * 64; base < end; base += RS_THREADS) {
         uint32_t idx = base + lane_id();
         bool valid = idx < end;
-        uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
+        uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
         uint64_t vm = __ballot(valid);
-        uint64_t m = digit_peers(d, vm);
+        uint64_t m = digit_peers<DB>(d, vm);
         if (valid && lane_id() == (uint32_t)__builtin_ctzll(m)) h[wv][d] += (uint32_t)__popcll(m);
     }
     __syncthreads();
-    uint32_t s = 0;
+    for (int d = tid; d < NB; d += RS_THREADS) {
+        uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; w++) s += h[w][tid];
-    if (block_major)
-        hist[(uint64_t)blockIdx.x * 256 + tid] = s;
-    else
-        hist[(uint64_t)tid * gridDim.x + blockIdx.x] = s;
+        for (int w = 0; w < RS_WAVES; w++) c += h[w][d];
+        if (block_major)
+            hist[(uint64_t)blockIdx.x * NB + d] = c;
+        else
+            hist[(uint64_t)d * gridDim.x + blockIdx.x] = c;
+    }
 }
 
+template <int DB>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            uint32_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_dev, uint32_t cap,
-                                                           int shift, const uint32_t* __restrict__ hist,
+                                                           int shift, int bits, const uint32_t* __restrict__ hist,
                                                            int block_major) {
-    __shared__ uint32_t wh[RS_WAVES][256];
-    __shared__ uint32_t bbase[256];
+    constexpr int NB = 1 << DB;
+    constexpr int DPT = NB / RS_THREADS > 0 ? NB / RS_THREADS : 1;  // digits per thread
+    __shared__ uint32_t wh[RS_WAVES][NB];
+    __shared__ uint32_t bbase[NB];
     __shared__ uint32_t ws[RS_WAVES];
-    int tid = threadIdx.x, wv = tid >> 6;
-    uint32_t lane = lane_id();
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const uint32_t lane = lane_id();
+    const uint32_t mask = (1u << bits) - 1u;
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
     rs_chunk(n, begin, end);
     if (block_major) {
-        // offset of digit tid for this block = count of smaller digits in all
-        // blocks + count of this digit in earlier blocks
-        uint32_t tot = 0, pre = 0;
+        // offset of digit d for this block = count of smaller digits in all
+        // blocks + count of digit d in earlier blocks; thread tid owns the
+        // DPT consecutive digits from tid * DPT
+        uint32_t tot[DPT], pre[DPT];
+#pragma unroll
+        for (int j = 0; j < DPT; j++) tot[j] = pre[j] = 0;
+        if (tid * DPT < NB) {
+            // independent loads, unrolled so that many are in flight
 #pragma unroll 8
-        for (uint32_t b = 0; b < gridDim.x; b++) {
-            const uint32_t c = hist[(uint64_t)b * 256 + tid];
-            tot += c;
-            if (b < blockIdx.x) pre += c;
+            for (uint32_t b = 0; b < gridDim.x; b++) {
+                uint32_t c[DPT];
+                if constexpr (DPT % 4 == 0) {
+#pragma unroll
+                    for (int j = 0; j < DPT; j += 4) {
+                        const uint4 q = *reinterpret_cast<const uint4*>(hist + (uint64_t)b * NB + tid * DPT + j);
+                        c[j] = q.x;
+                        c[j + 1] = q.y;
+                        c[j + 2] = q.z;
+                        c[j + 3] = q.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < DPT; j++) c[j] = hist[(uint64_t)b * NB + tid * DPT + j];
+                }
+                const bool earlier = b < blockIdx.x;
+#pragma unroll
+                for (int j = 0; j < DPT; j++) {
+                    tot[j] += c[j];
+                    pre[j] += earlier ? c[j] : 0u;
+                }
+            }
         }
-        uint32_t inc = wave_incl_scan(tot);
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; j++) mine += tot[j];
+        const uint32_t inc = wave_incl_scan(mine);
         if (lane == 63) ws[wv] = inc;
         __syncthreads();
-        uint32_t base = 0;
+        uint32_t base = inc - mine;
 #pragma unroll
         for (int w = 0; w < RS_WAVES; w++)
             if (w < wv) base += ws[w];
-        bbase[tid] = base + inc - tot + pre;
+        if (tid * DPT < NB) {
+#pragma unroll
+            for (int j = 0; j < DPT; j++) {
+                bbase[tid * DPT + j] = base + pre[j];
+                base += tot[j];
+            }
+        }
     } else {
-        bbase[tid] = hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+        for (int d = tid; d < NB; d += RS_THREADS) bbase[d] = hist[(uint64_t)d * gridDim.x + blockIdx.x];
     }
     for (uint32_t t0 = begin; t0 < end; t0 += RS_TILE) {
-        for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&wh[0][0])[i] = 0;
+        for (int i = tid; i < RS_WAVES * NB; i += RS_THREADS) (&wh[0][0])[i] = 0;
         __syncthreads();
         uint32_t seg = t0 + wv * RS_SEG;
         uint32_t k[RS_IPT], v[RS_IPT], pos[RS_IPT];
@@ -634,30 +682,30 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
         for (int j = 0; j < RS_IPT; j++) {
             uint32_t idx = seg + j * 64 + lane;
             bool valid = idx < end;
-            uint32_t d = (k[j] >> shift) & 255u;
+            uint32_t d = (k[j] >> shift) & mask;
             uint64_t vm = __ballot(valid);
-            uint64_t m = digit_peers(d, vm);
+            uint64_t m = digit_peers<DB>(d, vm);
             uint32_t before = valid ? wh[wv][d] : 0u;
             pos[j] = before + (uint32_t)__popcll(m & lanemask_lt());
             if (valid && lane == (uint32_t)__builtin_ctzll(m)) wh[wv][d] = before + (uint32_t)__popcll(m);
         }
         __syncthreads();
-        {
-            uint32_t run = bbase[tid];
+        for (int d = tid; d < NB; d += RS_THREADS) {
+            uint32_t run = bbase[d];
 #pragma unroll
             for (int w = 0; w < RS_WAVES; w++) {
-                uint32_t c = wh[w][tid];
-                wh[w][tid] = run;
+                uint32_t c = wh[w][d];
+                wh[w][d] = run;
                 run += c;
             }
-            bbase[tid] = run;
+            bbase[d] = run;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < RS_IPT; j++) {
             uint32_t idx = seg + j * 64 + lane;
             if (idx < end) {
-                uint32_t d = (k[j] >> shift) & 255u;
+                uint32_t d = (k[j] >> shift) & mask;
                 uint32_t dst = wh[wv][d] + pos[j];
                 kout[dst] = k[j];
                 vout[dst] = v[j];
@@ -1895,33 +1943,55 @@ void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const u
     k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, gather, out, n_dev, cap, ws.partial);
 }
 
-int sort_blocks(uint64_t cap) {
-    uint64_t b = (cap + RS_TILE - 1) / RS_TILE;
-    if (b < 1) b = 1;
-    if (b > RS_MAX_BLOCKS) b = RS_MAX_BLOCKS;
-    return (int)b;
+// Grid of a pass with digits of db bits: one block per tile of input, up to
+// RS_MAX_BLOCKS.  Wide digits make the per-block offset computation cost
+// 2^db x blocks loads per block, so for them inputs of up to
+// RS_FUSED_BLOCKS * 8 tiles use at most RS_FUSED_BLOCKS blocks, each walking
+// several tiles, and need no separate offset scan.
+int sort_blocks(uint64_t cap, int db) {
+    uint64_t t = (cap + RS_TILE - 1) / RS_TILE;
+    if (t < 1) t = 1;
+    if (db > 8 && t <= (uint64_t)RS_FUSED_BLOCKS * 8) return (int)std::min<uint64_t>(t, RS_FUSED_BLOCKS);
+    return (int)std::min<uint64_t>(t, RS_MAX_BLOCKS);
 }
 
+size_t sort_hist_words(uint64_t cap) {
+    return (size_t)(1u << RS_MAX_DB) * (size_t)std::max(sort_blocks(cap, 8), sort_blocks(cap, RS_MAX_DB));
+}
+
+template <int DB>
+static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, const uint32_t* n_dev, uint32_t cap,
+                    int nb, int shift, int bits, SortWs ws, hipStream_t s) {
+    const int fused = nb <= RS_FUSED_BLOCKS;
+    k_rs_upsweep<DB><<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, bits, ws.hist, fused);
+    if (!fused) {
+        // table of 2^DB * nb counts: the multi-block scan, in place
+        const uint32_t count = (uint32_t)((1u << DB) * nb);
+        int sb = scan_blocks(count);
+        k_fill_u32<<<1, 64, 0, s>>>(ws.partial + SC_MAX_BLOCKS, count, 1);
+        k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.partial + SC_MAX_BLOCKS, count, ws.partial);
+        k_scan_partials<<<1, SC_MAX_BLOCKS, 0, s>>>(ws.partial, sb, nullptr);
+        k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, ws.partial + SC_MAX_BLOCKS, count,
+                                              ws.partial);
+    }
+    k_rs_scatter<DB><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused);
+}
+
+// The nbits are split into the fewest passes of at most max_db bits, as
+// evenly as possible; passes of up to 8 bits use 256 bins.
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev, uint32_t cap,
-               int nbits, SortWs ws, hipStream_t s) {
-    int nb = sort_blocks(cap);
-    int passes = (nbits + 7) / 8;
+               int nbits, int max_db, SortWs ws, hipStream_t s) {
+    max_db = std::max(1, std::min(max_db, RS_MAX_DB));
+    const int passes = std::max(1, (nbits + max_db - 1) / max_db);
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
-    const int fused = nb <= 128;
+    int shift = 0;
     for (int p = 0; p < passes; p++) {
-        int shift = 8 * p;
-        k_rs_upsweep<<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, ws.hist, fused);
-        if (!fused) {
-            // table of 256 * nb counts: the multi-block scan, in place
-            const uint32_t count = (uint32_t)(256 * nb);
-            int sb = scan_blocks(count);
-            k_fill_u32<<<1, 64, 0, s>>>(ws.partial + SC_MAX_BLOCKS, count, 1);
-            k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.partial + SC_MAX_BLOCKS, count, ws.partial);
-            k_scan_partials<<<1, SC_MAX_BLOCKS, 0, s>>>(ws.partial, sb, nullptr);
-            k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, ws.partial + SC_MAX_BLOCKS, count,
-                                                  ws.partial);
-        }
-        k_rs_scatter<<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, ws.hist, fused);
+        const int bits = nbits / passes + (p < nbits % passes ? 1 : 0);
+        if (bits <= 8)
+            rs_pass<8>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, 8), shift, std::max(bits, 1), ws, s);
+        else
+            rs_pass<RS_MAX_DB>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, RS_MAX_DB), shift, bits, ws, s);
+        shift += bits;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
