@@ -1167,6 +1167,90 @@ __device__ __forceinline__ float wave_sum_dpp(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// Sums each of n per-lane values over the wave (the same DPP steps as
+// wave_sum_dpp, applied to all values step by step so they overlap).
+template <int N>
+__device__ __forceinline__ void wave_sum_dpp_n(float* x) {
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp_mov<0xb1>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp_mov<0x4e>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp_mov<0x124>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp_mov<0x128>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp_mov<0x142, 0xa>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp_mov<0x143, 0xc>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[i]), 63));
+}
+
+// Highest set bit of a wave-uniform mask array, cleared; -1 if none.
+template <int NW>
+__device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
+    // static indices only, so that m stays in registers
+    int k = -1;
+#pragma unroll
+    for (int c = 0; c < NW; c++)
+        if (m[c]) k = c * 64 + 63 - (int)__builtin_clzll(m[c]);
+#pragma unroll
+    for (int c = 0; c < NW; c++)
+        if (k >= 0 && c == (k >> 6)) m[c] &= ~(1ull << (k & 63));
+    return k;
+}
+
+// Adds a splat's 10 wave totals to its record's binary64 gradient slots:
+// mean (2), conic (3), opacity, colour (3), depth.
+__device__ __forceinline__ void add_g2d(double* g2d, uint32_t r, const float* t) {
+    double* dst = g2d + (uint64_t)r * G2D_STRIDE;
+#pragma unroll
+    for (int v = 0; v < 10; v++) unsafeAtomicAdd(dst + v, (double)t[v]);
+}
+
+// One pixel's step of the reverse compositing recursion for a kept splat:
+// restores T and the running sums S of the splats behind it, and adds the
+// pixel's contributions to the splat's per-lane sums acc (same order as
+// add_g2d).  T_i = T_{i+1} / (1 - a_i); w = a_i T_i.
+__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float w1, float w2, float4 g1,
+                                          float4 at, float ui, float amax, float kq, float gr, float gg, float gb,
+                                          float gd, float ga, float gu, float& T, float& S0, float& S1, float& S2,
+                                          float& S3, float& S4, float& S5, float* acc) {
+    const float inv = 1.0f / (1.0f - a);
+    const float Ti = T * inv;
+    const float w = a * Ti;
+    float da = gr * (at.x * Ti - S0 * inv);
+    da = fmaf(gg, at.y * Ti - S1 * inv, da);
+    da = fmaf(gb, at.z * Ti - S2 * inv, da);
+    da = fmaf(gd, at.w * Ti - S3 * inv, da);
+    da = fmaf(ga, Ti - S4 * inv, da);
+    da = fmaf(gu, ui * Ti - S5 * inv, da);
+    acc[6] = fmaf(gr, w, acc[6]);
+    acc[7] = fmaf(gg, w, acc[7]);
+    acc[8] = fmaf(gb, w, acc[8]);
+    acc[9] = fmaf(gd, w, acc[9]);
+    S0 = fmaf(at.x, w, S0);
+    S1 = fmaf(at.y, w, S1);
+    S2 = fmaf(at.z, w, S2);
+    S3 = fmaf(at.w, w, S3);
+    S4 += w;
+    S5 = fmaf(ui, w, S5);
+    T = Ti;
+    if (g1.w * G <= amax) {
+        acc[5] = fmaf(da, G, acc[5]);
+        // dL/dpower with power = d^T Q d and G = exp(-power / 2)
+        const float dpow = -0.5f * G * (da * g1.w);
+        acc[2] = fmaf(dpow * dx, dx, acc[2]);
+        acc[3] = fmaf(dpow * 2.0f * dx, dy, acc[3]);
+        acc[4] = fmaf(dpow * dy, dy, acc[4]);
+        // d = p - mean: dL/dmean = -dpow * 2 Q d, with Q d = (2 / log2e) M^T w
+        const float mm = -dpow * kq;
+        acc[0] = fmaf(mm, fmaf(g1.x, w1, g1.y * w2), acc[0]);
+        acc[1] = fmaf(mm, g1.z * w2, acc[1]);
+    }
+}
+
 // NW waves per tile; the tile's 8x8 pixel blocks are dealt to the waves in
 // row-major order (PPT blocks each) and a lane owns one pixel per block.
 // Splats are staged per batch for the whole workgroup; a wave visits only
@@ -1275,84 +1359,59 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
         // splats at or past every lane's last contributor cannot matter
         const int cnt = (int)(min<int64_t>(bend, (int64_t)wave_last) - bstart);
         wave_masks<B, BWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
-        // back to front over the splats that can reach this wave's pixels
-        for (int k = B - 1; k >= 0; k--) {
-            {
-                const int c = k >> 6;
-                const uint64_t below = m[c] & (~0ull >> (63 - (k & 63)));  // bits 0 .. k % 64
-                if (!below) {
-                    k = c * 64;  // nothing left in this chunk
-                    continue;
-                }
-                k = c * 64 + 63 - (int)__builtin_clzll(below);
-            }
-            const uint2 pb = s_pb[k];
-            const uint32_t pos = (uint32_t)(bstart + k);
-            const float4 g0 = s_g0[k], g1 = s_g1[k], at = s_at[k];
-            const float ui = s_u[k];
-            const uint32_t r = s_r[k];
-            float a_mx = 0.0f, a_my = 0.0f, a_qa = 0.0f, a_qb = 0.0f, a_qc = 0.0f, a_o = 0.0f;
-            float a_c0 = 0.0f, a_c1 = 0.0f, a_c2 = 0.0f, a_d = 0.0f;
-            bool any = false;
+        // back to front over the splats that can reach this wave's pixels,
+        // two per step: their alphas are independent of the pixel state, and
+        // their two wave reductions run interleaved
+        for (;;) {
+            const int k0 = pop_high<NW>(m);
+            if (k0 < 0) break;
+            const int k1 = pop_high<NW>(m);
+            const int kb = k1 < 0 ? k0 : k1;
+            const uint2 pb0 = s_pb[k0], pb1 = s_pb[kb];
+            const uint32_t pos0 = (uint32_t)(bstart + k0), pos1 = k1 < 0 ? 0xffffffffu : (uint32_t)(bstart + k1);
+            const float4 g00 = s_g0[k0], g10 = s_g1[k0], at0 = s_at[k0];
+            const float4 g01 = s_g0[kb], g11 = s_g1[kb], at1 = s_at[kb];
+            const float u0 = s_u[k0], u1 = s_u[kb];
+            const uint32_t r0 = s_r[k0], r1 = s_r[kb];
+            float acc[2][10];
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int v = 0; v < 10; v++) acc[q][v] = 0.0f;
+            bool any0 = false, any1 = false;
 #pragma unroll
             for (int j = 0; j < PPT; j++) {
-                if (pos >= last[j] || !in_box(pb, ipx[j], ipy[j])) continue;
-                float G, dx, dy, w1, w2;
-                const float a = splat_alpha(g0, g1, px[j], py[j], amax, G, dx, dy, w1, w2);
-                if (!splat_kept(a, g0, g1, rec.q64, r, px[j], py[j], st)) continue;
-                any = true;
-                const float inv = 1.0f / (1.0f - a);
-                const float Ti = T[j] * inv;
-                const float w = a * Ti;
-                float da = gr[j] * (at.x * Ti - S0[j] * inv);
-                da = fmaf(gg[j], at.y * Ti - S1[j] * inv, da);
-                da = fmaf(gb[j], at.z * Ti - S2[j] * inv, da);
-                da = fmaf(gd[j], at.w * Ti - S3[j] * inv, da);
-                da = fmaf(ga[j], Ti - S4[j] * inv, da);
-                da = fmaf(gu[j], ui * Ti - S5[j] * inv, da);
-                a_c0 = fmaf(gr[j], w, a_c0);
-                a_c1 = fmaf(gg[j], w, a_c1);
-                a_c2 = fmaf(gb[j], w, a_c2);
-                a_d = fmaf(gd[j], w, a_d);
-                S0[j] = fmaf(at.x, w, S0[j]);
-                S1[j] = fmaf(at.y, w, S1[j]);
-                S2[j] = fmaf(at.z, w, S2[j]);
-                S3[j] = fmaf(at.w, w, S3[j]);
-                S4[j] += w;
-                S5[j] = fmaf(ui, w, S5[j]);
-                T[j] = Ti;
-                if (g1.w * G <= amax) {
-                    a_o = fmaf(da, G, a_o);
-                    // dL/dpower with power = d^T Q d and G = exp(-power / 2)
-                    const float dpow = -0.5f * G * (da * g1.w);
-                    a_qa = fmaf(dpow * dx, dx, a_qa);
-                    a_qb = fmaf(dpow * 2.0f * dx, dy, a_qb);
-                    a_qc = fmaf(dpow * dy, dy, a_qc);
-                    // d = p - mean: dL/dmean = -dpow * 2 Q d, with Q d = (2 / log2e) M^T w
-                    const float m = -dpow * kq;
-                    a_mx = fmaf(m, fmaf(g1.x, w1, g1.y * w2), a_mx);
-                    a_my = fmaf(m, g1.z * w2, a_my);
+                float G0, dx0, dy0, w10, w20, G1, dx1, dy1, w11, w21;
+                const float a0 = splat_alpha(g00, g10, px[j], py[j], amax, G0, dx0, dy0, w10, w20);
+                const float a1 = splat_alpha(g01, g11, px[j], py[j], amax, G1, dx1, dy1, w11, w21);
+                const bool ok0 = pos0 < last[j] && in_box(pb0, ipx[j], ipy[j]) &&
+                                 splat_kept(a0, g00, g10, rec.q64, r0, px[j], py[j], st);
+                const bool ok1 = pos1 < last[j] && in_box(pb1, ipx[j], ipy[j]) &&
+                                 splat_kept(a1, g01, g11, rec.q64, r1, px[j], py[j], st);
+                if (ok0) {
+                    any0 = true;
+                    bwd_pixel(a0, G0, dx0, dy0, w10, w20, g10, at0, u0, amax, kq, gr[j], gg[j], gb[j], gd[j], ga[j],
+                              gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j], acc[0]);
+                }
+                if (ok1) {
+                    any1 = true;
+                    bwd_pixel(a1, G1, dx1, dy1, w11, w21, g11, at1, u1, amax, kq, gr[j], gg[j], gb[j], gd[j], ga[j],
+                              gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j], acc[1]);
                 }
             }
-            if (__ballot(any)) {
-                const float t_mx = wave_sum_dpp(a_mx), t_my = wave_sum_dpp(a_my);
-                const float t_qa = wave_sum_dpp(a_qa), t_qb = wave_sum_dpp(a_qb), t_qc = wave_sum_dpp(a_qc);
-                const float t_o = wave_sum_dpp(a_o);
-                const float t_c0 = wave_sum_dpp(a_c0), t_c1 = wave_sum_dpp(a_c1), t_c2 = wave_sum_dpp(a_c2);
-                const float t_d = wave_sum_dpp(a_d);
+            const bool t0 = __ballot(any0) != 0, t1 = __ballot(any1) != 0;
+            if (t0 && t1) {
+                wave_sum_dpp_n<20>(&acc[0][0]);
                 if (lane == 0) {
-                    double* dst = g2d + (uint64_t)r * G2D_STRIDE;
-                    unsafeAtomicAdd(dst + 0, (double)t_mx);
-                    unsafeAtomicAdd(dst + 1, (double)t_my);
-                    unsafeAtomicAdd(dst + 2, (double)t_qa);
-                    unsafeAtomicAdd(dst + 3, (double)t_qb);
-                    unsafeAtomicAdd(dst + 4, (double)t_qc);
-                    unsafeAtomicAdd(dst + 5, (double)t_o);
-                    unsafeAtomicAdd(dst + 6, (double)t_c0);
-                    unsafeAtomicAdd(dst + 7, (double)t_c1);
-                    unsafeAtomicAdd(dst + 8, (double)t_c2);
-                    unsafeAtomicAdd(dst + 9, (double)t_d);
+                    add_g2d(g2d, r0, acc[0]);
+                    add_g2d(g2d, r1, acc[1]);
                 }
+            } else if (t0) {
+                wave_sum_dpp_n<10>(acc[0]);
+                if (lane == 0) add_g2d(g2d, r0, acc[0]);
+            } else if (t1) {
+                wave_sum_dpp_n<10>(acc[1]);
+                if (lane == 0) add_g2d(g2d, r1, acc[1]);
             }
         }
     }
