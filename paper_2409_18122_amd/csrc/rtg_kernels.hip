@@ -919,10 +919,6 @@ __device__ __forceinline__ float splat_alpha(float4 g0, float4 g1, float px, flo
     return fminf(amax, g1.w * G);
 }
 
-// Pixel (u, v) inside a splat's support box (outside it, alpha < alpha_min).
-__device__ __forceinline__ bool in_box(uint2 b, int u, int v) {
-    return u >= (int)(b.x & 0xffffu) && u <= (int)(b.x >> 16) && v >= (int)(b.y & 0xffffu) && v <= (int)(b.y >> 16);
-}
 
 // Splat box meets the pixel rectangle [c0, c1] x [r0, r1].
 __device__ __forceinline__ bool box_meets(uint2 b, int c0, int c1, int r0, int r1) {
@@ -952,29 +948,38 @@ __device__ __forceinline__ void wave_masks(const uint2* s_pb, const float4* s_g0
         m[c] = __ballot(hit);
     }
 }
-// Next two set bits of a wave-uniform mask (k1 < 0 if only one is left).
-__device__ __forceinline__ void pop2(uint64_t& mm, int base, int& k0, int& k1) {
-    k0 = base + (int)__builtin_ctzll(mm);
-    mm &= mm - 1;
-    if (mm) {
-        k1 = base + (int)__builtin_ctzll(mm);
-        mm &= mm - 1;
-    } else {
-        k1 = -1;
+// Next P set bits of a wave-uniform mask (entries past the last are -1).
+template <int P>
+__device__ __forceinline__ void pop_n(uint64_t& mm, int base, int (&ks)[P]) {
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+        if (mm) {
+            ks[q] = base + (int)__builtin_ctzll(mm);
+            mm &= mm - 1;
+        } else {
+            ks[q] = -1;
+        }
     }
 }
 
+// Splats evaluated per step of the front-to-back loops: their alphas are
+// independent of the pixel state, so they overlap; the updates follow in order.
+constexpr int FWD_STEP = 4;
 // Relative band around alpha_min inside which the skip decision is re-taken
 // in binary64 (far wider than the binary32 error of alpha).
 constexpr float REFINE = 2e-3f;
 
 // The alpha_min test: a splat with alpha < alpha_min at a pixel is skipped
-// there.  Near the threshold the decision is taken in binary64 from the
-// binary64 conic, as the definition states it.
-__device__ __forceinline__ bool splat_kept(float a, float4 g0, float4 g1, const double4* __restrict__ q64,
-                                           uint32_t r, float px, float py, const SetDev& st) {
+// there.  Near the threshold (near_amin) the decision is re-taken in binary64
+// from the binary64 conic (kept64), as the definition states it.  No pixel
+// box test is needed: the box is the exact bounding box of the support, so
+// outside it alpha < alpha_min already.  The loops take the rare binary64
+// branch once per step, for all the splats of the step.
+__device__ __forceinline__ bool near_amin(float a, float amin) { return fabsf(a - amin) <= REFINE * amin; }
+
+__device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __restrict__ q64, uint32_t r, float px,
+                                       float py, const SetDev& st) {
     const float amin = st.alpha_min;
-    if (fabsf(a - amin) > REFINE * amin) return a >= amin;
     const double4 q = q64[r];
     const double dx = ((double)px - (double)g0.x) - (double)g0.z;
     const double dy = ((double)py - (double)g0.y) - (double)g0.w;
@@ -1031,40 +1036,48 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
         for (int c = 0; c < NT / 64; c++) {
             uint64_t mm = m[c];
             while (mm && !done) {
-                // two splats per step: their alphas are independent of T
-                int ks[2];
-                pop2(mm, c * 64, ks[0], ks[1]);
-                float as[2];
-                bool ok[2];
+                int ks[FWD_STEP];
+                pop_n<FWD_STEP>(mm, c * 64, ks);
+                float as[FWD_STEP];
+                bool ok[FWD_STEP];
+                bool need = false;
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
+                for (int q = 0; q < FWD_STEP; q++) {
                     const int k = ks[q] < 0 ? ks[0] : ks[q];
                     float G, dx, dy, w1, w2;
-                    const float4 g0 = s_g0[k], g1 = s_g1[k];
-                    as[q] = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
-                    ok[q] = ks[q] >= 0 && in_box(s_pb[k], u, v) &&
-                            splat_kept(as[q], g0, g1, rec.q64, s_r[k], px, py, st);
+                    as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
+                    ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
+                    need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
                 }
+                if (__ballot(need)) {
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    if (!ok[q] || done) continue;
-                    const int k = ks[q];
+                    for (int q = 0; q < FWD_STEP; q++) {
+                        const int k = ks[q] < 0 ? ks[0] : ks[q];
+                        if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
+                            ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
+                    }
+                }
+                // predicated, not branched: the update is a few FMAs
+#pragma unroll
+                for (int q = 0; q < FWD_STEP; q++) {
+                    const int k = ks[q] < 0 ? ks[0] : ks[q];
                     const float a = as[q];
                     const float Tn = T * (1.0f - a);
-                    if (Tn < st.T_min) {
-                        done = true;
-                        continue;
-                    }
+                    const bool take = ok[q] && !done;
+                    const bool stop = take && Tn < st.T_min;
+                    const bool use = take && !stop;
+                    done = done || stop;
                     const float w = a * T;
                     const float4 at = s_at[k];
-                    c0 = fmaf(at.x, w, c0);
-                    c1 = fmaf(at.y, w, c1);
-                    c2 = fmaf(at.z, w, c2);
-                    dd = fmaf(at.w, w, dd);
-                    uu = fmaf(s_u[k], w, uu);
-                    T = Tn;
-                    last = b - rg.x + (uint32_t)k + 1;
-                    ncontrib++;
+                    const float uk = s_u[k];
+                    c0 = use ? fmaf(at.x, w, c0) : c0;
+                    c1 = use ? fmaf(at.y, w, c1) : c1;
+                    c2 = use ? fmaf(at.z, w, c2) : c2;
+                    dd = use ? fmaf(at.w, w, dd) : dd;
+                    uu = use ? fmaf(uk, w, uu) : uu;
+                    T = use ? Tn : T;
+                    last = use ? b - rg.x + (uint32_t)k + 1 : last;
+                    ncontrib += use ? 1u : 0u;
                 }
             }
         }
@@ -1289,7 +1302,6 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
 
     float px[PPT], py[PPT], T[PPT];
-    int ipx[PPT], ipy[PPT];
     uint32_t last[PPT];
     float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
     float S0[PPT], S1[PPT], S2[PPT], S3[PPT], S4[PPT], S5[PPT];
@@ -1306,8 +1318,6 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
         const int u = bx0 + (lane & 7), v = by0 + (lane >> 3);
         px[j] = (float)u;
         py[j] = (float)v;
-        ipx[j] = u;
-        ipy[j] = v;
         T[j] = 1.0f;
         last[j] = 0;
         gr[j] = gg[j] = gb[j] = gd[j] = ga[j] = gu[j] = 0.0f;
@@ -1367,7 +1377,6 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
             if (k0 < 0) break;
             const int k1 = pop_high<NW>(m);
             const int kb = k1 < 0 ? k0 : k1;
-            const uint2 pb0 = s_pb[k0], pb1 = s_pb[kb];
             const uint32_t pos0 = (uint32_t)(bstart + k0), pos1 = k1 < 0 ? 0xffffffffu : (uint32_t)(bstart + k1);
             const float4 g00 = s_g0[k0], g10 = s_g1[k0], at0 = s_at[k0];
             const float4 g01 = s_g0[kb], g11 = s_g1[kb], at1 = s_at[kb];
@@ -1384,10 +1393,14 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
                 float G0, dx0, dy0, w10, w20, G1, dx1, dy1, w11, w21;
                 const float a0 = splat_alpha(g00, g10, px[j], py[j], amax, G0, dx0, dy0, w10, w20);
                 const float a1 = splat_alpha(g01, g11, px[j], py[j], amax, G1, dx1, dy1, w11, w21);
-                const bool ok0 = pos0 < last[j] && in_box(pb0, ipx[j], ipy[j]) &&
-                                 splat_kept(a0, g00, g10, rec.q64, r0, px[j], py[j], st);
-                const bool ok1 = pos1 < last[j] && in_box(pb1, ipx[j], ipy[j]) &&
-                                 splat_kept(a1, g01, g11, rec.q64, r1, px[j], py[j], st);
+                bool ok0 = pos0 < last[j] && a0 >= st.alpha_min;
+                bool ok1 = pos1 < last[j] && a1 >= st.alpha_min;
+                const bool n0 = pos0 < last[j] && near_amin(a0, st.alpha_min);
+                const bool n1 = pos1 < last[j] && near_amin(a1, st.alpha_min);
+                if (__ballot(n0 || n1)) {
+                    if (n0) ok0 = kept64(g00, g10, rec.q64, r0, px[j], py[j], st);
+                    if (n1) ok1 = kept64(g01, g11, rec.q64, r1, px[j], py[j], st);
+                }
                 if (ok0) {
                     any0 = true;
                     bwd_pixel(a0, G0, dx0, dy0, w10, w20, g10, at0, u0, amax, kq, gr[j], gg[j], gb[j], gd[j], ga[j],
@@ -1599,30 +1612,40 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
         for (int c = 0; c < NT / 64; c++) {
             uint64_t mm = m[c];
             while (mm && !done) {
-                int ks[2];
-                pop2(mm, c * 64, ks[0], ks[1]);
-                float as[2];
-                bool ok[2];
+                int ks[FWD_STEP];
+                pop_n<FWD_STEP>(mm, c * 64, ks);
+                float as[FWD_STEP];
+                bool ok[FWD_STEP];
+                bool need = false;
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
+                for (int q = 0; q < FWD_STEP; q++) {
                     const int k = ks[q] < 0 ? ks[0] : ks[q];
                     float G, dx, dy, w1, w2;
-                    const float4 g0 = s_g0[k], g1 = s_g1[k];
-                    as[q] = splat_alpha(g0, g1, px, py, st.alpha_max, G, dx, dy, w1, w2);
-                    ok[q] = ks[q] >= 0 && in_box(s_pb[k], u, v) &&
-                            splat_kept(as[q], g0, g1, rec.q64, s_r[k], px, py, st);
+                    as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
+                    ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
+                    need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
                 }
+                if (__ballot(need)) {
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    if (!ok[q] || done) continue;
+                    for (int q = 0; q < FWD_STEP; q++) {
+                        const int k = ks[q] < 0 ? ks[0] : ks[q];
+                        if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
+                            ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
+                    }
+                }
+                // predicated, not branched
+#pragma unroll
+                for (int q = 0; q < FWD_STEP; q++) {
+                    const int k = ks[q] < 0 ? ks[0] : ks[q];
                     const float a = as[q];
                     const float Tn = T * (1.0f - a);
-                    if (Tn < st.T_min) {
-                        done = true;
-                        continue;
-                    }
-                    uu = fmaf(s_u[ks[q]], a * T, uu);
-                    T = Tn;
+                    const bool take = ok[q] && !done;
+                    const bool stop = take && Tn < st.T_min;
+                    const bool use = take && !stop;
+                    done = done || stop;
+                    const float uk = s_u[k];
+                    uu = use ? fmaf(uk, a * T, uu) : uu;
+                    T = use ? Tn : T;
                 }
             }
         }
