@@ -965,6 +965,9 @@ __device__ __forceinline__ void pop_n(uint64_t& mm, int base, int (&ks)[P]) {
 // Splats evaluated per step of the front-to-back loops: their alphas are
 // independent of the pixel state, so they overlap; the updates follow in order.
 constexpr int FWD_STEP = 4;
+// Splats per step of the back-to-front backward loop (four measured slower:
+// the registers cut occupancy).
+constexpr int BWD_STEP = 2;
 // Relative band around alpha_min inside which the skip decision is re-taken
 // in binary64 (far wider than the binary32 error of alpha).
 constexpr float REFINE = 2e-3f;
@@ -1370,61 +1373,76 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
         const int cnt = (int)(min<int64_t>(bend, (int64_t)wave_last) - bstart);
         wave_masks<B, BWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
         // back to front over the splats that can reach this wave's pixels,
-        // two per step: their alphas are independent of the pixel state, and
-        // their two wave reductions run interleaved
+        // BWD_STEP per step: their alphas are independent of the pixel state,
+        // and their wave reductions run interleaved
         for (;;) {
-            const int k0 = pop_high<NW>(m);
-            if (k0 < 0) break;
-            const int k1 = pop_high<NW>(m);
-            const int kb = k1 < 0 ? k0 : k1;
-            const uint32_t pos0 = (uint32_t)(bstart + k0), pos1 = k1 < 0 ? 0xffffffffu : (uint32_t)(bstart + k1);
-            const float4 g00 = s_g0[k0], g10 = s_g1[k0], at0 = s_at[k0];
-            const float4 g01 = s_g0[kb], g11 = s_g1[kb], at1 = s_at[kb];
-            const float u0 = s_u[k0], u1 = s_u[kb];
-            const uint32_t r0 = s_r[k0], r1 = s_r[kb];
-            float acc[2][10];
+            int ks[BWD_STEP];
+            ks[0] = pop_high<NW>(m);
+            if (ks[0] < 0) break;
 #pragma unroll
-            for (int q = 0; q < 2; q++)
+            for (int q = 1; q < BWD_STEP; q++) ks[q] = pop_high<NW>(m);
+            float4 sg0[BWD_STEP], sg1[BWD_STEP], sat[BWD_STEP];
+            float su[BWD_STEP];
+            uint32_t sr[BWD_STEP], spos[BWD_STEP];
+#pragma unroll
+            for (int q = 0; q < BWD_STEP; q++) {
+                const int k = ks[q] < 0 ? ks[0] : ks[q];
+                sg0[q] = s_g0[k];
+                sg1[q] = s_g1[k];
+                sat[q] = s_at[k];
+                su[q] = s_u[k];
+                sr[q] = s_r[k];
+                spos[q] = ks[q] < 0 ? 0xffffffffu : (uint32_t)(bstart + ks[q]);
+            }
+            float acc[BWD_STEP][10];
+            bool any[BWD_STEP];
+#pragma unroll
+            for (int q = 0; q < BWD_STEP; q++) {
+                any[q] = false;
 #pragma unroll
                 for (int v = 0; v < 10; v++) acc[q][v] = 0.0f;
-            bool any0 = false, any1 = false;
+            }
 #pragma unroll
             for (int j = 0; j < PPT; j++) {
-                float G0, dx0, dy0, w10, w20, G1, dx1, dy1, w11, w21;
-                const float a0 = splat_alpha(g00, g10, px[j], py[j], amax, G0, dx0, dy0, w10, w20);
-                const float a1 = splat_alpha(g01, g11, px[j], py[j], amax, G1, dx1, dy1, w11, w21);
-                bool ok0 = pos0 < last[j] && a0 >= st.alpha_min;
-                bool ok1 = pos1 < last[j] && a1 >= st.alpha_min;
-                const bool n0 = pos0 < last[j] && near_amin(a0, st.alpha_min);
-                const bool n1 = pos1 < last[j] && near_amin(a1, st.alpha_min);
-                if (__ballot(n0 || n1)) {
-                    if (n0) ok0 = kept64(g00, g10, rec.q64, r0, px[j], py[j], st);
-                    if (n1) ok1 = kept64(g01, g11, rec.q64, r1, px[j], py[j], st);
+                float a[BWD_STEP], G[BWD_STEP], dx[BWD_STEP], dy[BWD_STEP], w1[BWD_STEP], w2[BWD_STEP];
+                bool ok[BWD_STEP];
+                bool need = false;
+#pragma unroll
+                for (int q = 0; q < BWD_STEP; q++) {
+                    a[q] = splat_alpha(sg0[q], sg1[q], px[j], py[j], amax, G[q], dx[q], dy[q], w1[q], w2[q]);
+                    ok[q] = spos[q] < last[j] && a[q] >= st.alpha_min;
+                    need = need || (spos[q] < last[j] && near_amin(a[q], st.alpha_min));
                 }
-                if (ok0) {
-                    any0 = true;
-                    bwd_pixel(a0, G0, dx0, dy0, w10, w20, g10, at0, u0, amax, kq, gr[j], gg[j], gb[j], gd[j], ga[j],
-                              gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j], acc[0]);
+                if (__ballot(need)) {
+#pragma unroll
+                    for (int q = 0; q < BWD_STEP; q++)
+                        if (spos[q] < last[j] && near_amin(a[q], st.alpha_min))
+                            ok[q] = kept64(sg0[q], sg1[q], rec.q64, sr[q], px[j], py[j], st);
                 }
-                if (ok1) {
-                    any1 = true;
-                    bwd_pixel(a1, G1, dx1, dy1, w11, w21, g11, at1, u1, amax, kq, gr[j], gg[j], gb[j], gd[j], ga[j],
-                              gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j], acc[1]);
+#pragma unroll
+                for (int q = 0; q < BWD_STEP; q++) {
+                    if (ok[q]) {
+                        any[q] = true;
+                        bwd_pixel(a[q], G[q], dx[q], dy[q], w1[q], w2[q], sg1[q], sat[q], su[q], amax, kq, gr[j],
+                                  gg[j], gb[j], gd[j], ga[j], gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j],
+                                  acc[q]);
+                    }
                 }
             }
-            const bool t0 = __ballot(any0) != 0, t1 = __ballot(any1) != 0;
-            if (t0 && t1) {
-                wave_sum_dpp_n<20>(&acc[0][0]);
+            bool t[BWD_STEP];
+            bool tany = false;
+#pragma unroll
+            for (int q = 0; q < BWD_STEP; q++) {
+                t[q] = __ballot(any[q]) != 0;
+                tany = tany || t[q];
+            }
+            if (tany) {
+                wave_sum_dpp_n<BWD_STEP * 10>(&acc[0][0]);
                 if (lane == 0) {
-                    add_g2d(g2d, r0, acc[0]);
-                    add_g2d(g2d, r1, acc[1]);
+#pragma unroll
+                    for (int q = 0; q < BWD_STEP; q++)
+                        if (t[q]) add_g2d(g2d, sr[q], acc[q]);
                 }
-            } else if (t0) {
-                wave_sum_dpp_n<10>(acc[0]);
-                if (lane == 0) add_g2d(g2d, r0, acc[0]);
-            } else if (t1) {
-                wave_sum_dpp_n<10>(acc[1]);
-                if (lane == 0) add_g2d(g2d, r1, acc[1]);
             }
         }
     }
