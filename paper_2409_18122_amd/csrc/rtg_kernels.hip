@@ -622,7 +622,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
         for (int j = 0; j < DPT; j++) tot[j] = pre[j] = 0;
         if (tid * DPT < NB) {
             // independent loads, unrolled so that many are in flight
-#pragma unroll 8
+#pragma unroll(DPT == 1 ? 32 : 8)
             for (uint32_t b = 0; b < gridDim.x; b++) {
                 uint32_t c[DPT];
                 if constexpr (DPT % 4 == 0) {
@@ -966,7 +966,7 @@ __device__ __forceinline__ void pop_n(uint64_t& mm, int base, int (&ks)[P]) {
 // independent of the pixel state, so they overlap; the updates follow in order.
 constexpr int FWD_STEP = 4;
 // Splats per step of the back-to-front backward loop (four measured slower:
-// the registers cut occupancy).
+// the registers cut occupancy); the reduction below is written for two.
 constexpr int BWD_STEP = 2;
 // Relative band around alpha_min inside which the skip decision is re-taken
 // in binary64 (far wider than the binary32 error of alpha).
@@ -1203,6 +1203,48 @@ __device__ __forceinline__ void wave_sum_dpp_n(float* x) {
     for (int i = 0; i < N; i++) x[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[i]), 63));
 }
 
+// Sums 20 per-lane values over the wave by recursive halving: at each of six
+// steps a lane keeps half of its values, sends the other half to its partner
+// and adds the partner's copy of the kept half.  Partners must agree on every
+// earlier choice, so the DPP pairings that flip several lane bits come first:
+// row_mirror (decided by lane bit 3), row_half_mirror (bit 2), then quad
+// swaps xor 2 (bit 1) and xor 1 (bit 0), then shuffles across 16 (bit 4) and
+// 32 lanes (sum).  Lane l ends with the total of value
+// v = 10 b3 + 5 b2 + 3 b1 + 2 b0 + b4, valid when 2 b0 + b4 < (b1 ? 2 : 3)
+// (else v = -1); lanes l and l + 32 hold the same total.
+__device__ __forceinline__ float wave_sum_halving20(const float* x, int lane, int& v) {
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1,
+               b4 = (lane >> 4) & 1;
+    float a[10], c[5], d[3], e[2];
+#pragma unroll
+    for (int j = 0; j < 10; j++) {
+        const float keep = b3 ? x[10 + j] : x[j], send = b3 ? x[j] : x[10 + j];
+        a[j] = keep + dpp_mov<0x140>(send);  // row_mirror
+    }
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        const float keep = b2 ? a[5 + j] : a[j], send = b2 ? a[j] : a[5 + j];
+        c[j] = keep + dpp_mov<0x141>(send);  // row_half_mirror
+    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) {  // halves {0, 1, 2} and {3, 4, pad}
+        const float hi = j + 3 < 5 ? c[j + 3] : 0.0f;
+        const float keep = b1 ? hi : c[j], send = b1 ? c[j] : hi;
+        d[j] = keep + dpp_mov<0x4e>(send);  // quad_perm [2, 3, 0, 1]
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) {  // halves {0, 1} and {2, pad}
+        const float hi = j + 2 < 3 ? d[j + 2] : 0.0f;
+        const float keep = b0 ? hi : d[j], send = b0 ? d[j] : hi;
+        e[j] = keep + dpp_mov<0xb1>(send);  // quad_perm [1, 0, 3, 2]
+    }
+    const float keep = b4 ? e[1] : e[0], send = b4 ? e[0] : e[1];
+    const float f = keep + __shfl_xor(send, 16, 64);
+    const int pos = 2 * (int)b0 + (int)b4;
+    v = pos < (b1 ? 2 : 3) ? 10 * (int)b3 + 5 * (int)b2 + 3 * (int)b1 + pos : -1;
+    return f + __shfl_xor(f, 32, 64);
+}
+
 // Highest set bit of a wave-uniform mask array, cleared; -1 if none.
 template <int NW>
 __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
@@ -1437,11 +1479,14 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
                 tany = tany || t[q];
             }
             if (tany) {
-                wave_sum_dpp_n<BWD_STEP * 10>(&acc[0][0]);
-                if (lane == 0) {
-#pragma unroll
-                    for (int q = 0; q < BWD_STEP; q++)
-                        if (t[q]) add_g2d(g2d, sr[q], acc[q]);
+                // lane l < 32 ends with the total of value v (splat v / 10,
+                // gradient slot v % 10) and adds it: one 20-lane atomic
+                int v;
+                const float tot = wave_sum_halving20(&acc[0][0], lane, v);
+                if (lane < 32 && v >= 0) {
+                    const int q = v >= 10 ? 1 : 0;
+                    if (q ? t[1] : t[0])
+                        unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + (v - 10 * q), (double)tot);
                 }
             }
         }
