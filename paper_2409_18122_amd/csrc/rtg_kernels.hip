@@ -467,35 +467,42 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __re
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(SC_MAX_BLOCKS) void k_scan_partials(uint32_t* __restrict__ partial,
-                                                                 int nblocks, uint32_t* __restrict__ total) {
-    __shared__ uint32_t ws[SC_MAX_BLOCKS / 64];
-    uint32_t x = threadIdx.x < (uint32_t)nblocks ? partial[threadIdx.x] : 0;
-    uint32_t inc = wave_incl_scan(x);
-    int wv = threadIdx.x >> 6;
-    if (lane_id() == 63) ws[wv] = inc;
+
+// Sum of one value per thread over a 256-thread block (every thread gets it).
+__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* ws) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = x;
     __syncthreads();
-    uint32_t base = 0, tot = 0;
-    for (int k = 0; k < SC_MAX_BLOCKS / 64; k++) {
-        uint32_t t = ws[k];
-        if (k < wv) base += t;
-        tot += t;
-    }
-    if (threadIdx.x < (uint32_t)nblocks) partial[threadIdx.x] = base + inc - x;
-    if (threadIdx.x == 0 && total) *total = tot;
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < SC_THREADS / 64; k++) t += ws[k];
+    __syncthreads();
+    return t;
 }
 
+// partial[b] holds block b's total (k_scan_reduce); each block adds up the
+// totals before it, and block 0 writes the grand total to *total (nullable).
 // in and out may be the same array (each item is read and written by one thread).
 __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
                                                           const uint32_t* __restrict__ gather,
                                                           uint32_t* out,
                                                           const uint32_t* __restrict__ n_dev, uint32_t cap,
-                                                          const uint32_t* __restrict__ partial) {
+                                                          const uint32_t* __restrict__ partial,
+                                                          uint32_t* __restrict__ total_out) {
     __shared__ uint32_t ws[SC_THREADS / 64];
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
     chunk_of(n, gridDim.x, begin, end);
-    uint32_t run = partial[blockIdx.x];
+    uint32_t before = 0, all = 0;
+    for (uint32_t t = threadIdx.x; t < gridDim.x; t += SC_THREADS) {
+        const uint32_t p = partial[t];
+        all += p;
+        before += t < blockIdx.x ? p : 0u;
+    }
+    uint32_t run = block_sum(before, ws);
+    all = block_sum(all, ws);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = all;
     for (uint32_t t0 = begin; t0 < end; t0 += SC_TILE) {
         // thread owns SC_IPT consecutive items
         uint32_t v[SC_IPT];
@@ -739,6 +746,25 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint3
     return lo;
 }
 
+// The same search over global memory by one wave in 64-way steps: the lanes
+// probe 64 evenly spaced positions of the current range; the probes with
+// a[p] <= x form a prefix of the lanes (a is non-decreasing), so their count
+// narrows the range 64-fold per step.  All values are wave-uniform.
+__device__ __forceinline__ uint32_t wave_last_le(const uint32_t* __restrict__ a, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n - 1;  // a[lo] <= x; the answer lies in [lo, hi]
+    const uint32_t lane = lane_id();
+    while (hi > lo) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint64_t p = (uint64_t)lo + (uint64_t)step * (lane + 1);
+        const bool le = p <= hi && a[p] <= x;
+        const uint32_t c = (uint32_t)__popcll(__ballot(le));
+        const uint32_t nlo = lo + step * c;
+        hi = (uint32_t)min<uint64_t>(hi, (uint64_t)lo + (uint64_t)step * (c + 1) - 1);
+        lo = nlo;
+    }
+    return lo;
+}
+
 // Position within one record's pairs.
 struct PairCursor {
     uint32_t r, tile_off, tiles_x, tx0, nx, ty0, ty1;
@@ -828,16 +854,18 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
     for (uint32_t k0 = blockIdx.x * EM_ITEMS; k0 < K; k0 += gridDim.x * EM_ITEMS) {
         const uint32_t k1 = min(k0 + EM_ITEMS, K);  // exclusive
         __syncthreads();
-        if (threadIdx.x == 0) {
-            // every record owns at least one pair, so at most EM_ITEMS records
-            // span the block's pairs
-            const uint32_t lo = last_le(inst_off, R, k0);
-            const uint32_t hi = last_le(inst_off, R, k1 - 1);
-            s_lo = lo;
-            s_n = hi - lo + 1;
+        // the first and last record spanning the block's pairs, one wave each
+        // (every record owns at least one pair, so at most EM_ITEMS records
+        // span them)
+        if (threadIdx.x < 64) {
+            const uint32_t lo = wave_last_le(inst_off, R, k0);
+            if (threadIdx.x == 0) s_lo = lo;
+        } else if (threadIdx.x < 128) {
+            const uint32_t hi = wave_last_le(inst_off, R, k1 - 1);
+            if (threadIdx.x == 64) s_n = hi;
         }
         __syncthreads();
-        const uint32_t lo = s_lo, nrec = s_n;
+        const uint32_t lo = s_lo, nrec = s_n - s_lo + 1;
         for (uint32_t i = threadIdx.x; i < nrec; i += EM_THREADS) s_off[i] = inst_off[lo + i];
         __syncthreads();
         const uint32_t kb = k0 + threadIdx.x * EM_RUN;
@@ -2084,8 +2112,7 @@ void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const u
               uint32_t* total, ScanWs ws, hipStream_t s) {
     int nb = scan_blocks(cap);
     k_scan_reduce<<<nb, SC_THREADS, 0, s>>>(in, gather, n_dev, cap, ws.partial);
-    k_scan_partials<<<1, SC_MAX_BLOCKS, 0, s>>>(ws.partial, nb, total);
-    k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, gather, out, n_dev, cap, ws.partial);
+    k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, gather, out, n_dev, cap, ws.partial, total);
 }
 
 // Grid of a pass with digits of db bits: one block per tile of input, up to
@@ -2115,9 +2142,8 @@ static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, cons
         int sb = scan_blocks(count);
         k_fill_u32<<<1, 64, 0, s>>>(ws.partial + SC_MAX_BLOCKS, count, 1);
         k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.partial + SC_MAX_BLOCKS, count, ws.partial);
-        k_scan_partials<<<1, SC_MAX_BLOCKS, 0, s>>>(ws.partial, sb, nullptr);
         k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, ws.partial + SC_MAX_BLOCKS, count,
-                                              ws.partial);
+                                              ws.partial, nullptr);
     }
     k_rs_scatter<DB><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused);
 }
