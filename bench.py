@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (20483.0 * 2.0 * 1024 + 87564.1 * 1024,
-                        "b5243d0e3843fce070f07eb3094553f4325a580b8e24a63371740eb755a977ec"),
-    "render": (20563.4 * 2.0 * 1024 + 8400.0 * 1024,
-               "b5243d0e3843fce070f07eb3094553f4325a580b8e24a63371740eb755a977ec"),
+    "render_backward": (20496.0 * 2.0 * 1024 + 26269.2 * 1024,
+                        "2114ca5356faeef6597ae5b191da0ba1ab834e598c0d3817c67fb2208038c233"),
+    "render": (20790.8 * 2.0 * 1024 + 8400.0 * 1024,
+               "2114ca5356faeef6597ae5b191da0ba1ab834e598c0d3817c67fb2208038c233"),
 }
 
 
