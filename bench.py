@@ -215,7 +215,7 @@ def main():
         mg4.close()
         P4 = sum(c["width"] * c["height"] for c in cams4)
         keyframes = {"ms_per_step": round(dt * 1e3, 3), "mpix_per_s": round(P4 / dt / 1e6, 1),
-                     "tile": f"{S4['tile_w']}x{S4['tile_h']}", "pixels": P4}
+                     "tile": f"{S4['tile_w']}x{S4['tile_h']}", "batch": S4["batch"], "pixels": P4}
         log(f"8 keyframes: {keyframes}")
         del g4, t4, grads4
 

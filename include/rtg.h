@@ -57,7 +57,9 @@ typedef struct rtg_camera {
 /* Rasterizer settings (rtg_default_settings fills the defaults shown).
  *   tile_w x tile_h: screen tile, one of 8x8, 16x16 (default), 32x8; 0x0
  *     asks for the tile chosen by rtg_autotune (16x16 if never tuned);
- *   batch: Gaussians staged per LDS batch; 0 = one per thread of the tile;
+ *   batch: Gaussians staged per LDS batch by the forward and scoring
+ *     kernels: 0 = one per thread of the tile, else 32, 64, 128 or 256, not
+ *     above the tile's pixel count (the backward stages 64 per wave);
  *   T_min = 1e-4: compositing stops before the Gaussian that would take the
  *     transmittance below T_min;
  *   alpha_min = 1/255: a Gaussian whose alpha at a pixel is below it is
@@ -234,10 +236,12 @@ rtg_status rtg_score_graph_launch(rtg_graph *gr, const rtg_camera *cams, int32_t
 rtg_status rtg_score_graph_status(rtg_graph *gr);
 void rtg_score_graph_destroy(rtg_graph *gr);
 
-/* Autotuner: times the candidate tiles {8x8, 16x16, 32x8} (and LDS batch
- * sizes) for `mode` (0 forward, 1 forward+backward, 2 scoring) on the given
- * map and cameras, and writes the fastest into settings->tile_w/tile_h/
- * batch.  Images and gradients do not depend on the choice. */
+/* Autotuner: times `mode` (0 forward, 1 forward+backward, 2 scoring) on the
+ * given map and cameras for each tile in {8x8, 16x16, 32x8} with one splat
+ * staged per thread, then for the fastest tile each smaller staging batch in
+ * {32, 64, 128}; writes the fastest into settings->tile_w/tile_h/batch and
+ * makes it the context's choice for settings with tile 0x0.  Images, scores
+ * and gradients do not depend on the choice.  Synchronises `stream`. */
 rtg_status rtg_autotune(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                         int32_t n_views, int32_t mode, rtg_settings *settings, void *stream);
 

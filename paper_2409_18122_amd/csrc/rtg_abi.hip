@@ -114,15 +114,6 @@ struct Pool {
 
 }  // namespace
 
-struct TuneKey {
-    int mode, w, h, nbucket;
-    bool operator<(const TuneKey& o) const {
-        if (mode != o.mode) return mode < o.mode;
-        if (w != o.w) return w < o.w;
-        if (h != o.h) return h < o.h;
-        return nbucket < o.nbucket;
-    }
-};
 
 constexpr int N_TIMERS = 9;
 
@@ -136,8 +127,7 @@ struct rtg_ctx {
     int cu = 0;
     Pool pool;
     uint32_t* pinned = nullptr;  // small host readback area
-    std::map<TuneKey, std::pair<int, int>> tuned;
-    int last_tw = 16, last_th = 16;
+    int last_tw = 16, last_th = 16, last_batch = 0;
     // measurement
     bool timing = false;
     bool capturing = false;
@@ -271,6 +261,7 @@ rtg_status resolve_settings(rtg_ctx* ctx, const rtg_settings* in, rtg_settings* 
     if (out->tile_w == 0 && out->tile_h == 0) {
         out->tile_w = ctx->last_tw;
         out->tile_h = ctx->last_th;
+        if (out->batch == 0) out->batch = ctx->last_batch;
     }
     if (!valid_tile(out->tile_w, out->tile_h))
         return set_err(RTG_ERR_INVALID, "tile %dx%d not one of 8x8, 16x16, 32x8", out->tile_w, out->tile_h);
@@ -282,7 +273,10 @@ rtg_status resolve_settings(rtg_ctx* ctx, const rtg_settings* in, rtg_settings* 
     if (!(out->T_min > 0.0f) || !(out->T_min < 1.0f)) return set_err(RTG_ERR_INVALID, "need 0 < T_min < 1");
     if (!(out->z_near > 0.0f)) return set_err(RTG_ERR_INVALID, "need z_near > 0");
     if (out->eps2d < 0.0f) return set_err(RTG_ERR_INVALID, "need eps2d >= 0");
-    if (out->batch < 0) return set_err(RTG_ERR_INVALID, "batch < 0");
+    const int b = out->batch;
+    if (b != 0 && ((b != 32 && b != 64 && b != 128 && b != 256) || b > out->tile_w * out->tile_h))
+        return set_err(RTG_ERR_INVALID, "batch %d is not 0 or one of 32, 64, 128, 256 within the tile's %d pixels", b,
+                       out->tile_w * out->tile_h);
     return RTG_OK;
 }
 
@@ -771,7 +765,7 @@ rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera*
     RTG_TRY(enqueue_project(f.get(), true, s));
     RTG_TRY(enqueue_bin(f.get(), true, s));
     RTG_TRY(f->score_part.ensure(ctx, sizeof(double) * std::max<uint32_t>(f->L.hdr.tiles_total, 1)));
-    int grid = score_persistent_blocks(f->st.tile_w, f->st.tile_h);
+    int grid = score_persistent_blocks(f->st.tile_w, f->st.tile_h, f->st.batch);
     Timer tm(ctx, 7, s);
     score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, true, grid, f->views.as<ViewDev>(), f->n_views,
                 f->hdr.as<Header>(), 0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(),
@@ -951,7 +945,7 @@ rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t 
     }
     make_layout(dummy.data(), max_views, st.tile_w, st.tile_h, f->L);
     f->n_views = max_views;
-    gr->grid = score_persistent_blocks(st.tile_w, st.tile_h);
+    gr->grid = score_persistent_blocks(st.tile_w, st.tile_h, st.batch);
     hipError_t e;
     if ((e = hipHostMalloc((void**)&gr->staging, sizeof(ViewDev) * max_views, hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc((void**)&gr->staging_hdr, sizeof(Header), hipHostMallocDefault)) != hipSuccess ||
@@ -1196,40 +1190,64 @@ rtg_status rtg_autotune(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* 
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    float best = 1e30f;
-    int bi = 1;
-    rtg_status rs = RTG_OK;
-    for (int t = 0; t < 3 && rs == RTG_OK; t++) {
-        rtg_settings st = *settings;
-        st.tile_w = tiles[t][0];
-        st.tile_h = tiles[t][1];
-        float ms_best = 1e30f;
-        for (int rep = 0; rep < 3 && rs == RTG_OK; rep++) {
+    // one timed call of `mode` with the given settings (the first of three
+    // warms up; the best of the other two counts)
+    auto time_it = [&](const rtg_settings& st, float& ms_best) -> rtg_status {
+        ms_best = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {
             (void)hipEventRecord(e0, s);
+            rtg_status r = RTG_OK;
             if (mode == 2) {
-                rs = rtg_score_views(ctx, g, cams, n_views, &st, scores.as<double>(), 1, stream);
+                r = rtg_score_views(ctx, g, cams, n_views, &st, scores.as<double>(), 1, stream);
             } else {
                 rtg_frame* f = nullptr;
-                rs = rtg_project(ctx, g, cams, n_views, &st, &f, stream);
-                if (rs == RTG_OK) rs = rtg_bin_sort(ctx, f, nullptr, stream);
-                if (rs == RTG_OK)
-                    rs = rtg_render(ctx, f, im, im + 3 * pix, im + 4 * pix, g->uncert ? im + 5 * pix : nullptr,
-                                    stream);
-                if (rs == RTG_OK && mode == 1) {
+                r = rtg_project(ctx, g, cams, n_views, &st, &f, stream);
+                if (r == RTG_OK) r = rtg_bin_sort(ctx, f, nullptr, stream);
+                if (r == RTG_OK)
+                    r = rtg_render(ctx, f, im, im + 3 * pix, im + 4 * pix, g->uncert ? im + 5 * pix : nullptr, stream);
+                if (r == RTG_OK && mode == 1) {
                     float* d = dimg.as<float>();
-                    rs = rtg_render_backward(ctx, f, d, d + 3 * pix, nullptr, nullptr, &gr, stream);
+                    r = rtg_render_backward(ctx, f, d, d + 3 * pix, nullptr, nullptr, &gr, stream);
                 }
                 rtg_frame_destroy(f);
             }
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
+            if (r != RTG_OK) return r;
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) ms_best = std::min(ms_best, ms);  // first run warms up
+            if (rep > 0) ms_best = std::min(ms_best, ms);
         }
-        if (ms_best < best) {
-            best = ms_best;
+        return RTG_OK;
+    };
+    // the tile first (one splat staged per thread), then the staging batch
+    float best = 1e30f;
+    int bi = 1, bb = 0;
+    rtg_status rs = RTG_OK;
+    for (int t = 0; t < 3 && rs == RTG_OK; t++) {
+        rtg_settings st = *settings;
+        st.tile_w = tiles[t][0];
+        st.tile_h = tiles[t][1];
+        st.batch = 0;
+        float ms;
+        rs = time_it(st, ms);
+        if (rs == RTG_OK && ms < best) {
+            best = ms;
             bi = t;
+        }
+    }
+    static const int batches[3] = {32, 64, 128};
+    for (int k = 0; k < 3 && rs == RTG_OK; k++) {
+        if (batches[k] >= tiles[bi][0] * tiles[bi][1]) break;
+        rtg_settings st = *settings;
+        st.tile_w = tiles[bi][0];
+        st.tile_h = tiles[bi][1];
+        st.batch = batches[k];
+        float ms;
+        rs = time_it(st, ms);
+        if (rs == RTG_OK && ms < best) {
+            best = ms;
+            bb = batches[k];
         }
     }
     (void)hipEventDestroy(e0);
@@ -1237,12 +1255,10 @@ rtg_status rtg_autotune(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* 
     if (rs != RTG_OK) return rs;
     settings->tile_w = tiles[bi][0];
     settings->tile_h = tiles[bi][1];
-    int w = cams[0].width, h = cams[0].height;
-    int nb = 0;
-    for (int64_t n = g->n; n > 1; n >>= 1) nb++;
-    ctx->tuned[TuneKey{mode, w, h, nb}] = {tiles[bi][0], tiles[bi][1]};
+    settings->batch = bb;
     ctx->last_tw = tiles[bi][0];
     ctx->last_th = tiles[bi][1];
+    ctx->last_batch = bb;
     return RTG_OK;
 }
 

@@ -163,7 +163,7 @@ void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent
                  uint32_t tile_begin, uint32_t n_tiles, const uint2* ranges,
                  const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s);
-int score_persistent_blocks(int tw, int th);
+int score_persistent_blocks(int tw, int th, int batch);
 void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, const double* partial,
                   double* scores, hipStream_t s);
 

@@ -966,10 +966,10 @@ constexpr bool FWD_ELL = false, BWD_ELL = false, SCORE_ELL = true;
 template <int NT, bool ELL>
 __device__ __forceinline__ void wave_masks(const uint2* s_pb, const float4* s_g0, const float4* s_g1,
                                            float log2_amin, int cnt, int c0, int c1, int r0, int r1,
-                                           uint64_t (&m)[NT / 64]) {
+                                           uint64_t (&m)[(NT + 63) / 64]) {
     const int lane = (int)lane_id();
 #pragma unroll
-    for (int c = 0; c < NT / 64; c++) {
+    for (int c = 0; c < (NT + 63) / 64; c++) {
         const int e = c * 64 + lane;
         bool hit = e < cnt && box_meets(s_pb[e], c0, c1, r0, r1);
         if (ELL && hit) hit = support_meets_rect(s_g0[e], s_g1[e], log2_amin, c0, c1, r0, r1);
@@ -1019,18 +1019,21 @@ __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __re
     return ad >= (double)amin;
 }
 
-template <int TW, int TH>
+// B splats are staged per batch (B <= TW * TH; threads below B load them).
+template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec,
                                                         Records rec, SetDev st, RenderOut out,
                                                         const uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
+    constexpr int NC = (B + 63) / 64;
+    static_assert(B <= NT, "batch larger than the tile");
     if (flags && *flags) return;
-    __shared__ float4 s_g0[NT], s_g1[NT], s_at[NT];
-    __shared__ float s_u[NT];
-    __shared__ uint32_t s_r[NT];
-    __shared__ uint2 s_pb[NT];
+    __shared__ float4 s_g0[B], s_g1[B], s_at[B];
+    __shared__ float s_u[B];
+    __shared__ uint32_t s_r[B];
+    __shared__ uint2 s_pb[B];
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -1047,10 +1050,10 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dd = 0.0f, uu = 0.0f;
     uint32_t last = 0, ncontrib = 0;
     bool done = !inside;
-    for (uint32_t b = rg.x; b < rg.y; b += NT) {
+    for (uint32_t b = rg.x; b < rg.y; b += B) {
         if (__syncthreads_count(done) == NT) break;
         uint32_t idx = b + threadIdx.x;
-        if (idx < rg.y) {
+        if (threadIdx.x < (uint32_t)B && idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
             s_pb[threadIdx.x] = rec.pbox[r];
@@ -1060,11 +1063,11 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
             s_u[threadIdx.x] = rec.unc[r];
         }
         __syncthreads();
-        const int cnt = (int)min<uint32_t>(NT, rg.y - b);
-        uint64_t m[NT / 64] = {};
-        if (__ballot(!done)) wave_masks<NT, FWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
+        const int cnt = (int)min<uint32_t>(B, rg.y - b);
+        uint64_t m[NC] = {};
+        if (__ballot(!done)) wave_masks<B, FWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
 #pragma unroll
-        for (int c = 0; c < NT / 64; c++) {
+        for (int c = 0; c < NC; c++) {
             uint64_t mm = m[c];
             while (mm && !done) {
                 int ks[FWD_STEP];
@@ -1663,7 +1666,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
 // over pixels of the composited uncertainty sum_i u_i a_i T_i.  Only alpha,
 // transmittance and uncertainty are composited; nothing is written per pixel.
 
-template <int TW, int TH>
+template <int TW, int TH, int B>
 __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views, int n_views, uint32_t tile,
                                                const uint2* __restrict__ ranges,
                                                const uint32_t* __restrict__ inst_rec, const Records& rec,
@@ -1684,10 +1687,11 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
     const uint2 rg = ranges[tile];
     float T = 1.0f, uu = 0.0f;
     bool done = !inside;
-    for (uint32_t b = rg.x; b < rg.y; b += NT) {
+    constexpr int NC = (B + 63) / 64;
+    for (uint32_t b = rg.x; b < rg.y; b += B) {
         if (__syncthreads_count(done) == NT) break;
         uint32_t idx = b + threadIdx.x;
-        if (idx < rg.y) {
+        if (threadIdx.x < (uint32_t)B && idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
             s_pb[threadIdx.x] = rec.pbox[r];
@@ -1696,11 +1700,11 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
             s_u[threadIdx.x] = rec.unc[r];
         }
         __syncthreads();
-        const int cnt = (int)min<uint32_t>(NT, rg.y - b);
-        uint64_t m[NT / 64] = {};
-        if (__ballot(!done)) wave_masks<NT, SCORE_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
+        const int cnt = (int)min<uint32_t>(B, rg.y - b);
+        uint64_t m[NC] = {};
+        if (__ballot(!done)) wave_masks<B, SCORE_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
 #pragma unroll
-        for (int c = 0; c < NT / 64; c++) {
+        for (int c = 0; c < NC; c++) {
             uint64_t mm = m[c];
             while (mm && !done) {
                 int ks[FWD_STEP];
@@ -1752,22 +1756,23 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
     __syncthreads();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restrict__ views, int n_views,
                                                          uint32_t tile_begin, const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec, Records rec,
                                                          SetDev st, double* __restrict__ partial) {
     constexpr int NT = TW * TH;
-    __shared__ float4 s_g0[NT], s_g1[NT];
-    __shared__ float s_u[NT];
-    __shared__ uint32_t s_r[NT];
-    __shared__ uint2 s_pb[NT];
+    static_assert(B <= NT, "batch larger than the tile");
+    __shared__ float4 s_g0[B], s_g1[B];
+    __shared__ float s_u[B];
+    __shared__ uint32_t s_r[B];
+    __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
-    score_one_tile<TW, TH>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial, s_g0,
-                           s_g1, s_u, s_r, s_pb, ws);
+    score_one_tile<TW, TH, B>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial, s_g0,
+                              s_g1, s_u, s_r, s_pb, ws);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __restrict__ views,
                                                               const Header* __restrict__ hdr,
                                                               const uint2* __restrict__ ranges,
@@ -1776,11 +1781,12 @@ __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __r
                                                               uint32_t* __restrict__ queue,
                                                               const uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
+    static_assert(B <= NT, "batch larger than the tile");
     if (*flags) return;  // overflowed binning: results are reported invalid
-    __shared__ float4 s_g0[NT], s_g1[NT];
-    __shared__ float s_u[NT];
-    __shared__ uint32_t s_r[NT];
-    __shared__ uint2 s_pb[NT];
+    __shared__ float4 s_g0[B], s_g1[B];
+    __shared__ float s_u[B];
+    __shared__ uint32_t s_r[B];
+    __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
     __shared__ uint32_t s_item;
     const uint32_t total = hdr->tiles_total;
@@ -1791,7 +1797,8 @@ __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __r
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= total) break;
-        score_one_tile<TW, TH>(views, nv, item, ranges, inst_rec, rec, st, partial, s_g0, s_g1, s_u, s_r, s_pb, ws);
+        score_one_tile<TW, TH, B>(views, nv, item, ranges, inst_rec, rec, st, partial, s_g0, s_g1, s_u, s_r, s_pb,
+                                  ws);
     }
 }
 
@@ -2027,12 +2034,33 @@ inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535u * 16u
     }
 
 
-int score_persistent_blocks(int tw, int th) {
+// Tile and staging batch: batch 0 means one splat per thread of the tile;
+// otherwise one of 32, 64, 128, 256 not above the tile's pixel count
+// (checked by the library before any launch).
+#define RTG_BATCH_DISPATCH(TW_, TH_, B_, CALL)                 \
+    RTG_TILE_DISPATCH(TW_, TH_, {                              \
+        const int bsel_ = batch > 0 ? batch : TW_ * TH_;       \
+        if (bsel_ == 32) {                                     \
+            constexpr int B_ = 32;                             \
+            CALL;                                              \
+        } else if (bsel_ == 64 || TW_ * TH_ == 64) {           \
+            constexpr int B_ = 64;                             \
+            CALL;                                              \
+        } else if (bsel_ == 128) {                             \
+            constexpr int B_ = (TW_ * TH_ >= 128) ? 128 : 64;  \
+            CALL;                                              \
+        } else {                                               \
+            constexpr int B_ = (TW_ * TH_ >= 256) ? 256 : 64;  \
+            CALL;                                              \
+        }                                                      \
+    })
+
+int score_persistent_blocks(int tw, int th, int batch) {
     int per_cu = 0;
     hipError_t e = hipSuccess;
-    RTG_TILE_DISPATCH(TW, TH,
-                      (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_persistent<TW, TH>,
-                                                                        TW * TH, 0)));
+    RTG_BATCH_DISPATCH(TW, TH, B,
+                       (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_persistent<TW, TH, B>,
+                                                                         TW * TH, 0)));
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return per_cu * device_cu_count();
 }
@@ -2187,10 +2215,10 @@ void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_
 void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
                     RenderOut out, const uint32_t* flags, hipStream_t s) {
-    (void)batch;
     if (tiles_total == 0) return;
-    RTG_TILE_DISPATCH(TW, TH, (k_render_fwd<TW, TH><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges,
-                                                                                   inst_rec, rec, st, out, flags)));
+    RTG_BATCH_DISPATCH(TW, TH, B, (k_render_fwd<TW, TH, B><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges,
+                                                                                          inst_rec, rec, st, out,
+                                                                                          flags)));
 }
 
 void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
@@ -2226,7 +2254,7 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
                      const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, const float* T_final,
                      const uint32_t* n_last, const float* d_rgb, const float* d_depth, const float* d_alpha,
                      const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s) {
-    (void)batch;
+    (void)batch;  // the backward stages 64 splats per wave of the tile
     if (tiles_total == 0) return;
     const int nw = backward_waves(tw, th, tiles_total);
 #define RTG_BWD_LAUNCH(TW_, TH_, NW_)                                                                          \
@@ -2260,19 +2288,19 @@ void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent
                  int n_views, const Header* hdr, uint32_t tile_begin, uint32_t n_tiles,
                  const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s) {
-    (void)batch;
     if (persistent) {
         fill_u32(queue, 0u, 1, s);
-        RTG_TILE_DISPATCH(TW, TH,
-                          (k_score_persistent<TW, TH><<<grid_persistent, TW * TH, 0, s>>>(views, hdr, ranges,
-                                                                                          inst_rec, rec, st,
-                                                                                          partial, queue,
-                                                                                          flags)));
+        RTG_BATCH_DISPATCH(TW, TH, B,
+                           (k_score_persistent<TW, TH, B><<<grid_persistent, TW * TH, 0, s>>>(views, hdr, ranges,
+                                                                                             inst_rec, rec, st,
+                                                                                             partial, queue,
+                                                                                             flags)));
     } else {
         if (n_tiles == 0) return;
-        RTG_TILE_DISPATCH(TW, TH,
-                          (k_score_plain<TW, TH><<<n_tiles, TW * TH, 0, s>>>(views, n_views, tile_begin, ranges,
-                                                                             inst_rec, rec, st, partial)));
+        RTG_BATCH_DISPATCH(TW, TH, B,
+                           (k_score_plain<TW, TH, B><<<n_tiles, TW * TH, 0, s>>>(views, n_views, tile_begin,
+                                                                                ranges, inst_rec, rec, st,
+                                                                                partial)));
     }
 }
 

@@ -7,6 +7,8 @@ Tensors must be float32, contiguous and on the context's device.
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 
 import torch
 
@@ -383,14 +385,40 @@ def trajectory_select(ctx, xi, offsets):
     return util, best
 
 
-def autotune(ctx, g, cams, mode, settings=None):
+def tune_key(g, cams, mode):
+    """Cache key of a tuning result: mode, resolution(s), view count and the
+    power-of-two bucket of the Gaussian count."""
+    n = int(g["opacity"].shape[0])
+    res = sorted({(int(c["width"]), int(c["height"])) for c in cams})
+    return f"mode{int(mode)}:" + ",".join(f"{w}x{h}" for w, h in res) + f":v{len(cams)}:n2^{max(n, 1).bit_length() - 1}"
+
+
+def autotune(ctx, g, cams, mode, settings=None, cache=None):
+    """Fastest tile and staging batch for `mode` (0 forward, 1 forward +
+    backward, 2 scoring).  With `cache` (a JSON file path), a result stored
+    under the same tune_key is returned without timing, and a new result is
+    stored there."""
+    out = dict(settings or DEFAULTS)
+    key = tune_key(g, cams, mode)
+    table = {}
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+        if key in table:
+            out.update({k: int(table[key][k]) for k in ("tile_w", "tile_h", "batch")})
+            return out
     st = make_settings(settings)
     gs = make_gaussians(g)
     cs = make_cameras(cams)
     check(lib().rtg_autotune(ctx.handle, ctypes.byref(gs), cs, len(cams), int(mode),
                              ctypes.byref(st), _stream()))
-    out = dict(settings or DEFAULTS)
     out["tile_w"], out["tile_h"], out["batch"] = st.tile_w, st.tile_h, st.batch
+    if cache is not None:
+        table[key] = {"tile_w": st.tile_w, "tile_h": st.tile_h, "batch": st.batch}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
     return out
 
 
@@ -412,5 +440,5 @@ def unpack_images(out, cams):
     return res
 
 
-__all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph", "MapGraph",
+__all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph", "MapGraph", "tune_key",
            "autotune", "to_device", "unpack_images", "RtgError", "DEFAULTS"]

@@ -215,7 +215,7 @@ def test_c5_uneven_graph_full_size(raster, rctx):
         assert abs(got[v] - ref) <= SCORE_TOL_PER_PIXEL * P
 
 
-def test_autotuner_choice_does_not_change_results(raster, rctx):
+def test_autotuner_choice_does_not_change_results(raster, rctx, tmp_path):
     g, cams = scenes.tiny_scene(800, 5, 160, 120)
     dev = raster.to_device(g)
     base, f0 = raster.render(rctx, dev, cams, S())
@@ -224,13 +224,28 @@ def test_autotuner_choice_does_not_change_results(raster, rctx):
         say(f"autotune mode {mode}")
         tuned = raster.autotune(rctx, dev, cams, mode, S())
         assert (tuned["tile_w"], tuned["tile_h"]) in ((8, 8), (16, 16), (32, 8))
+        assert tuned["batch"] in (0, 32, 64, 128) and tuned["batch"] < tuned["tile_w"] * tuned["tile_h"]
         out, f = raster.render(rctx, dev, cams, tuned)
         for k in base:
             assert torch.equal(base[k], out[k]), (mode, k)
         f.close()
-    # settings 0x0 take the context's tuned tile
+    # settings 0x0 take the context's tuned tile and batch
     out, f = raster.render(rctx, dev, cams, dict(S(), tile_w=0, tile_h=0))
     assert f.info()["tile_w"] == tuned["tile_w"]
     for k in base:
         assert torch.equal(base[k], out[k])
     f.close()
+    # the JSON cache: the first call tunes and stores, the second returns the
+    # stored choice, keyed by mode, resolution, view count and N bucket
+    cache = str(tmp_path / "tune.json")
+    first = raster.autotune(rctx, dev, cams, 1, S(), cache=cache)
+    import json
+    with open(cache) as fh:
+        table = json.load(fh)
+    key = raster.tune_key(g, cams, 1)
+    assert table[key] == {"tile_w": first["tile_w"], "tile_h": first["tile_h"], "batch": first["batch"]}
+    table[key] = {"tile_w": 32, "tile_h": 8, "batch": 64}  # a stored entry wins without timing
+    with open(cache, "w") as fh:
+        json.dump(table, fh)
+    again = raster.autotune(rctx, dev, cams, 1, S(), cache=cache)
+    assert (again["tile_w"], again["tile_h"], again["batch"]) == (32, 8, 64)

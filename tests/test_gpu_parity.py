@@ -71,16 +71,32 @@ def test_tiny_scenes_vs_brute_force(raster, rctx, n, size):
         assert_images_close(imgs[0], r, label=f"n={n} {size} {tile}")
 
 
-def test_tile_size_invariance(raster, rctx):
+BATCHES = {(8, 8): (0, 32, 64), (16, 16): (0, 32, 64, 128, 256), (32, 8): (0, 32, 64, 128, 256)}
+
+
+def test_tile_and_batch_invariance(raster, rctx):
     g, cams = scenes.config1()
     outs = []
     for tile in TILES:
-        say(f"C1 tile invariance {tile}")
-        imgs, _, _, _ = gpu_render(raster, rctx, g, cams, S(tile))
-        outs.append(imgs[0])
-    # the per-pixel sequence of splats does not depend on the tile, so the
-    # float32 results are identical
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+        for batch in BATCHES[tile]:
+            say(f"C1 tile/batch invariance {tile} batch {batch}")
+            imgs, _, _, _ = gpu_render(raster, rctx, g, cams, S(tile, batch=batch))
+            outs.append(imgs[0])
+    # the per-pixel sequence of splats does not depend on the tile or the
+    # staging batch, so the float32 results are identical
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    # scores too (binary64 per-tile partials are summed in a fixed order per
+    # tile size, so compare within a tile size)
+    g3, cams3 = scenes.config3(n=20_000, n_views=3, width=96, height=64)
+    dev3 = raster.to_device(g3)
+    for tile in TILES:
+        ref = None
+        for batch in BATCHES[tile]:
+            sc = raster.score_views(rctx, dev3, cams3, S(tile, batch=batch), persistent=True).cpu().numpy()
+            if ref is None:
+                ref = sc
+            assert np.array_equal(sc, ref), (tile, batch)
 
 
 def test_c2_forward_full_size(raster, rctx):
@@ -348,6 +364,9 @@ def test_invalid_arguments(raster, rctx):
     nan = [dict(cams[0], fx=float("nan"))]
     with pytest.raises(raster.RtgError):
         raster.Frame(rctx, dev, nan, S())
+    for tile, batch in (((16, 16), 48), ((16, 16), 512), ((8, 8), 128), ((16, 16), -1)):
+        with pytest.raises(raster.RtgError):
+            raster.Frame(rctx, dev, cams, S(tile, batch=batch))
 
 
 # ------------------------------------------------------- captured mapping step
