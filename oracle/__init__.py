@@ -64,7 +64,7 @@ def lib():
         L.rtgo_keys.restype = ctypes.c_int
         L.rtgo_loss.argtypes = [i64, p, p, p, p, ctypes.c_double, p, p]
         L.rtgo_loss.restype = ctypes.c_double
-        L.rtgo_score.argtypes = [i64] + [p] * 7 + [ctypes.c_int, p, ctypes.c_int, ctypes.c_int, p]
+        L.rtgo_score.argtypes = [i64] + [p] * 7 + [ctypes.c_int, p, ctypes.c_int, ctypes.c_int, ctypes.c_int, p]
         L.rtgo_score.restype = ctypes.c_int
         L.rtgo_adjoint.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 2 + [p] * 10)
         L.rtgo_adjoint.restype = ctypes.c_int
@@ -211,13 +211,15 @@ def loss(rgb, depth, target_rgb, target_depth, w_depth=0.5):
     return float(L), grgb, gdep
 
 
-def score(scene, cams, settings, tile=(16, 16)):
+def score(scene, cams, settings, tile=(16, 16), mode=0):
+    """Per-view score: mode 0 the rendered trace proxy sum_p sum_i u_i a_i T_i,
+    mode 1 the binary-J trace sum_p sum_{i contributing at p} u_i."""
     g = _G(scene)
     ca = np.ascontiguousarray(np.concatenate([cam_array(c) for c in cams]))
     sa = set_array(settings)
     out = np.zeros(len(cams))
     rc = lib().rtgo_score(g.n, *g.all(), _ptr(ca), len(cams), _ptr(sa), int(tile[0]),
-                          int(tile[1]), _ptr(out))
+                          int(tile[1]), int(mode), _ptr(out))
     if rc:
         raise MemoryError("oracle score failed")
     return out

@@ -362,6 +362,7 @@ typedef struct {
 
 typedef struct {
     double out[6]; /* r, g, b, depth, alpha, uncertainty */
+    double ub;     /* sum of u over the contributing Gaussians (binary-J trace) */
     double T;      /* final transmittance */
     int ncontrib;  /* Gaussians that contributed */
     int nevents;   /* near-threshold decisions (may exceed OEV_CAP) */
@@ -401,7 +402,7 @@ static void composite(const oview *V, const int64_t *list, int64_t n, int u, int
 {
     const double *col = V->g.colors, *unc = V->g.uncert;
     int64_t N = V->g.n;
-    double T = 1.0, C0 = 0.0, C1 = 0.0, C2 = 0.0, D = 0.0, U = 0.0;
+    double T = 1.0, C0 = 0.0, C1 = 0.0, C2 = 0.0, D = 0.0, U = 0.0, UB = 0.0;
     int nc = 0, ne = 0;
     for (int64_t k = 0; k < n; k++) {
         int64_t i = list[k];
@@ -429,11 +430,13 @@ static void composite(const oview *V, const int64_t *list, int64_t n, int u, int
         C2 += col[2 * N + i] * w;
         D += V->P[i].depth * w;
         U += unc[i] * w;
+        UB += unc[i];
         T = Tn;
         nc++;
     }
     r->out[0] = C0; r->out[1] = C1; r->out[2] = C2;
     r->out[3] = D; r->out[4] = 1.0 - T; r->out[5] = U;
+    r->ub = UB;
     r->T = T;
     r->ncontrib = nc;
     r->nevents = ne;
@@ -706,9 +709,14 @@ double rtgo_loss(int64_t P, const double *rgb, const double *dep, const double *
 
 /* Sum over pixels of the composited uncertainty for each of nv cameras
  * (cams: nv x 18).  The per-view sum is taken in pixel order. */
+/* View scores (Sec. IV-A eq. (7)) as sums over pixels, per pixel p:
+ *   mode 0: the rendered trace proxy U(p) = sum_i u_i a_i T_i;
+ *   mode 1: the binary-J trace, the same sum with the Jacobian replaced by
+ *           its sparsity pattern: sum of u_i over the Gaussians i that
+ *           contribute to p (pass the alpha_min test, before termination). */
 int rtgo_score(int64_t n, const double *means, const double *ls, const double *q,
                const double *o, const double *colors, const double *unc,
-               const double *cams, int nv, const double *set, int tw, int th, double *scores)
+               const double *cams, int nv, const double *set, int tw, int th, int mode, double *scores)
 {
     ogauss g;
     gauss_from(&g, n, means, ls, q, o, colors, unc);
@@ -729,7 +737,7 @@ int rtgo_score(int64_t n, const double *means, const double *ls, const double *q
             int64_t t = (int64_t)(vv / th) * T.ntx + u / tw;
             opix r;
             composite(&V, T.items + T.start[t], T.start[t + 1] - T.start[t], u, vv, NULL, 0, &r);
-            row[pix] = r.out[5];
+            row[pix] = mode ? r.ub : r.out[5];
         }
         double s = 0.0;
         for (int64_t p = 0; p < P; p++) s += row[p];

@@ -478,6 +478,60 @@ def test_score_single_gaussian_integral():
     assert abs(s - integral) <= AMIN * perimeter + 1e-6 * integral
 
 
+# Binary-J trace (eq. (7) with the Jacobian replaced by its sparsity
+# pattern): per pixel, the sum of u over the Gaussians that contribute.
+
+def test_binary_score_single_gaussian_footprint():
+    # on the optical axis with identity rotation the support is the ellipse
+    # ((u-cx)/ax)^2 + ((v-cy)/ay)^2 <= 2 ln(o/amin); each pixel inside adds u
+    z, o, u = 2.5, 0.6, 0.37
+    ls = (-1.2, -1.7, -2.0)
+    c = cam(w=200, h=150, fx=180.0, fy=170.0, cx=97.3, cy=71.8)
+    g = one_gaussian((0, 0, z), ls, opacity=o, unc=u)
+    ax = 180.0 * math.exp(ls[0]) / z
+    ay = 170.0 * math.exp(ls[1]) / z
+    rho2 = 2.0 * math.log(o / AMIN)
+    U, V = np.meshgrid(np.arange(200), np.arange(150))
+    q = ((U - 97.3) / ax) ** 2 + ((V - 71.8) / ay) ** 2
+    assert np.min(np.abs(q - rho2)) > 1e-6
+    n_inside = int((q <= rho2).sum())
+    assert oracle.score(g, [c], S(), mode=1)[0] == pytest.approx(u * n_inside, rel=1e-12)
+
+
+def test_binary_score_equal_alpha_stack():
+    # five coincident Gaussians (equal depth, ties by index): at a pixel with
+    # alpha a >= alpha_min each, exactly k = min(5, floor(ln T_min / ln(1 - a)))
+    # contribute, the first k in index order
+    z, o = 2.0, 0.95
+    c = cam(w=48, h=40, fx=60.0, fy=60.0, cx=23.5, cy=19.5)
+    us = [0.11, 0.23, 0.35, 0.47, 0.59]
+    g = stack(*[one_gaussian((0, 0, z), (-1.5,) * 3, opacity=o, unc=u) for u in us])
+    sig = 60.0 * math.exp(-1.5) / z
+    U, V = np.meshgrid(np.arange(48), np.arange(40))
+    G = np.exp(-0.5 * ((U - 23.5) ** 2 + (V - 19.5) ** 2) / sig ** 2)
+    a = np.minimum(AMAX, o * G)
+    ratio = np.log(TMIN) / np.log1p(-a)
+    keep = a >= AMIN
+    assert np.min(np.abs(ratio - np.round(ratio))[keep]) > 1e-6 and np.min(np.abs(a - AMIN)) > 1e-9
+    k = np.where(keep, np.minimum(5, np.floor(ratio)), 0).astype(int)
+    cum = np.concatenate([[0.0], np.cumsum(us)])
+    assert (k == 3).any() and (k == 5).any()
+    want = cum[k].sum()
+    assert oracle.score(g, [c], S(), mode=1)[0] == pytest.approx(want, rel=1e-12)
+
+
+def test_binary_score_relations():
+    g, cams = scenes.config3(n=3000, n_views=3, width=64, height=48)
+    rendered = oracle.score(g, cams, S())
+    binary = oracle.score(g, cams, S(), mode=1)
+    assert np.all(binary >= rendered) and np.all(binary > 0)
+    # u = 1: the binary score counts contributing (pixel, Gaussian) pairs
+    g1 = dict(g, uncert=np.ones_like(g["uncert"]))
+    b1 = oracle.score(g1, cams, S(), mode=1)
+    for v, c in enumerate(cams):
+        assert b1[v] == oracle.render(g1, c, S())["ncontrib"].sum()
+
+
 def test_score_batch_invariance():
     g, cams = scenes.config3(n=3000, n_views=4, width=64, height=48)
     batch = oracle.score(g, cams, S())
