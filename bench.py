@@ -255,6 +255,18 @@ def main():
         views["256_uneven_graph"] = round(len(cams5) / dt, 1)
         log(f"256 views graph: {dt * 1e3:.2f} ms")
         gr.close()
+        # the binary-J trace (sum of u over contributing Gaussians), same pipeline
+        grb = raster.ScoreGraph(ctx, g5, 256, 640, 480, S, probe=cams5, mode="binary")
+        grb.launch(cams5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            grb.launch(cams5)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t0) / reps
+        assert grb.status(), "graph capacity overflow"
+        views["256_uneven_graph_binary_j"] = round(len(cams5) / dtb, 1)
+        grb.close()
         f5 = raster.Frame(ctx, g5, cams5, S)
         f5.bin_sort()
         f5.render(("alpha",))

@@ -181,23 +181,28 @@ rtg_status rtg_frame_export(rtg_ctx *ctx, rtg_frame *f, uint64_t *keys, uint32_t
  * tiles, [3] total pixels, [4] tile_w, [5] tile_h. */
 rtg_status rtg_frame_info(const rtg_frame *f, int64_t info[6]);
 
-/* View scoring by the rendered form of the trace proxy of Sec. IV-A eq. (7):
- *   score_v = sum over pixels p of view v of sum_i u_i a_i(p) T_i(p),
- * i.e. the per-Gaussian uncertainty composited like a colour channel and
- * summed over the image (binary64).  scores: device array of n_views
- * doubles.  persistent = 1: all views go through one projection, one sort
- * and one persistent compositing launch; persistent = 0: a plain loop of
- * per-view launches (for comparison).  Results are identical either way.
- * Synchronises `stream` to size buffers. */
+/* View scoring by the trace proxy of Sec. IV-A eq. (7), summed over the
+ * pixels p of view v in binary64:
+ *   mode 0 (rendered): score_v = sum_p sum_i u_i a_i(p) T_i(p), the
+ *     per-Gaussian uncertainty composited like a colour channel;
+ *   mode 1 (binary-J): score_v = sum_p sum of u_i over the Gaussians i that
+ *     contribute at p (pass the alpha_min test before termination) - the
+ *     Jacobian in the trace replaced by its binary sparsity pattern.
+ * scores: device array of n_views doubles.  persistent = 1: all views go
+ * through one projection, one sort and one persistent compositing launch;
+ * persistent = 0: a plain loop of per-view launches (for comparison).
+ * Results are identical either way.  A mode other than 0 or 1 is
+ * RTG_ERR_INVALID.  Synchronises `stream` to size buffers. */
 rtg_status rtg_score_views(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                            int32_t n_views, const rtg_settings *settings, double *scores,
-                           int32_t persistent, void *stream);
+                           int32_t persistent, int32_t mode, void *stream);
 
 /* Captured scoring pipeline: the whole batched path of rtg_score_views in
  * one hipGraph with device-side sizes, replayed for new poses.
  * create: fixes the map g (its arrays must stay valid and unchanged), at
  * most max_views views, each at most max_width x max_height pixels, and the
- * settings.  Buffers have fixed capacities: the (tile, Gaussian) pair
+ * settings, and the score mode (as in rtg_score_views).  Buffers have
+ * fixed capacities: the (tile, Gaussian) pair
  * capacity is settings->max_instances if > 0, else twice the count measured
  * by an eager pass over the n_probe `probe` cameras, scaled to max_views
  * (probe must then be non-NULL).  launch: uploads cams (host, n_views <=
@@ -207,8 +212,9 @@ rtg_status rtg_score_views(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camer
  * it (its scores are then invalid; create a graph with larger capacity). */
 rtg_status rtg_score_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, int32_t max_views,
                                   int32_t max_width, int32_t max_height,
-                                  const rtg_settings *settings, const rtg_camera *probe,
-                                  int32_t n_probe, rtg_graph **out, void *stream);
+                                  const rtg_settings *settings, int32_t mode,
+                                  const rtg_camera *probe, int32_t n_probe, rtg_graph **out,
+                                  void *stream);
 /* Captured mapping iteration for fixed keyframes: the gradient of the
  * mapping problem of Sec. III eq. (2) with the L1 part of eq. (4), as one
  * hipGraph replayed once per optimiser iteration.  One replay runs

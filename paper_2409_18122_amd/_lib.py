@@ -59,8 +59,8 @@ SIGNATURES = {
     "rtg_frame_export": (i32, [vp, vp, vp, vp, vp, vp]),
     "rtg_frame_info": (i32, [vp, _c.POINTER(i64)]),
     "rtg_score_views": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, _c.POINTER(Settings),
-                              vp, i32, vp]),
-    "rtg_score_graph_create": (i32, [vp, _c.POINTER(Gaussians), i32, i32, i32, _c.POINTER(Settings),
+                              vp, i32, i32, vp]),
+    "rtg_score_graph_create": (i32, [vp, _c.POINTER(Gaussians), i32, i32, i32, _c.POINTER(Settings), i32,
                                      _c.POINTER(Camera), i32, _c.POINTER(vp), vp]),
     "rtg_score_graph_launch": (i32, [vp, _c.POINTER(Camera), i32, vp, vp]),
     "rtg_score_graph_status": (i32, [vp]),

@@ -758,7 +758,7 @@ rtg_status rtg_frame_info(const rtg_frame* f, int64_t info[6]) {
 namespace {
 
 rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int n_views,
-                         const rtg_settings* settings, double* scores, hipStream_t s) {
+                         const rtg_settings* settings, int mode, double* scores, hipStream_t s) {
     rtg_frame* fp = nullptr;
     RTG_TRY(new_frame(ctx, g, cams, n_views, settings, &fp, s));
     std::unique_ptr<rtg_frame> f(fp);
@@ -767,7 +767,7 @@ rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera*
     RTG_TRY(f->score_part.ensure(ctx, sizeof(double) * std::max<uint32_t>(f->L.hdr.tiles_total, 1)));
     int grid = score_persistent_blocks(f->st.tile_w, f->st.tile_h, f->st.batch);
     Timer tm(ctx, 7, s);
-    score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, true, grid, f->views.as<ViewDev>(), f->n_views,
+    score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, mode, true, grid, f->views.as<ViewDev>(), f->n_views,
                 f->hdr.as<Header>(), 0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(),
                 to_dev(f->st), f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
     score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), n_views, f->score_part.as<double>(), scores, s);
@@ -775,7 +775,7 @@ rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera*
 }
 
 rtg_status score_plain(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int n_views,
-                       const rtg_settings* settings, double* scores, hipStream_t s) {
+                       const rtg_settings* settings, int mode, double* scores, hipStream_t s) {
     for (int v = 0; v < n_views; v++) {
         rtg_frame* fp = nullptr;
         RTG_TRY(new_frame(ctx, g, cams + v, 1, settings, &fp, s));
@@ -784,7 +784,8 @@ rtg_status score_plain(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* c
         RTG_TRY(enqueue_bin(f.get(), true, s));
         RTG_TRY(f->score_part.ensure(ctx, sizeof(double) * std::max<uint32_t>(f->L.hdr.tiles_total, 1)));
         Timer tm(ctx, 7, s);
-        score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, false, 0, f->views.as<ViewDev>(), 1, f->hdr.as<Header>(),
+        score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, mode, false, 0, f->views.as<ViewDev>(), 1,
+                    f->hdr.as<Header>(),
                     0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
                     f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
         score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), 1, f->score_part.as<double>(), scores + v, s);
@@ -797,14 +798,15 @@ rtg_status score_plain(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* c
 
 extern "C" rtg_status rtg_score_views(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams,
                                       int32_t n_views, const rtg_settings* settings, double* scores,
-                                      int32_t persistent, void* stream) {
+                                      int32_t persistent, int32_t mode, void* stream) {
     RTG_TRY(ctx_ok(ctx));
     RTG_TRY(check_gauss(g, false, true));
     RTG_TRY(check_cams(cams, n_views));
     if (!scores) return set_err(RTG_ERR_INVALID, "scores is NULL");
+    if (mode != 0 && mode != 1) return set_err(RTG_ERR_INVALID, "score mode %d not in {0, 1}", mode);
     hipStream_t s = (hipStream_t)stream;
-    return persistent ? score_batched(ctx, g, cams, n_views, settings, scores, s)
-                      : score_plain(ctx, g, cams, n_views, settings, scores, s);
+    return persistent ? score_batched(ctx, g, cams, n_views, settings, mode, scores, s)
+                      : score_plain(ctx, g, cams, n_views, settings, mode, scores, s);
 }
 
 // ================================================================== graph
@@ -823,6 +825,7 @@ struct rtg_graph {
     uint32_t* flag_host = nullptr;  // pinned, written by the graph
     Buf scores;
     int grid = 0;
+    int mode = 0;  // scoring: 0 rendered proxy, 1 binary-J trace
     int last_views = 0;
     bool launched = false;
 };
@@ -848,7 +851,8 @@ rtg_status enqueue_graph_body(rtg_graph* gr, hipStream_t s) {
     rtg_frame* f = gr->f.get();
     RTG_TRY(enqueue_project(f, false, s));
     RTG_TRY(enqueue_bin(f, false, s));
-    score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, true, gr->grid, f->views.as<ViewDev>(), gr->max_views,
+    score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, gr->mode, true, gr->grid, f->views.as<ViewDev>(),
+                gr->max_views,
                 f->hdr.as<Header>(), 0, 0, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
                 f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
     score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), gr->max_views, f->score_part.as<double>(),
@@ -873,11 +877,12 @@ rtg_status graph_layout(rtg_graph* gr, const rtg_camera* cams, int n_views) {
 extern "C" {
 
 rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t max_views, int32_t max_width,
-                                  int32_t max_height, const rtg_settings* settings, const rtg_camera* probe,
-                                  int32_t n_probe, rtg_graph** out, void* stream) {
+                                  int32_t max_height, const rtg_settings* settings, int32_t mode,
+                                  const rtg_camera* probe, int32_t n_probe, rtg_graph** out, void* stream) {
     if (!out) return set_err(RTG_ERR_INVALID, "out is NULL");
     *out = nullptr;
     RTG_TRY(ctx_ok(ctx));
+    if (mode != 0 && mode != 1) return set_err(RTG_ERR_INVALID, "score mode %d not in {0, 1}", mode);
     RTG_TRY(check_gauss(g, false, true));
     if (max_views < 1 || max_views > MAX_VIEWS) return set_err(RTG_ERR_INVALID, "max_views = %d", max_views);
     if (max_width < 1 || max_height < 1 || max_width > 16384 || max_height > 16384)
@@ -908,6 +913,7 @@ rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t 
     rtg_graph* gr = new (std::nothrow) rtg_graph();
     if (!gr) return set_err(RTG_ERR_OOM, "host allocation failed");
     gr->ctx = ctx;
+    gr->mode = mode;
     gr->max_views = max_views;
     gr->max_w = max_width;
     gr->max_h = max_height;
@@ -1198,7 +1204,7 @@ rtg_status rtg_autotune(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* 
             (void)hipEventRecord(e0, s);
             rtg_status r = RTG_OK;
             if (mode == 2) {
-                r = rtg_score_views(ctx, g, cams, n_views, &st, scores.as<double>(), 1, stream);
+                r = rtg_score_views(ctx, g, cams, n_views, &st, scores.as<double>(), 1, 0, stream);
             } else {
                 rtg_frame* f = nullptr;
                 r = rtg_project(ctx, g, cams, n_views, &st, &f, stream);

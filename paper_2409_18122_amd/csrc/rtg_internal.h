@@ -155,10 +155,11 @@ void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const 
                       float* d_colors, const uint32_t* flags, hipStream_t s);
 
 // Scoring: per-(view, tile) partial sums of the composited uncertainty.
+// mode 0 sums u a T per pixel, mode 1 sums u over the contributing splats.
 // persistent: a fixed grid pulls tiles from an atomic queue (counter must be
 // zeroed; done inside).  Otherwise one workgroup per tile of [tile_begin,
 // tile_begin + n_tiles).
-void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent,
+void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_persistent,
                  const ViewDev* views, int n_views, const Header* hdr,
                  uint32_t tile_begin, uint32_t n_tiles, const uint2* ranges,
                  const uint32_t* inst_rec, Records rec, SetDev st, double* partial,

@@ -1666,11 +1666,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
 // over pixels of the composited uncertainty sum_i u_i a_i T_i.  Only alpha,
 // transmittance and uncertainty are composited; nothing is written per pixel.
 
+// mode 0: sum_i u_i a_i T_i (the rendered proxy); mode 1: sum of u_i over
+// the contributing splats (the binary-J trace).
 template <int TW, int TH, int B>
 __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views, int n_views, uint32_t tile,
                                                const uint2* __restrict__ ranges,
                                                const uint32_t* __restrict__ inst_rec, const Records& rec,
-                                               const SetDev& st, double* __restrict__ partial,
+                                               const SetDev& st, int mode, double* __restrict__ partial,
                                                float4* s_g0, float4* s_g1, float* s_u, uint32_t* s_r,
                                                uint2* s_pb, double* ws) {
     constexpr int NT = TW * TH;
@@ -1739,7 +1741,8 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
                     const bool use = take && !stop;
                     done = done || stop;
                     const float uk = s_u[k];
-                    uu = use ? fmaf(uk, a * T, uu) : uu;
+                    const float wk = mode ? 1.0f : a * T;
+                    uu = use ? fmaf(uk, wk, uu) : uu;
                     T = use ? Tn : T;
                 }
             }
@@ -1760,7 +1763,7 @@ template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restrict__ views, int n_views,
                                                          uint32_t tile_begin, const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec, Records rec,
-                                                         SetDev st, double* __restrict__ partial) {
+                                                         SetDev st, int mode, double* __restrict__ partial) {
     constexpr int NT = TW * TH;
     static_assert(B <= NT, "batch larger than the tile");
     __shared__ float4 s_g0[B], s_g1[B];
@@ -1768,8 +1771,8 @@ __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restri
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
-    score_one_tile<TW, TH, B>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial, s_g0,
-                              s_g1, s_u, s_r, s_pb, ws);
+    score_one_tile<TW, TH, B>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, mode, partial,
+                              s_g0, s_g1, s_u, s_r, s_pb, ws);
 }
 
 template <int TW, int TH, int B>
@@ -1777,7 +1780,7 @@ __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __r
                                                               const Header* __restrict__ hdr,
                                                               const uint2* __restrict__ ranges,
                                                               const uint32_t* __restrict__ inst_rec, Records rec,
-                                                              SetDev st, double* __restrict__ partial,
+                                                              SetDev st, int mode, double* __restrict__ partial,
                                                               uint32_t* __restrict__ queue,
                                                               const uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
@@ -1797,8 +1800,8 @@ __global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __r
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= total) break;
-        score_one_tile<TW, TH, B>(views, nv, item, ranges, inst_rec, rec, st, partial, s_g0, s_g1, s_u, s_r, s_pb,
-                                  ws);
+        score_one_tile<TW, TH, B>(views, nv, item, ranges, inst_rec, rec, st, mode, partial, s_g0, s_g1, s_u, s_r,
+                                  s_pb, ws);
     }
 }
 
@@ -2284,7 +2287,7 @@ void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const 
                                                      d_log_scales, d_quats, d_opacity, d_colors, flags);
 }
 
-void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent, const ViewDev* views,
+void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_persistent, const ViewDev* views,
                  int n_views, const Header* hdr, uint32_t tile_begin, uint32_t n_tiles,
                  const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s) {
@@ -2293,13 +2296,13 @@ void score_tiles(int tw, int th, int batch, bool persistent, int grid_persistent
         RTG_BATCH_DISPATCH(TW, TH, B,
                            (k_score_persistent<TW, TH, B><<<grid_persistent, TW * TH, 0, s>>>(views, hdr, ranges,
                                                                                              inst_rec, rec, st,
-                                                                                             partial, queue,
+                                                                                             mode, partial, queue,
                                                                                              flags)));
     } else {
         if (n_tiles == 0) return;
         RTG_BATCH_DISPATCH(TW, TH, B,
                            (k_score_plain<TW, TH, B><<<n_tiles, TW * TH, 0, s>>>(views, n_views, tile_begin,
-                                                                                ranges, inst_rec, rec, st,
+                                                                                ranges, inst_rec, rec, st, mode,
                                                                                 partial)));
     }
 }

@@ -248,21 +248,26 @@ def rasterize(rctx, g, cams, settings=None):
                              g.get("uncert"), cams, settings, rctx)
 
 
-def score_views(ctx, g, cams, settings=None, persistent=True):
-    """Per-view sum of the composited uncertainty (float64 tensor of len(cams))."""
+SCORE_MODES = {"rendered": 0, "binary": 1}
+
+
+def score_views(ctx, g, cams, settings=None, persistent=True, mode="rendered"):
+    """Per-view score (float64 tensor of len(cams)): mode "rendered" sums the
+    composited uncertainty sum_i u_i a_i T_i over the pixels, "binary" sums u_i
+    over the contributing Gaussians of each pixel (the binary-J trace)."""
     gs = make_gaussians(g)
     cs = make_cameras(cams)
     st = make_settings(settings)
     out = torch.empty(len(cams), device=g["means"].device, dtype=torch.float64)
     check(lib().rtg_score_views(ctx.handle, ctypes.byref(gs), cs, len(cams), ctypes.byref(st),
-                                _ptr(out), int(bool(persistent)), _stream()))
+                                _ptr(out), int(bool(persistent)), SCORE_MODES[mode], _stream()))
     return out
 
 
 class ScoreGraph:
     """The batched scoring pipeline captured once, replayed for new poses."""
 
-    def __init__(self, ctx, g, max_views, max_width, max_height, settings=None, probe=None):
+    def __init__(self, ctx, g, max_views, max_width, max_height, settings=None, probe=None, mode="rendered"):
         self.ctx = ctx
         self._g = g
         self._gs = make_gaussians(g)
@@ -271,7 +276,7 @@ class ScoreGraph:
         h = ctypes.c_void_p()
         check(lib().rtg_score_graph_create(ctx.handle, ctypes.byref(self._gs), int(max_views),
                                            int(max_width), int(max_height),
-                                           ctypes.byref(self.settings), pr,
+                                           ctypes.byref(self.settings), SCORE_MODES[mode], pr,
                                            len(probe) if probe else 0, ctypes.byref(h), _stream()))
         self.handle = h
 

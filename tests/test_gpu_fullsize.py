@@ -203,6 +203,13 @@ def test_c5_uneven_graph_full_size(raster, rctx):
     eager = raster.score_views(rctx, dev, cams, S(), persistent=True).cpu().numpy()
     assert np.array_equal(got, eager)
     gr.close()
+    say("C5: binary-J graph over the same views")
+    grb = raster.ScoreGraph(rctx, dev, 256, 640, 480, S(), probe=cams, mode="binary")
+    gotb = grb.launch(cams).cpu().numpy()
+    assert grb.status()
+    grb.close()
+    eagerb = raster.score_views(rctx, dev, cams, S(), persistent=True, mode="binary").cpu().numpy()
+    assert np.array_equal(gotb, eagerb) and np.all(gotb >= got)
     sizes = {}
     for v, c in enumerate(cams):
         sizes.setdefault(c["width"], v)
@@ -213,6 +220,9 @@ def test_c5_uneven_graph_full_size(raster, rctx):
         say(f"C5 view {v} ({c['width']}x{c['height']}): gpu {got[v]:.6f} oracle {ref:.6f} "
             f"rel {abs(got[v] - ref) / max(abs(ref), 1e-30):.2e}")
         assert abs(got[v] - ref) <= SCORE_TOL_PER_PIXEL * P
+        refb = oracle.score(g, [c], S(), mode=1)[0]
+        say(f"C5 view {v} binary-J: gpu {gotb[v]:.4f} oracle {refb:.4f} diff {abs(gotb[v] - refb):.3g}")
+        assert abs(gotb[v] - refb) <= SCORE_TOL_PER_PIXEL * P
 
 
 def test_autotuner_choice_does_not_change_results(raster, rctx, tmp_path):

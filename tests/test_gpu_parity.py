@@ -277,6 +277,38 @@ def test_c3_scores(raster, rctx):
     assert alone[0] == batched[17]
 
 
+def test_c3_binary_j_scores(raster, rctx):
+    # the binary-J trace: per pixel the sum of u over the contributing
+    # Gaussians.  A termination decision that flips between binary32 and
+    # binary64 moves a pixel by one u (<= 1); such flips are rare (~1e-5 of
+    # pixels), inside the per-pixel tolerance
+    g, cams = scenes.config3(n=200_000, n_views=16)
+    say("C3-like binary-J scoring, 200k Gaussians, 16 views 320x240")
+    dev = raster.to_device(g)
+    batched = raster.score_views(rctx, dev, cams, S(), persistent=True, mode="binary").cpu().numpy()
+    plain = raster.score_views(rctx, dev, cams, S(), persistent=False, mode="binary").cpu().numpy()
+    assert np.array_equal(batched, plain)
+    rendered = raster.score_views(rctx, dev, cams, S(), persistent=True).cpu().numpy()
+    assert np.all(batched >= rendered)
+    ref = oracle.score(g, [cams[v] for v in (0, 7, 15)], S(), mode=1)
+    for j, v in enumerate((0, 7, 15)):
+        P = cams[v]["width"] * cams[v]["height"]
+        say(f"binary view {v}: gpu {batched[v]:.4f} oracle {ref[j]:.4f} diff {abs(batched[v] - ref[j]):.3g}")
+        assert abs(batched[v] - ref[j]) <= SCORE_TOL_PER_PIXEL * P
+    # captured graph, same mode
+    gr = raster.ScoreGraph(rctx, dev, 16, 320, 240, S(), probe=cams, mode="binary")
+    got = gr.launch(cams).cpu().numpy()
+    assert gr.status() and np.array_equal(got, batched)
+    gr.close()
+    # a mode other than 0 or 1 is an argument error
+    import ctypes
+    st = raster.make_settings(S())
+    out = torch.empty(16, device="cuda", dtype=torch.float64)
+    rc = raster.lib().rtg_score_views(rctx.handle, ctypes.byref(raster.make_gaussians(dev)),
+                                      raster.make_cameras(cams), 16, ctypes.byref(st), out.data_ptr(), 1, 2, None)
+    assert rc == -1
+
+
 def test_score_graph_replay_uneven(raster, rctx):
     g, cams = scenes.config5(n=300_000, n_views=48)
     dev = raster.to_device(g)
