@@ -72,6 +72,12 @@ def lib():
         L.rtgo_thresholds.restype = None
         L.rtgo_view_utility.argtypes = ([i64, p, p, p, ctypes.c_int] + [ctypes.c_double] * 5 + [p] * 4)
         L.rtgo_view_utility.restype = ctypes.c_int
+        L.rtgo_uncertainty_update.argtypes = [i64, p, p, p, ctypes.c_int, p]
+        L.rtgo_uncertainty_update.restype = None
+        L.rtgo_region_grid.argtypes = [p, ctypes.c_double, p]
+        L.rtgo_region_grid.restype = ctypes.c_int
+        L.rtgo_region_utility.argtypes = [i64, p, p, p, ctypes.c_double, p, p, p]
+        L.rtgo_region_utility.restype = ctypes.c_int
         L.rtgo_set_threads.argtypes = [ctypes.c_int]
         L.rtgo_max_threads.restype = ctypes.c_int
         _lib = L
@@ -267,3 +273,33 @@ def view_utility(scene, cams, settings, lo, hi, range_=5.0, lam=1.0):
                             float(np.float32(range_)), float(lo), float(hi), float(lam),
                             _ptr(nh), _ptr(nl), _ptr(su), _ptr(xi))
     return nh, nl, su, xi
+
+
+def uncertainty_update(means_prev, means_cur, u_prev, squared=False):
+    """Per-Gaussian ||mu_k - mu_{k-1}|| (squared with squared=True); Gaussians
+    whose mean did not change keep u_prev.  Means 3 x N."""
+    mp, mc, up = _d(means_prev), _d(means_cur), _d(u_prev)
+    n = up.size
+    out = np.zeros(n)
+    lib().rtgo_uncertainty_update(n, _ptr(mp), _ptr(mc), _ptr(up), int(bool(squared)), _ptr(out))
+    return out
+
+
+def region_grid(box, size):
+    b = _d(box)
+    dims = np.zeros(3, np.int32)
+    if lib().rtgo_region_grid(_ptr(b), float(size), _ptr(dims)):
+        raise ValueError("bad region box or size")
+    return tuple(int(x) for x in dims)
+
+
+def region_utility(means, u, box, size=2.5):
+    """(count, sum, mean) per cuboid region of edge `size` of box (lo xyz, hi
+    xyz), region index ix + nx (iy + ny iz)."""
+    m, uu, b = _d(means), _d(u), _d(box)
+    nx, ny, nz = region_grid(box, size)
+    nr = nx * ny * nz
+    cnt = np.zeros(nr, np.int64); sm = np.zeros(nr); mean = np.zeros(nr)
+    if lib().rtgo_region_utility(uu.size, _ptr(m), _ptr(uu), _ptr(b), float(size), _ptr(cnt), _ptr(sm), _ptr(mean)):
+        raise ValueError("bad region box or size")
+    return cnt, sm, mean

@@ -1083,3 +1083,74 @@ int rtgo_view_utility(int64_t n, const double *means, const double *u, const dou
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Uncertainty bookkeeping and region utility (Sec. IV-A, IV-C)             */
+/* ------------------------------------------------------------------------ */
+
+/* Per-Gaussian uncertainty after a map update: the magnitude of the change
+ * of its mean, ||mu_k - mu_{k-1}||_2 (squared when `squared`, the -sq
+ * variant of Sec. V-A); a Gaussian whose mean did not change in this update
+ * (all three components equal) keeps its previous value u_prev.  Means are
+ * planar 3 x n.  The displacement is formed in binary64 as
+ * sqrt((dx dx + dy dy) + dz dz) and returned in binary64 (callers round). */
+void rtgo_uncertainty_update(int64_t n, const double *prev, const double *cur, const double *u_prev,
+                             int squared, double *u_out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double dx = cur[i] - prev[i];
+        double dy = cur[n + i] - prev[n + i];
+        double dz = cur[2 * n + i] - prev[2 * n + i];
+        if (dx == 0.0 && dy == 0.0 && dz == 0.0) {
+            u_out[i] = u_prev[i];
+            continue;
+        }
+        double s2 = (dx * dx + dy * dy) + dz * dz;
+        u_out[i] = squared ? s2 : sqrt(s2);
+    }
+}
+
+/* Grid of the region utility of Sec. IV-C: the enclosing box [lo, hi)
+ * (box = lo xyz, hi xyz) is partitioned into cuboids of edge `size`,
+ * dims[a] = ceil((hi_a - lo_a) / size) per axis. */
+int rtgo_region_grid(const double *box, double size, int *dims)
+{
+    if (!(size > 0.0)) return -1;
+    for (int a = 0; a < 3; a++) {
+        double e = (box[3 + a] - box[a]) / size;
+        if (!(e > 0.0) || e > 1e6) return -1;
+        dims[a] = (int)ceil(e);
+    }
+    return 0;
+}
+
+/* Region utility of Sec. IV-C: region (ix, iy, iz), index ix + nx (iy + ny iz),
+ * holds the Gaussians whose mean lies in [lo + i size, lo + (i + 1) size) on
+ * every axis (i = floor((mu_a - lo_a) / size) evaluated in binary64); means
+ * outside the grid belong to no region.  count = M_k, sum = sum of u over the
+ * region (index order), mean = Omega_k = sum / M_k (0 for an empty region). */
+int rtgo_region_utility(int64_t n, const double *means, const double *u, const double *box, double size,
+                        int64_t *count, double *sum, double *mean)
+{
+    int d[3];
+    if (rtgo_region_grid(box, size, d)) return -1;
+    int64_t nr = (int64_t)d[0] * d[1] * d[2];
+    for (int64_t r = 0; r < nr; r++) {
+        count[r] = 0;
+        sum[r] = 0.0;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        int idx[3], inside = 1;
+        for (int a = 0; a < 3; a++) {
+            double f = floor((means[(int64_t)a * n + i] - box[a]) / size);
+            if (!(f >= 0.0) || !(f < (double)d[a])) { inside = 0; break; }
+            idx[a] = (int)f;
+        }
+        if (!inside) continue;
+        int64_t r = idx[0] + (int64_t)d[0] * (idx[1] + (int64_t)d[1] * idx[2]);
+        count[r]++;
+        sum[r] += u[i];
+    }
+    for (int64_t r = 0; r < nr; r++) mean[r] = count[r] ? sum[r] / (double)count[r] : 0.0;
+    return 0;
+}
