@@ -237,6 +237,7 @@ def main():
             views[f"64x320x240_{name}"] = round(len(cams3) / dt, 1)
             log(f"64 views {name}: {dt * 1e3:.2f} ms")
         del g3
+    bookkeeping = None
     if not args.no_scoring and not args.no_uneven:
         log("setup: 256-view uneven scoring workload, 2M Gaussians")
         g5_np, cams5 = scenes.config5()
@@ -287,6 +288,36 @@ def main():
         views["256_uneven_plain"] = round(len(cams5) / dt, 1)
         log(f"256 views: {views}")
 
+        # ------------------------- uncertainty bookkeeping and region utility
+        # over the 2M-Gaussian map: u = |mu_k - mu_{k-1}| with retention, then
+        # the mean uncertainty of 2.5 m regions; algorithmic bytes per
+        # Gaussian: 28 read + 4 written, and 16 read
+        n5 = int(g5["opacity"].shape[0])
+        prev = g5["means"] + 0.01 * torch.randn_like(g5["means"])
+        prev[:, ::3] = g5["means"][:, ::3]
+        u5 = torch.rand(n5, device=dev)
+        box = [-10.0, -10.0, 0.0, 10.0, 10.0, 4.0]
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        for _ in range(2):
+            raster.uncertainty_update(ctx, prev, g5["means"], u5, out=u5)
+            raster.region_utility(ctx, g5["means"], u5, box, 2.5)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            raster.uncertainty_update(ctx, prev, g5["means"], u5, out=u5)
+        e1.record()
+        for _ in range(reps):
+            raster.region_utility(ctx, g5["means"], u5, box, 2.5)
+        e2.record()
+        torch.cuda.synchronize()
+        t_upd = e0.elapsed_time(e1) / reps * 1e-3
+        t_reg = e1.elapsed_time(e2) / reps * 1e-3
+        bookkeeping = {"gaussians": n5,
+                       "update_us": round(t_upd * 1e6, 2), "update_GBps": round(32.0 * n5 / t_upd / 1e9, 1),
+                       "region_us": round(t_reg * 1e6, 2), "region_GBps": round(16.0 * n5 / t_reg / 1e9, 1),
+                       "regions": int(np.prod(raster.region_grid(box, 2.5)))}
+        log(f"bookkeeping: {bookkeeping}")
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
@@ -327,6 +358,7 @@ def main():
         "cpu_baseline": cpu,
         "views_per_s": views,
         "keyframes_8x1280x720": keyframes,
+        "bookkeeping_2M": bookkeeping,
         "kernel_ms_per_step_eager": {k: round(v[0] / args.steps, 4) for k, v in kern.items() if v[1]},
         "frame_stats": stats,
     }

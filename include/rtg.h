@@ -284,6 +284,39 @@ rtg_status rtg_trajectory_select(rtg_ctx *ctx, const double *xi, const int32_t *
                                  int32_t n_traj, double *traj_utility, int32_t *best,
                                  void *stream);
 
+/* Uncertainty bookkeeping of Sec. IV-A: the uncertainty of a Gaussian is the
+ * magnitude of the change of its mean over a map update,
+ *   u_out[i] = ||mu_cur[i] - mu_prev[i]||_2  (squared when squared != 0: the
+ *              -sq variant of Sec. V-A),
+ * except that a Gaussian whose mean did not change in the update (all three
+ * components equal) keeps u_out[i] = u_prev[i].  Formed in binary64 as
+ * sqrt((dx^2 + dy^2) + dz^2) and rounded once to binary32.  means_prev and
+ * means_cur: device, planar 3 x n; u_prev, u_out: device, n floats (u_out
+ * may equal u_prev).  Asynchronous on `stream`. */
+rtg_status rtg_uncertainty_update(rtg_ctx *ctx, int64_t n, const float *means_prev,
+                                  const float *means_cur, const float *u_prev, int32_t squared,
+                                  float *u_out, void *stream);
+
+/* Region grid of Sec. IV-C (host only): the box [lo, hi) (box = lo x, y, z,
+ * hi x, y, z) is partitioned into cuboids of edge `size` (2.5 m in the
+ * paper), dims[a] = ceil((hi_a - lo_a) / size).  RTG_ERR_INVALID for a
+ * non-positive size or extent. */
+rtg_status rtg_region_grid(const double *box, double size, int32_t *dims);
+
+/* Region utility of Sec. IV-C: for each cuboid region r = ix + nx (iy + ny iz)
+ * of rtg_region_grid(box, size), count[r] = M = the number of Gaussians whose
+ * mean lies in it (i = floor((mu_a - lo_a) / size) in binary64, half-open
+ * cells; means outside the grid count nowhere), sum[r] = the sum of their u,
+ * mean[r] = Omega = sum / M (0 for an empty region).  Sums are accumulated in
+ * fixed point with 2^-32 resolution, independent of the order of the
+ * atomics; a region holding a non-finite u or |u| >= 2^20 reports NaN.
+ * means (planar 3 x n), u (n): device; box: host, 6 doubles; count, sum,
+ * mean: device arrays of nx ny nz entries, any may be NULL.  Asynchronous on
+ * `stream`. */
+rtg_status rtg_region_utility(rtg_ctx *ctx, int64_t n, const float *means, const float *u,
+                              const double *box, double size, int64_t *count, double *sum,
+                              double *mean, void *stream);
+
 /* Work counters of a rendered frame (host output, synchronises `stream`):
  *   out[0] records (visible view-Gaussian pairs), out[1] instances
  *   (tile-Gaussian pairs), out[2] contributing pixel-Gaussian pairs (terms of

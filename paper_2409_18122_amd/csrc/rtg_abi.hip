@@ -1310,6 +1310,48 @@ rtg_status rtg_view_utility(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_came
     return check_launch("view utility");
 }
 
+rtg_status rtg_uncertainty_update(rtg_ctx* ctx, int64_t n, const float* means_prev, const float* means_cur,
+                                  const float* u_prev, int32_t squared, float* u_out, void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (n < 0) return set_err(RTG_ERR_INVALID, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!means_prev || !means_cur || !u_prev || !u_out))
+        return set_err(RTG_ERR_INVALID, "means_prev, means_cur, u_prev and u_out must be non-NULL");
+    uncertainty_update(n, means_prev, means_cur, u_prev, squared ? 1 : 0, u_out, (hipStream_t)stream);
+    return check_launch("uncertainty update");
+}
+
+rtg_status rtg_region_grid(const double* box, double size, int32_t* dims) {
+    if (!box || !dims) return set_err(RTG_ERR_INVALID, "box and dims must be non-NULL");
+    if (!(size > 0.0) || !std::isfinite(size)) return set_err(RTG_ERR_INVALID, "size must be finite and > 0");
+    int64_t nr = 1;
+    for (int a = 0; a < 3; a++) {
+        const double e = (box[3 + a] - box[a]) / size;
+        if (!(e > 0.0) || !(e <= 65536.0)) return set_err(RTG_ERR_INVALID, "box axis %d: extent / size = %g", a, e);
+        dims[a] = (int32_t)std::ceil(e);
+        nr *= dims[a];
+    }
+    if (nr > ((int64_t)1 << 28)) return set_err(RTG_ERR_UNSUPPORTED, "%lld regions", (long long)nr);
+    return RTG_OK;
+}
+
+rtg_status rtg_region_utility(rtg_ctx* ctx, int64_t n, const float* means, const float* u, const double* box,
+                              double size, int64_t* count, double* sum, double* mean, void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (n < 0) return set_err(RTG_ERR_INVALID, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!means || !u)) return set_err(RTG_ERR_INVALID, "means and u must be non-NULL");
+    int32_t dims[3];
+    RTG_TRY(rtg_region_grid(box, size, dims));
+    const int64_t nr = (int64_t)dims[0] * dims[1] * dims[2];
+    hipStream_t s = (hipStream_t)stream;
+    Buf acc;
+    RTG_TRY(acc.ensure(ctx, (2 * sizeof(unsigned long long) + sizeof(unsigned int)) * (size_t)nr));
+    unsigned long long* cnt = acc.as<unsigned long long>();
+    int dm[3] = {dims[0], dims[1], dims[2]};
+    region_utility(n, means, u, box, size, dm, cnt, cnt + nr, reinterpret_cast<unsigned int*>(cnt + 2 * nr), count,
+                   sum, mean, s);
+    return check_launch("region utility");
+}
+
 rtg_status rtg_trajectory_select(rtg_ctx* ctx, const double* xi, const int32_t* offsets, int32_t n_traj,
                                  double* traj_utility, int32_t* best, void* stream) {
     RTG_TRY(ctx_ok(ctx));

@@ -165,6 +165,14 @@ void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_
                  const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s);
 int score_persistent_blocks(int tw, int th, int batch);
+// Uncertainty bookkeeping (n Gaussians, planar 3 x n means).
+void uncertainty_update(int64_t n, const float* prev, const float* cur, const float* u_prev, int squared,
+                        float* u_out, hipStream_t s);
+// Region utility over dims[0] x dims[1] x dims[2] cuboids from lo (host
+// values) with edge size; cnt/fix (u64) and bad (u32) are nr-entry scratch.
+void region_utility(int64_t n, const float* means, const float* u, const double* lo, double size, const int* dims,
+                    unsigned long long* cnt, unsigned long long* fix, unsigned int* bad, int64_t* count, double* sum,
+                    double* mean, hipStream_t s);
 void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, const double* partial,
                   double* scores, hipStream_t s);
 

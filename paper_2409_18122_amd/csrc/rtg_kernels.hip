@@ -2020,6 +2020,103 @@ inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 65535u * 16u
     return (unsigned)g;
 }
 
+// ------------------------------------------------- uncertainty bookkeeping
+// Sec. IV-A: the uncertainty of a Gaussian is the magnitude of the change of
+// its mean over a map update (squared for the -sq variant); a Gaussian whose
+// mean did not change keeps its previous value.  Formed in binary64 as
+// sqrt((dx dx + dy dy) + dz dz) and rounded once to binary32.
+
+__global__ __launch_bounds__(256) void k_uncertainty_update(int64_t n, const float* __restrict__ prev,
+                                                            const float* __restrict__ cur,
+                                                            const float* u_prev, int squared, float* u_out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double dx = (double)cur[i] - (double)prev[i];
+        const double dy = (double)cur[n + i] - (double)prev[n + i];
+        const double dz = (double)cur[2 * n + i] - (double)prev[2 * n + i];
+        float u;
+        if (dx == 0.0 && dy == 0.0 && dz == 0.0) {
+            u = u_prev[i];
+        } else {
+            const double s2 = (dx * dx + dy * dy) + dz * dz;
+            u = (float)(squared ? s2 : sqrt(s2));
+        }
+        u_out[i] = u;
+    }
+}
+
+// ---------------------------------------------------------- region utility
+// Sec. IV-C: cuboid regions of edge `size` over the box [lo, lo + dims size);
+// a Gaussian belongs to region (ix, iy, iz), index ix + nx (iy + ny iz), with
+// i = floor((mu - lo) / size) in binary64.  Counts are exact; sums are in
+// fixed point with 2^-32 resolution (|u| < 2^20 per value), so the result
+// does not depend on the order of the atomics.  A non-finite or out-of-range
+// u marks its region (its sum and mean become NaN).
+
+constexpr double RG_FIX = 4294967296.0;  // 2^32
+constexpr int RG_LDS = 2048;             // regions privatised in LDS per block
+
+__device__ __forceinline__ int64_t region_of(const float* __restrict__ means, int64_t n, int64_t i, double lx,
+                                             double ly, double lz, double size, int nx, int ny, int nz) {
+    const double fx = floor(((double)means[i] - lx) / size);
+    const double fy = floor(((double)means[n + i] - ly) / size);
+    const double fz = floor(((double)means[2 * n + i] - lz) / size);
+    if (!(fx >= 0.0 && fx < (double)nx && fy >= 0.0 && fy < (double)ny && fz >= 0.0 && fz < (double)nz)) return -1;
+    return (int64_t)fx + (int64_t)nx * ((int64_t)fy + (int64_t)ny * (int64_t)fz);
+}
+
+__global__ __launch_bounds__(256) void k_region_utility(int64_t n, const float* __restrict__ means,
+                                                        const float* __restrict__ u, double lx, double ly,
+                                                        double lz, double size, int nx, int ny, int nz,
+                                                        unsigned long long* __restrict__ cnt,
+                                                        unsigned long long* __restrict__ fix,
+                                                        unsigned int* __restrict__ bad) {
+    __shared__ unsigned long long s_cnt[RG_LDS], s_fix[RG_LDS];
+    const int64_t nr = (int64_t)nx * ny * nz;
+    const bool lds = nr <= RG_LDS;
+    if (lds) {
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) s_cnt[r] = s_fix[r] = 0ull;
+        __syncthreads();
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = region_of(means, n, i, lx, ly, lz, size, nx, ny, nz);
+        if (r < 0) continue;
+        const float v = u[i];
+        const bool ok = isfinite(v) && fabsf(v) < 1048576.0f;
+        const long long f = ok ? __double2ll_rn((double)v * RG_FIX) : 0ll;
+        if (!ok) atomicOr(&bad[r], 1u);
+        if (lds) {
+            atomicAdd(&s_cnt[r], 1ull);
+            atomicAdd(&s_fix[r], (unsigned long long)f);  // two's complement: signed sums wrap correctly
+        } else {
+            atomicAdd(&cnt[r], 1ull);
+            atomicAdd(&fix[r], (unsigned long long)f);
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+            if (s_cnt[r]) {
+                atomicAdd(&cnt[r], s_cnt[r]);
+                atomicAdd(&fix[r], s_fix[r]);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_region_finish(int64_t nr, const unsigned long long* __restrict__ cnt,
+                                                       const unsigned long long* __restrict__ fix,
+                                                       const unsigned int* __restrict__ bad,
+                                                       int64_t* __restrict__ count, double* __restrict__ sum,
+                                                       double* __restrict__ mean) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = (int64_t)cnt[r];
+        const double sm = bad[r] ? __longlong_as_double(0x7ff8000000000000ll) : (double)(long long)fix[r] / RG_FIX;
+        if (count) count[r] = c;
+        if (sum) sum[r] = sm;
+        if (mean) mean[r] = c ? sm / (double)c : 0.0;
+    }
+}
+
 }  // namespace
 
 // ================================================================ launchers
@@ -2315,6 +2412,27 @@ void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, cons
 void sum_u32_pair(const uint32_t* a, const uint32_t* b, uint64_t n, unsigned long long* out, hipStream_t s) {
     if (n == 0) return;
     k_sum_u32_pair<<<grid_for(n, 256, 2048), 256, 0, s>>>(a, b, n, out);
+}
+
+void uncertainty_update(int64_t n, const float* prev, const float* cur, const float* u_prev, int squared,
+                        float* u_out, hipStream_t s) {
+    if (n <= 0) return;
+    k_uncertainty_update<<<grid_for((uint64_t)n, 256, 1u << 20), 256, 0, s>>>(n, prev, cur, u_prev, squared, u_out);
+}
+
+void region_utility(int64_t n, const float* means, const float* u, const double* lo, double size, const int* dims,
+                    unsigned long long* cnt, unsigned long long* fix, unsigned int* bad, int64_t* count, double* sum,
+                    double* mean, hipStream_t s) {
+    const int64_t nr = (int64_t)dims[0] * dims[1] * dims[2];
+    fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 2 * (uint64_t)nr, s);
+    fill_u32(reinterpret_cast<uint32_t*>(fix), 0u, 2 * (uint64_t)nr, s);
+    fill_u32(bad, 0u, (uint64_t)nr, s);
+    if (n > 0) {
+        const unsigned grid = grid_for((uint64_t)n, 256 * 16, 2048);  // blocks walk 16 x 256 Gaussians
+        k_region_utility<<<grid, 256, 0, s>>>(n, means, u, lo[0], lo[1], lo[2], size, dims[0], dims[1], dims[2], cnt,
+                                              fix, bad);
+    }
+    k_region_finish<<<grid_for((uint64_t)nr, 256, 4096), 256, 0, s>>>(nr, cnt, fix, bad, count, sum, mean);
 }
 
 void export_pairs(const uint32_t* tile_key, const uint32_t* inst_rec, const uint32_t* K_dev, Records rec,

@@ -427,6 +427,42 @@ def autotune(ctx, g, cams, mode, settings=None, cache=None):
     return out
 
 
+def uncertainty_update(ctx, means_prev, means_cur, u_prev, squared=False, out=None):
+    """Per-Gaussian ||mu_cur - mu_prev|| (squared with squared=True); a
+    Gaussian whose mean did not change keeps u_prev (Sec. IV-A bookkeeping).
+    Means: (3, N) float32 device tensors; returns (N,) float32 (out may be
+    u_prev for an in-place update)."""
+    n = int(u_prev.shape[0])
+    if out is None:
+        out = torch.empty_like(u_prev)
+    check(lib().rtg_uncertainty_update(ctx.handle, n, _ptr(means_prev.contiguous()),
+                                       _ptr(means_cur.contiguous()), _ptr(u_prev), int(bool(squared)),
+                                       _ptr(out), _stream()))
+    return out
+
+
+def region_grid(box, size=2.5):
+    b = (ctypes.c_double * 6)(*[float(x) for x in box])
+    d = (ctypes.c_int32 * 3)()
+    check(lib().rtg_region_grid(b, float(size), d))
+    return tuple(int(x) for x in d)
+
+
+def region_utility(ctx, means, u, box, size=2.5):
+    """(count int64, sum float64, mean float64) per cuboid region of edge
+    `size` of box = (lo x, y, z, hi x, y, z), region ix + nx (iy + ny iz)."""
+    nx, ny, nz = region_grid(box, size)
+    nr = nx * ny * nz
+    dev = u.device
+    count = torch.empty(nr, device=dev, dtype=torch.int64)
+    sm = torch.empty(nr, device=dev, dtype=torch.float64)
+    mean = torch.empty(nr, device=dev, dtype=torch.float64)
+    b = (ctypes.c_double * 6)(*[float(x) for x in box])
+    check(lib().rtg_region_utility(ctx.handle, int(u.shape[0]), _ptr(means.contiguous()), _ptr(u), b, float(size),
+                                   _ptr(count), _ptr(sm), _ptr(mean), _stream()))
+    return count, sm, mean
+
+
 def unpack_images(out, cams):
     """Split packed per-view outputs into lists of (C, H, W) / (H, W) tensors."""
     res = []
@@ -446,4 +482,5 @@ def unpack_images(out, cams):
 
 
 __all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph", "MapGraph", "tune_key",
+           "uncertainty_update", "region_grid", "region_utility",
            "autotune", "to_device", "unpack_images", "RtgError", "DEFAULTS"]

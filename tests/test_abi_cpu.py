@@ -79,6 +79,9 @@ def test_null_arguments_rejected_on_host(L):
     assert L.rtg_view_utility(None, None, None, 1, None, 5.0, None, 1.0, None, None, None, None, None) == -1
     assert L.rtg_uncertainty_thresholds(None, None, 0, 0.5, None, None) == -1
     assert L.rtg_trajectory_select(None, None, None, 1, None, None, None) == -1
+    assert L.rtg_uncertainty_update(None, 4, None, None, None, 0, None, None) == -1
+    box = (ctypes.c_double * 6)(0, 0, 0, 10, 5, 2.5)
+    assert L.rtg_region_utility(None, 4, None, None, box, 2.5, None, None, None, None) == -1
     stats = (ctypes.c_int64 * 4)()
     assert L.rtg_frame_stats(None, None, stats, None) == -1
     assert L.rtg_timing_enable(None, 1) == -1
@@ -92,6 +95,22 @@ def test_null_arguments_rejected_on_host(L):
     L.rtg_frame_destroy(None)
     L.rtg_score_graph_destroy(None)
     L.rtg_map_graph_destroy(None)
+
+
+def test_region_grid_on_host(L):
+    # host-only: needs no device; same dims as the oracle's definition
+    import oracle
+    for box, size in (([0, 0, 0, 10, 5, 2.5], 2.5), ([-10, -10, 0, 10.1, 10, 4], 2.5), ([0, 0, 0, 1, 1, 1], 0.3)):
+        b = (ctypes.c_double * 6)(*box)
+        d = (ctypes.c_int32 * 3)()
+        assert L.rtg_region_grid(b, size, d) == 0
+        assert tuple(d) == oracle.region_grid(box, size)
+    b = (ctypes.c_double * 6)(0, 0, 0, 0, 1, 1)
+    d = (ctypes.c_int32 * 3)()
+    assert L.rtg_region_grid(b, 2.5, d) == -1
+    assert L.rtg_region_grid(None, 2.5, d) == -1
+    b = (ctypes.c_double * 6)(0, 0, 0, 1, 1, 1)
+    assert L.rtg_region_grid(b, 0.0, d) == -1
 
 
 def test_missing_library_fails_loudly(monkeypatch):
