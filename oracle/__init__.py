@@ -78,6 +78,8 @@ def lib():
         L.rtgo_region_grid.restype = ctypes.c_int
         L.rtgo_region_utility.argtypes = [i64, p, p, p, ctypes.c_double, p, p, p]
         L.rtgo_region_utility.restype = ctypes.c_int
+        L.rtgo_collision.argtypes = [i64, p, p, i64, p, ctypes.c_double, ctypes.c_double, p, p]
+        L.rtgo_collision.restype = None
         L.rtgo_set_threads.argtypes = [ctypes.c_int]
         L.rtgo_max_threads.restype = ctypes.c_int
         _lib = L
@@ -303,3 +305,16 @@ def region_utility(means, u, box, size=2.5):
     if lib().rtgo_region_utility(uu.size, _ptr(m), _ptr(uu), _ptr(b), float(size), _ptr(cnt), _ptr(sm), _ptr(mean)):
         raise ValueError("bad region box or size")
     return cnt, sm, mean
+
+
+def collision(means, log_scales, points, r_robot, lambda_g=3.0):
+    """(collide int32[P], clearance float64[P]): point p collides when
+    ||p - mu_i|| < r_robot + lambda_g exp(max log-scale_i) for some i;
+    clearance = min_i (||p - mu_i|| - lambda_g r_i).  Planar 3 x N / 3 x P."""
+    m, l, pts = _d(means), _d(log_scales), _d(points)
+    n = m.shape[1] if m.ndim == 2 else 0
+    npt = pts.shape[1] if pts.ndim == 2 else 0
+    hit = np.zeros(npt, np.int32)
+    clr = np.zeros(npt)
+    lib().rtgo_collision(n, _ptr(m), _ptr(l), npt, _ptr(pts), float(r_robot), float(lambda_g), _ptr(hit), _ptr(clr))
+    return hit, clr

@@ -1154,3 +1154,44 @@ int rtgo_region_utility(int64_t n, const double *means, const double *u, const d
     for (int64_t r = 0; r < nr; r++) mean[r] = count[r] ? sum[r] / (double)count[r] : 0.0;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Collision checking (Sec. IV-D, Collision Checking)                       */
+/* ------------------------------------------------------------------------ */
+
+/* Each test point is a sphere of radius r_robot; each Gaussian's radius is
+ * its principal axis r_i = exp(max_k log_scale_k), scaled by lambda_g.  The
+ * point collides when its distance to some Gaussian's mean is below
+ * gamma_i = r_robot + lambda_g r_i, decided in binary64 as
+ * (dx^2 + dy^2) + dz^2 < gamma_i^2.  clearance = min_i (||p - mu_i|| -
+ * lambda_g r_i), so the point collides exactly when clearance < r_robot.
+ * Gaussians with non-finite mean or log-scales are ignored; with none left,
+ * clearance = +inf.  points and means planar (3 x n_points, 3 x n). */
+void rtgo_collision(int64_t n, const double *means, const double *ls, int64_t np, const double *pts,
+                    double r_robot, double lambda_g, int32_t *collide, double *clearance)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < np; j++) {
+        double px = pts[j], py = pts[np + j], pz = pts[2 * np + j];
+        int hit = 0;
+        double best = INFINITY;
+        for (int64_t i = 0; i < n; i++) {
+            double mx = means[i], my = means[n + i], mz = means[2 * n + i];
+            double l0 = ls[i], l1 = ls[n + i], l2 = ls[2 * n + i];
+            if (!isfinite(mx) || !isfinite(my) || !isfinite(mz) || !isfinite(l0) || !isfinite(l1) ||
+                !isfinite(l2))
+                continue;
+            double lm = l0 > l1 ? l0 : l1;
+            lm = lm > l2 ? lm : l2;
+            double r = exp(lm);
+            double dx = px - mx, dy = py - my, dz = pz - mz;
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            double g = r_robot + lambda_g * r;
+            if (d2 < g * g) hit = 1;
+            double c = sqrt(d2) - lambda_g * r;
+            if (c < best) best = c;
+        }
+        collide[j] = hit;
+        clearance[j] = best;
+    }
+}
