@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--no-scoring", action="store_true", help="skip the view-scoring workloads")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256-view uneven scoring workload")
     ap.add_argument("--no-keyframes", action="store_true", help="skip the 8-keyframe 1280x720 mapping workload")
+    ap.add_argument("--no-collision", action="store_true", help="skip the 3M-Gaussian collision-check workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=str, default="16x16")
     ap.add_argument("--sweep-tiles", action="store_true", help="also time the step at every tile shape")
@@ -318,6 +319,35 @@ def main():
                        "regions": int(np.prod(raster.region_grid(box, 2.5)))}
         log(f"bookkeeping: {bookkeeping}")
 
+    # ------------------------------------------------------- collision check
+    # 3M Gaussians over a 40 m x 40 m lot; one 5 m motion primitive of 129
+    # points, and a tree layer of 64 such primitives; every point against
+    # every Gaussian.  The pair loop issues 15 VALU instructions per pair.
+    collision = None
+    if not args.no_collision:
+        glot = scenes.lot_scene()
+        gl = {k: torch.as_tensor(glot[k]).to(dev) for k in ("means", "log_scales")}
+        nl = int(glot["means"].shape[1])
+        collision = {"gaussians": nl, "r_robot": 0.25, "lambda_g": 3.0}
+        for name, n_paths in (("1x129", 1), ("64x129", 64)):
+            pl = torch.as_tensor(scenes.path_points(n_paths, 7)).to(dev)
+            npt = int(pl.shape[1])
+            for _ in range(2):
+                raster.collision_check(ctx, gl, pl, 0.25, 3.0)
+            reps = 10 if n_paths > 1 else 50
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            e0.record()
+            for _ in range(reps):
+                hit, _ = raster.collision_check(ctx, gl, pl, 0.25, 3.0)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps * 1e-3
+            pairs = float(nl) * npt
+            collision[name] = {"points": npt, "us": round(t * 1e6, 1), "Gpairs_per_s": round(pairs / t / 1e9, 1),
+                               "alu_frac": round(pairs * 15 / t / ALU_PEAK_OPS, 3),
+                               "collisions": int(hit.sum().item())}
+        log(f"collision: {collision}")
+
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
@@ -359,6 +389,7 @@ def main():
         "views_per_s": views,
         "keyframes_8x1280x720": keyframes,
         "bookkeeping_2M": bookkeeping,
+        "collision_3M": collision,
         "kernel_ms_per_step_eager": {k: round(v[0] / args.steps, 4) for k, v in kern.items() if v[1]},
         "frame_stats": stats,
     }

@@ -317,6 +317,25 @@ rtg_status rtg_region_utility(rtg_ctx *ctx, int64_t n, const float *means, const
                               const double *box, double size, int64_t *count, double *sum,
                               double *mean, void *stream);
 
+/* Collision check of Sec. IV-D: a Gaussian is treated as a sphere about its
+ * mean of radius lambda_g r_i, r_i = exp(max of its three log-scales) (the
+ * principal axis); a point sampled on a path collides when a sphere of radius
+ * r_robot about it meets one of them:
+ *   collide[j]   = 1 if ||p_j - mu_i||^2 < (r_robot + lambda_g r_i)^2 for
+ *                  some i, else 0 (strict; decided in binary64 wherever the
+ *                  binary32 distance is within a relative 4e-6 of the bound);
+ *   clearance[j] = min_i (||p_j - mu_i|| - lambda_g r_i), binary32, +inf when
+ *                  no Gaussian is left.
+ * Gaussians with a non-finite mean or log-scale are ignored.  points: device,
+ * planar 3 x n_points; collide: device, n_points int32 (required);
+ * clearance: device, n_points floats or NULL.  Only g->means and
+ * g->log_scales are read.  r_robot, lambda_g: finite and >= 0 (the paper
+ * uses lambda_g = 3).  Every point is tested against every Gaussian (no
+ * spatial index).  Asynchronous on `stream`. */
+rtg_status rtg_collision_check(rtg_ctx *ctx, const rtg_gaussians *g, const float *points,
+                               int64_t n_points, float r_robot, float lambda_g, int32_t *collide,
+                               float *clearance, void *stream);
+
 /* Work counters of a rendered frame (host output, synchronises `stream`):
  *   out[0] records (visible view-Gaussian pairs), out[1] instances
  *   (tile-Gaussian pairs), out[2] contributing pixel-Gaussian pairs (terms of

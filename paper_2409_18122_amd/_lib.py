@@ -80,6 +80,7 @@ SIGNATURES = {
     "rtg_uncertainty_update": (i32, [vp, i64, vp, vp, vp, i32, vp, vp]),
     "rtg_region_grid": (i32, [_c.POINTER(_c.c_double), _c.c_double, _c.POINTER(i32)]),
     "rtg_region_utility": (i32, [vp, i64, vp, vp, _c.POINTER(_c.c_double), _c.c_double, vp, vp, vp, vp]),
+    "rtg_collision_check": (i32, [vp, _c.POINTER(Gaussians), vp, i64, f32, f32, vp, vp, vp]),
     "rtg_timing_enable": (i32, [vp, i32]),
     "rtg_timing_read": (i32, [vp, i32, _c.POINTER(_c.c_double), _c.POINTER(i64)]),
     "rtg_timing_reset": (i32, [vp]),

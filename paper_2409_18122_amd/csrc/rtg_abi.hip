@@ -1352,6 +1352,31 @@ rtg_status rtg_region_utility(rtg_ctx* ctx, int64_t n, const float* means, const
     return check_launch("region utility");
 }
 
+rtg_status rtg_collision_check(rtg_ctx* ctx, const rtg_gaussians* g, const float* points, int64_t n_points,
+                               float r_robot, float lambda_g, int32_t* collide, float* clearance, void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (!g) return set_err(RTG_ERR_INVALID, "gaussians is NULL");
+    if (g->n < 0 || n_points < 0) return set_err(RTG_ERR_INVALID, "n = %lld, n_points = %lld", (long long)g->n,
+                                                 (long long)n_points);
+    if (g->n >= (int64_t)1 << 31 || n_points >= (int64_t)1 << 31)
+        return set_err(RTG_ERR_UNSUPPORTED, "n = %lld, n_points = %lld: 2^31 or more", (long long)g->n,
+                       (long long)n_points);
+    if (g->n > 0 && (!g->means || !g->log_scales)) return set_err(RTG_ERR_INVALID, "means and log_scales are required");
+    if (n_points > 0 && (!points || !collide)) return set_err(RTG_ERR_INVALID, "points and collide must be non-NULL");
+    if (!std::isfinite(r_robot) || !(r_robot >= 0.0f)) return set_err(RTG_ERR_INVALID, "r_robot must be finite and >= 0");
+    if (!std::isfinite(lambda_g) || !(lambda_g >= 0.0f))
+        return set_err(RTG_ERR_INVALID, "lambda_g must be finite and >= 0");
+    if (n_points == 0) return RTG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Buf packed, bound, key;
+    RTG_TRY(packed.ensure(ctx, sizeof(float4) * (size_t)std::max<int64_t>(g->n, 1)));
+    RTG_TRY(bound.ensure(ctx, sizeof(float2) * (size_t)std::max<int64_t>(g->n, 1)));
+    RTG_TRY(key.ensure(ctx, sizeof(uint32_t) * (size_t)n_points));
+    collision_check(to_dev(*g), points, n_points, r_robot, lambda_g, packed.as<float4>(), bound.as<float2>(), collide,
+                    key.as<uint32_t>(), clearance, s);
+    return check_launch("collision check");
+}
+
 rtg_status rtg_trajectory_select(rtg_ctx* ctx, const double* xi, const int32_t* offsets, int32_t n_traj,
                                  double* traj_utility, int32_t* best, void* stream) {
     RTG_TRY(ctx_ok(ctx));

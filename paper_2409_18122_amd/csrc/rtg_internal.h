@@ -165,6 +165,11 @@ void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_
                  const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s);
 int score_persistent_blocks(int tw, int th, int batch);
+// Collision check of np points (planar 3 x np) against the map; packed,
+// bound: n float4 / float2 scratch, collide: np int32 (required), clear_key:
+// np uint32 scratch, clearance: np floats or NULL.
+void collision_check(const GaussDev& g, const float* pts, int64_t np, float r_robot, float lambda_g, float4* packed,
+                     float2* bound, int32_t* collide, uint32_t* clear_key, float* clearance, hipStream_t s);
 // Uncertainty bookkeeping (n Gaussians, planar 3 x n means).
 void uncertainty_update(int64_t n, const float* prev, const float* cur, const float* u_prev, int squared,
                         float* u_out, hipStream_t s);

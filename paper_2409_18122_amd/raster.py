@@ -463,6 +463,27 @@ def region_utility(ctx, means, u, box, size=2.5):
     return count, sm, mean
 
 
+def collision_check(ctx, g, points, r_robot, lambda_g=3.0, clearance=True):
+    """(collide int32[P], clearance float32[P] or None) of the points
+    (planar 3 x P) against the Gaussians' principal-axis spheres."""
+    for k in ("means", "log_scales"):
+        t = g[k]
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda or t.dim() != 2 or t.shape[0] != 3:
+            raise ValueError(f"gaussian array {k} must be a contiguous planar 3 x N float32 CUDA tensor")
+    gs = Gaussians(int(g["means"].shape[1]), *[_ptr(g[k]) if k in ("means", "log_scales") else None
+                                              for k in GAUSS_KEYS])
+    pts = points.contiguous()
+    if pts.dtype != torch.float32:
+        raise ValueError("points must be float32")
+    P = int(pts.shape[1]) if pts.dim() == 2 else 0
+    dev = g["means"].device
+    hit = torch.empty(P, device=dev, dtype=torch.int32)
+    clr = torch.empty(P, device=dev, dtype=torch.float32) if clearance else None
+    check(lib().rtg_collision_check(ctx.handle, ctypes.byref(gs), _ptr(pts), P, float(r_robot), float(lambda_g),
+                                    _ptr(hit), _ptr(clr), _stream()))
+    return hit, clr
+
+
 def unpack_images(out, cams):
     """Split packed per-view outputs into lists of (C, H, W) / (H, W) tensors."""
     res = []
@@ -482,5 +503,5 @@ def unpack_images(out, cams):
 
 
 __all__ = ["Context", "Frame", "RasterizeFn", "rasterize", "render", "score_views", "ScoreGraph", "MapGraph", "tune_key",
-           "uncertainty_update", "region_grid", "region_utility",
+           "uncertainty_update", "region_grid", "region_utility", "collision_check",
            "autotune", "to_device", "unpack_images", "RtgError", "DEFAULTS"]

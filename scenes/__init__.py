@@ -213,6 +213,54 @@ def config5(n=2_000_000, seed=5, n_views=256):
     return g, cams
 
 
+LOT_HALF = 20.0  # a 40 m x 40 m lot
+
+
+def lot_scene(n=3_000_000, seed=6, n_obstacles=80, ground=0.6):
+    """A 40 m x 40 m outdoor lot of n Gaussians lying on surfaces: a fraction
+    `ground` on the ground plane (z ~ N(0, 0.02)), the rest on the mantles of
+    `n_obstacles` upright cylinders (radius U(0.3, 2), height U(0.5, 3)).
+    Log-scales N(-3.5, 0.3); the other attributes as in the room scenes.  The
+    means come from default_rng(seed + 2000)."""
+    rng = np.random.default_rng(seed)
+    _, ls, q, op, col, unc = _gaussians(rng, n, (-LOT_HALF, -LOT_HALF, 0.0), (LOT_HALF, LOT_HALF, 3.0),
+                                        ls_mean=-3.5, ls_std=0.3)
+    r2 = np.random.default_rng(seed + 2000)
+    n_g = int(round(ground * n))
+    m = np.empty((3, n))
+    m[0, :n_g] = r2.uniform(-LOT_HALF, LOT_HALF, n_g)
+    m[1, :n_g] = r2.uniform(-LOT_HALF, LOT_HALF, n_g)
+    m[2, :n_g] = r2.normal(0.0, 0.02, n_g)
+    cx = r2.uniform(-LOT_HALF + 2, LOT_HALF - 2, n_obstacles)
+    cy = r2.uniform(-LOT_HALF + 2, LOT_HALF - 2, n_obstacles)
+    rad = r2.uniform(0.3, 2.0, n_obstacles)
+    hgt = r2.uniform(0.5, 3.0, n_obstacles)
+    k = r2.integers(0, n_obstacles, n - n_g)
+    phi = r2.uniform(0, 2 * np.pi, n - n_g)
+    m[0, n_g:] = cx[k] + rad[k] * np.cos(phi) + r2.normal(0, 0.02, n - n_g)
+    m[1, n_g:] = cy[k] + rad[k] * np.sin(phi) + r2.normal(0, 0.02, n - n_g)
+    m[2, n_g:] = r2.uniform(0, 1, n - n_g) * hgt[k]
+    return _pack(m, ls, q, op, col, unc)
+
+
+def path_points(n_paths, seed, samples=129, length=5.0, z=0.5, curvature=0.3):
+    """Points sampled on motion primitives: n_paths arcs of the given length
+    at height z, start uniform in the lot, heading U(0, 2 pi), curvature
+    U(-c, c) per metre, each sampled at `samples` evenly spaced arc lengths
+    (both ends included).  Planar (3, n_paths * samples), path after path."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(-LOT_HALF + 3, LOT_HALF - 3, (2, n_paths))
+    th0 = rng.uniform(0, 2 * np.pi, n_paths)
+    kap = rng.uniform(-curvature, curvature, n_paths)
+    ds = length / max(samples - 1, 1)
+    s = np.arange(samples) * ds
+    th = th0[:, None] + kap[:, None] * s[None, :]
+    px = x0[0][:, None] + np.concatenate([np.zeros((n_paths, 1)), np.cumsum(np.cos(th[:, :-1]) * ds, 1)], 1)
+    py = x0[1][:, None] + np.concatenate([np.zeros((n_paths, 1)), np.cumsum(np.sin(th[:, :-1]) * ds, 1)], 1)
+    pts = np.stack([px.ravel(), py.ravel(), np.full(n_paths * samples, z)])
+    return _f32(pts)
+
+
 def tiny_scene(n, seed, width=32, height=24, depth=(1.5, 4.0), ls=(-2.5, 0.5),
                opacity="sigmoid"):
     """Small random scene in front of an identity camera (for brute force)."""

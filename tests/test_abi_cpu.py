@@ -82,6 +82,7 @@ def test_null_arguments_rejected_on_host(L):
     assert L.rtg_uncertainty_update(None, 4, None, None, None, 0, None, None) == -1
     box = (ctypes.c_double * 6)(0, 0, 0, 10, 5, 2.5)
     assert L.rtg_region_utility(None, 4, None, None, box, 2.5, None, None, None, None) == -1
+    assert L.rtg_collision_check(None, None, None, 4, 0.25, 3.0, None, None, None) == -1
     stats = (ctypes.c_int64 * 4)()
     assert L.rtg_frame_stats(None, None, stats, None) == -1
     assert L.rtg_timing_enable(None, 1) == -1

@@ -1,0 +1,189 @@
+"""GPU parity of the collision check (Sec. IV-D) against the oracle, through
+the C ABI: flags bit-exact outside a 1e-12 relative tie band, clearance within
+the binary32 evaluation bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+LAMBDA_G = 3.0
+R_ROBOT = 0.25
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def raster():
+    from paper_2409_18122_amd import raster as r
+    return r
+
+
+@pytest.fixture(scope="module")
+def rctx(raster):
+    return raster.Context(0)
+
+
+def run(raster, rctx, means, ls, pts, r_robot=R_ROBOT, lambda_g=LAMBDA_G):
+    g = {"means": torch.as_tensor(means).cuda(), "log_scales": torch.as_tensor(ls).cuda()}
+    hit, clr = raster.collision_check(rctx, g, torch.as_tensor(pts).cuda(), r_robot, lambda_g)
+    torch.cuda.synchronize()
+    return hit.cpu().numpy(), clr.cpu().numpy()
+
+
+def tie_bands(means, ls, pts, r_robot, lambda_g, rel=1e-12):
+    """(surely_hit, maybe_hit) per point in binary64: a pair within `rel` of
+    its bound counts as a tie, where either answer is accepted."""
+    m = means.astype(np.float64)
+    l = ls.astype(np.float64)
+    ok = np.all(np.isfinite(m), 0) & np.all(np.isfinite(l), 0)
+    m, l = m[:, ok], l[:, ok]
+    g2 = (r_robot + lambda_g * np.exp(l.max(0))) ** 2
+    sure = np.zeros(pts.shape[1], bool)
+    maybe = np.zeros(pts.shape[1], bool)
+    p = pts.astype(np.float64)
+    for j0 in range(0, p.shape[1], 64):
+        q = p[:, j0:j0 + 64]
+        d2 = ((q[:, :, None] - m[:, None, :]) ** 2).sum(0)
+        sure[j0:j0 + 64] = (d2 < g2 * (1 - rel)).any(1)
+        maybe[j0:j0 + 64] = (d2 < g2 * (1 + rel)).any(1)
+    return sure, maybe
+
+
+def w_max(ls, lambda_g):
+    l = ls.astype(np.float64)
+    l = l[:, np.all(np.isfinite(l), 0)]
+    return float(lambda_g * np.exp(l.max())) if l.size else 0.0
+
+
+def check(hit, clr, ref_hit, ref_clr, sure=None, maybe=None, wmax=0.0):
+    if sure is None:
+        assert np.array_equal(hit, ref_hit)
+    else:
+        assert np.all(ref_hit.astype(bool) >= sure) and np.all(ref_hit.astype(bool) <= maybe)
+        assert np.all(hit.astype(bool) >= sure) and np.all(hit.astype(bool) <= maybe)
+        tie = sure != maybe
+        assert tie.sum() <= 2
+        assert np.array_equal(hit[~tie], ref_hit[~tie])
+    assert set(np.unique(hit)) <= {0, 1}
+    inf = np.isinf(ref_clr)
+    assert np.array_equal(np.isinf(clr), inf)
+    tol = 2e-6 * (1.0 + np.abs(ref_clr[~inf]) + 2 * wmax)
+    err = np.abs(clr[~inf].astype(np.float64) - ref_clr[~inf])
+    assert np.all(err <= tol), float((err / tol).max())
+
+
+@pytest.mark.parametrize("n,n_paths,samples,seed", [
+    (5000, 3, 129, 11),      # 774 points: four point blocks, the last ragged
+    (40_000, 2, 129, 12),    # 40 Gaussian chunks combined by atomics
+    (3001, 1, 1, 13),        # two points
+])
+def test_collision_matches_oracle(raster, rctx, n, n_paths, samples, seed):
+    say(f"collision n={n} paths={n_paths}x{samples} seed={seed}")
+    g = scenes.lot_scene(n, seed, n_obstacles=6)
+    means, ls = g["means"], g["log_scales"]
+    # path points, and as many points within half a metre of Gaussians of this sparse map
+    pts = scenes.path_points(n_paths, seed + 1, samples=samples)
+    rng = np.random.default_rng(seed + 2)
+    near = means[:, rng.integers(0, n, pts.shape[1])] + rng.uniform(-0.5, 0.5, pts.shape).astype(np.float32)
+    pts = np.ascontiguousarray(np.concatenate([pts, near], 1))
+    means[0, :3] = np.nan
+    ls[1, 3:6] = np.inf
+    ls[2, 6:9] = -np.inf
+    hit, clr = run(raster, rctx, means, ls, pts)
+    ref_hit, ref_clr = oracle.collision(means, ls, pts, R_ROBOT, LAMBDA_G)
+    sure, maybe = tie_bands(means, ls, pts, R_ROBOT, LAMBDA_G)
+    check(hit, clr, ref_hit, ref_clr, sure, maybe, w_max(ls, LAMBDA_G))
+    say(f"  collisions {int(ref_hit.sum())} of {pts.shape[1]}")
+
+
+def test_collision_dense_obstacles(raster, rctx):
+    # points among the Gaussians themselves: about 40% collide
+    say("collision dense")
+    rng = np.random.default_rng(21)
+    means = rng.uniform(-2, 2, (3, 20_000)).astype(np.float32)
+    ls = rng.normal(-4.5, 0.5, (3, 20_000)).astype(np.float32)
+    pts = rng.uniform(-2.2, 2.2, (3, 1000)).astype(np.float32)
+    hit, clr = run(raster, rctx, means, ls, pts, r_robot=0.02)
+    ref_hit, ref_clr = oracle.collision(means, ls, pts, 0.02, LAMBDA_G)
+    assert 0.2 < ref_hit.mean() < 0.95
+    sure, maybe = tie_bands(means, ls, pts, 0.02, LAMBDA_G)
+    check(hit, clr, ref_hit, ref_clr, sure, maybe, w_max(ls, LAMBDA_G))
+
+
+def test_collision_exact_ties(raster, rctx):
+    # r = exp(0) = 1 exactly, lambda_g r + r_robot = 4: points on and next to the sphere of radius 4
+    say("collision ties")
+    means = np.zeros((3, 1), np.float32)
+    ls = np.array([[0.0], [-1.0], [-2.0]], np.float32)
+    rng = np.random.default_rng(22)
+    v = rng.normal(size=(3, 2000))
+    v /= np.linalg.norm(v, axis=0)
+    on = (4.0 * v).astype(np.float32)
+    axis = np.array([[4.0, 0, 0], [0, 0, 4.0], [np.nextafter(np.float32(4), np.float32(0)), 0, 0],
+                     [np.nextafter(np.float32(4), np.float32(8)), 0, 0], [0, -4.0, 0]], np.float32).T
+    pts = np.ascontiguousarray(np.concatenate([on, axis], 1))
+    hit, clr = run(raster, rctx, means, ls, pts, r_robot=1.0, lambda_g=3.0)
+    ref_hit, ref_clr = oracle.collision(means, ls, pts, 1.0, 3.0)
+    # r is exact on both sides, so the binary64 decision is the oracle's bit for bit
+    assert np.array_equal(hit, ref_hit)
+    assert list(hit[-5:]) == [0, 0, 1, 0, 0]
+    assert 0 < ref_hit[:2000].sum() < 2000
+    check(hit, clr, ref_hit, ref_clr, wmax=3.0)
+
+
+@pytest.mark.parametrize("case", ["no_gaussians", "all_ignored", "zero_radii", "no_points"])
+def test_collision_degenerate(raster, rctx, case):
+    say(f"collision degenerate {case}")
+    rng = np.random.default_rng(23)
+    pts = rng.uniform(-1, 1, (3, 300)).astype(np.float32)
+    means = rng.uniform(-1, 1, (3, 500)).astype(np.float32)
+    ls = rng.normal(-3, 0.5, (3, 500)).astype(np.float32)
+    r_robot, lam = R_ROBOT, LAMBDA_G
+    if case == "no_gaussians":
+        means, ls = np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32)
+    elif case == "all_ignored":
+        means[1, :] = np.inf
+    elif case == "zero_radii":
+        r_robot, lam = 0.0, 0.0  # d^2 < 0 never holds; clearance = nearest-mean distance
+    elif case == "no_points":
+        pts = np.zeros((3, 0), np.float32)
+    hit, clr = run(raster, rctx, means, ls, pts, r_robot, lam)
+    ref_hit, ref_clr = oracle.collision(means, ls, pts, r_robot, lam)
+    check(hit, clr, ref_hit, ref_clr, wmax=w_max(ls, lam))
+    if case in ("no_gaussians", "all_ignored"):
+        assert not hit.any() and np.all(np.isinf(clr))
+    if case == "zero_radii":
+        assert not hit.any()
+
+
+def test_collision_invalid_arguments(raster, rctx):
+    g = {"means": torch.zeros(3, 4, device="cuda"), "log_scales": torch.zeros(3, 4, device="cuda")}
+    pts = torch.zeros(3, 5, device="cuda")
+    for rr, lam in ((-1.0, 3.0), (0.1, -1.0), (float("nan"), 3.0), (0.1, float("inf"))):
+        with pytest.raises(raster.RtgError):
+            raster.collision_check(rctx, g, pts, rr, lam)
+
+
+def test_collision_full_size_sampled(raster, rctx):
+    # the benchmark's map (3M Gaussians over a 40 m x 40 m lot) and a layer of
+    # 64 five-metre primitives of 129 points; the oracle checks a sample of points
+    say("collision full size")
+    g = scenes.lot_scene()
+    pts = scenes.path_points(64, 7)
+    hit, clr = run(raster, rctx, g["means"], g["log_scales"], pts)
+    # a property at any size: the flag is the clearance below r_robot, up to rounding
+    wm = w_max(g["log_scales"], LAMBDA_G)
+    band = 4e-6 * (1 + np.abs(clr) + 2 * wm)
+    clear = np.abs(clr - R_ROBOT) > band
+    assert np.array_equal(hit[clear].astype(bool), (clr < R_ROBOT)[clear])
+    idx = np.random.default_rng(8).choice(pts.shape[1], 64, replace=False)
+    sub = np.ascontiguousarray(pts[:, idx])
+    ref_hit, ref_clr = oracle.collision(g["means"], g["log_scales"], sub, R_ROBOT, LAMBDA_G)
+    check(hit[idx], clr[idx], ref_hit, ref_clr, wmax=wm)
+    say(f"  collisions {int(hit.sum())} of {pts.shape[1]}")
