@@ -64,6 +64,8 @@ def lib():
         L.rtgo_keys.restype = ctypes.c_int
         L.rtgo_loss.argtypes = [i64, p, p, p, p, ctypes.c_double, p, p]
         L.rtgo_loss.restype = ctypes.c_double
+        L.rtgo_loss_ssim.argtypes = [ctypes.c_int, ctypes.c_int] + [p] * 4 + [ctypes.c_double] * 3 + [p] * 3
+        L.rtgo_loss_ssim.restype = ctypes.c_double
         L.rtgo_score.argtypes = [i64] + [p] * 7 + [ctypes.c_int, p, ctypes.c_int, ctypes.c_int, ctypes.c_int, p]
         L.rtgo_score.restype = ctypes.c_int
         L.rtgo_adjoint.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 2 + [p] * 10)
@@ -217,6 +219,24 @@ def loss(rgb, depth, target_rgb, target_depth, w_depth=0.5):
     L = lib().rtgo_loss(P, _ptr(rgb), _ptr(dep), _ptr(trgb), _ptr(tdep), float(w_depth),
                         _ptr(grgb), _ptr(gdep))
     return float(L), grgb, gdep
+
+
+def loss_ssim(rgb, depth, target_rgb, target_depth, width, height, w_depth=1.0, lambda1=0.4, lambda2=0.1,
+              ssim_map=False):
+    """Mapping loss of eq. (4) for one view: (L, dL/dC (3, P), dL/dD (P,)[, S map (3, P)]),
+    L = mean_p (w_depth |D - D*| + lambda1 sum_ch |C - C*|) + lambda2 (1 - SSIM(C, C*))."""
+    rgb = _d(rgb).reshape(3, -1); dep = _d(depth).reshape(-1)
+    trgb = _d(target_rgb).reshape(3, -1); tdep = _d(target_depth).reshape(-1)
+    P = int(width) * int(height)
+    assert rgb.shape == (3, P) and trgb.shape == (3, P) and dep.size == P and tdep.size == P
+    grgb = np.zeros_like(rgb); gdep = np.zeros_like(dep)
+    smap = np.zeros_like(rgb) if ssim_map else None
+    L = lib().rtgo_loss_ssim(int(width), int(height), _ptr(rgb), _ptr(dep), _ptr(trgb), _ptr(tdep),
+                             float(w_depth), float(lambda1), float(lambda2), _ptr(grgb), _ptr(gdep),
+                             _ptr(smap) if smap is not None else None)
+    if L != L:
+        raise MemoryError("oracle loss_ssim failed")
+    return (float(L), grgb, gdep, smap) if ssim_map else (float(L), grgb, gdep)
 
 
 def score(scene, cams, settings, tile=(16, 16), mode=0):

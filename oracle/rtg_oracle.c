@@ -707,6 +707,129 @@ double rtgo_loss(int64_t P, const double *rgb, const double *dep, const double *
     return L / (double)P;
 }
 
+/* SSIM term of the mapping loss of Sec. III eq. (4).  The paper names SSIM
+ * without defining it; this is the structural similarity index of Wang et
+ * al. (2004) in the form the 3DGS mappers it builds on use: per colour
+ * channel, local statistics under an 11 x 11 Gaussian window (sigma 1.5,
+ * weights w(a, b) = g(a) g(b) with g normalised to sum 1 over -5..5), pixels
+ * outside the image read as 0, C1 = 0.01^2, C2 = 0.03^2 (data range 1):
+ *   mx = sum w x,  sx = sum w x^2 - mx^2,  sxy = sum w x y - mx my,
+ *   S  = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sx + sy + C2)),
+ * and SSIM = the mean of S over the three channels and all pixels. */
+#define SSIM_R 5
+#define SSIM_C1 (0.01 * 0.01)
+#define SSIM_C2 (0.03 * 0.03)
+
+static void ssim_window(double g[2 * SSIM_R + 1])
+{
+    double sum = 0.0;
+    for (int k = -SSIM_R; k <= SSIM_R; k++) {
+        g[k + SSIM_R] = exp(-(double)(k * k) / (2.0 * 1.5 * 1.5));
+        sum += g[k + SSIM_R];
+    }
+    for (int k = 0; k <= 2 * SSIM_R; k++)
+        g[k] /= sum;
+}
+
+/* Mapping loss of Sec. III eq. (4) for one W x H view (planar rgb 3 x P):
+ *   L = (1/P) sum_p ( wd |D - D*| + l1 sum_ch |C - C*| ) + l2 (1 - SSIM(C, C*)),
+ * with its gradient with respect to the rendered C and D (the target gets
+ * none; sign(0) = 0).  The SSIM gradient is the exact reverse mode of the
+ * definition above: pixel p's S depends on x(q) for q in its window through
+ *   dS(p)/dx(q) = w(q - p) [dS/dmx + 2 (x(q) - mx) dS/dsx + (y(q) - my) dS/dsxy](p),
+ * gathered per q.  smap (3 x P) receives S when not NULL. */
+double rtgo_loss_ssim(int W, int H, const double *rgb, const double *dep, const double *trgb,
+                      const double *tdep, double wd, double l1, double l2, double *grgb, double *gdep,
+                      double *smap)
+{
+    const int64_t P = (int64_t)W * H;
+    double g[2 * SSIM_R + 1];
+    ssim_window(g);
+    double L = 0.0;
+    for (int64_t p = 0; p < P; p++) {
+        double row = 0.0;
+        for (int ch = 0; ch < 3; ch++) {
+            double e = rgb[ch * P + p] - trgb[ch * P + p];
+            row += fabs(e);
+            grgb[ch * P + p] = l1 * (e > 0.0 ? 1.0 : (e < 0.0 ? -1.0 : 0.0)) / (double)P;
+        }
+        double e = dep[p] - tdep[p];
+        L += wd * fabs(e) + l1 * row;
+        gdep[p] = wd * (e > 0.0 ? 1.0 : (e < 0.0 ? -1.0 : 0.0)) / (double)P;
+    }
+    L /= (double)P;
+    /* per pixel: mx, my, dS/dmx, dS/dsx, dS/dsxy */
+    double *st = (double *)malloc(sizeof(double) * 5 * (size_t)P);
+    if (!st)
+        return NAN;
+    double ssum = 0.0;
+    for (int ch = 0; ch < 3; ch++) {
+        const double *x = rgb + ch * P, *y = trgb + ch * P;
+        double csum = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : csum)
+        for (int v = 0; v < H; v++) {
+            for (int u = 0; u < W; u++) {
+                double mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+                for (int b = -SSIM_R; b <= SSIM_R; b++) {
+                    int vv = v + b;
+                    if (vv < 0 || vv >= H)
+                        continue;
+                    for (int a = -SSIM_R; a <= SSIM_R; a++) {
+                        int uu = u + a;
+                        if (uu < 0 || uu >= W)
+                            continue;
+                        double w = g[a + SSIM_R] * g[b + SSIM_R];
+                        double xv = x[(int64_t)vv * W + uu], yv = y[(int64_t)vv * W + uu];
+                        mx += w * xv;
+                        my += w * yv;
+                        exx += w * (xv * xv);
+                        eyy += w * (yv * yv);
+                        exy += w * (xv * yv);
+                    }
+                }
+                double sx = exx - mx * mx, sy = eyy - my * my, sxy = exy - mx * my;
+                double n1 = 2.0 * mx * my + SSIM_C1, n2 = 2.0 * sxy + SSIM_C2;
+                double d1 = mx * mx + my * my + SSIM_C1, d2 = sx + sy + SSIM_C2;
+                double S = (n1 * n2) / (d1 * d2);
+                int64_t p = (int64_t)v * W + u;
+                if (smap)
+                    smap[ch * P + p] = S;
+                csum += S;
+                st[5 * p + 0] = mx;
+                st[5 * p + 1] = my;
+                st[5 * p + 2] = (2.0 * my * n2 - S * 2.0 * mx * d2) / (d1 * d2); /* dS/dmx */
+                st[5 * p + 3] = -S / d2;                                        /* dS/dsx */
+                st[5 * p + 4] = 2.0 * n1 / (d1 * d2);                           /* dS/dsxy */
+            }
+        }
+        ssum += csum;
+        const double k = -l2 / (3.0 * (double)P);
+#pragma omp parallel for schedule(static)
+        for (int v = 0; v < H; v++) {
+            for (int u = 0; u < W; u++) {
+                int64_t q = (int64_t)v * W + u;
+                double acc = 0.0;
+                for (int b = -SSIM_R; b <= SSIM_R; b++) {
+                    int vv = v + b;
+                    if (vv < 0 || vv >= H)
+                        continue;
+                    for (int a = -SSIM_R; a <= SSIM_R; a++) {
+                        int uu = u + a;
+                        if (uu < 0 || uu >= W)
+                            continue;
+                        const double *sp = st + 5 * ((int64_t)vv * W + uu);
+                        double w = g[a + SSIM_R] * g[b + SSIM_R];
+                        acc += w * (sp[2] + 2.0 * (x[q] - sp[0]) * sp[3] + (y[q] - sp[1]) * sp[4]);
+                    }
+                }
+                grgb[ch * P + q] += k * acc;
+            }
+        }
+    }
+    free(st);
+    return L + l2 * (1.0 - ssum / (3.0 * (double)P));
+}
+
 /* Sum over pixels of the composited uncertainty for each of nv cameras
  * (cams: nv x 18).  The per-view sum is taken in pixel order. */
 /* View scores (Sec. IV-A eq. (7)) as sums over pixels, per pixel p:
