@@ -151,6 +151,38 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = P / (ms_step * 1e-3) / 1e6
     log(f"captured mapping step {ms_step:.3f} ms -> {value:.1f} Mpix/s")
+
+    # the same captured step with the full loss of eq. (4) (L1 depth + 0.4 L1 colour
+    # + 0.1 (1 - SSIM)), and the SSIM loss kernels alone (forward + backward)
+    mgs = raster.MapGraph(ctx, g, cams, target["rgb"], target["depth"], 1.0, S, grads=grads,
+                          lambda1=0.4, lambda2=0.1)
+    for _ in range(args.warmup):
+        mgs.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mgs.launch()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert mgs.status(), "mapping graph capacity overflow"
+    mgs.close()
+    ms_eq4 = (t1 - t0) * 1e3 / args.steps
+    fl = raster.Frame(ctx, g, cams, S)
+    fl.bin_sort()
+    img = fl.render(("rgb", "depth"))
+    for _ in range(3):
+        fl.loss_ssim(img["rgb"], img["depth"], target["rgb"], target["depth"], 1.0, 0.4, 0.1)
+    e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    e0.record()
+    for _ in range(20):
+        fl.loss_ssim(img["rgb"], img["depth"], target["rgb"], target["depth"], 1.0, 0.4, 0.1)
+    e1.record()
+    torch.cuda.synchronize()
+    fl.close()
+    ssim_us = e0.elapsed_time(e1) / 20 * 1e3
+    eq4 = {"ms_per_step": round(ms_eq4, 4), "mpix_per_s": round(P / (ms_eq4 * 1e-3) / 1e6, 1),
+           "loss_ssim_us": round(ssim_us, 1)}
+    log(f"captured mapping step with eq. (4): {eq4}")
     log("kernel ms per step: " + ", ".join(f"{k}={v[0] / args.steps:.3f}" for k, v in kern.items() if v[1]))
 
     if args.sweep_tiles:
@@ -387,6 +419,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "views_per_s": views,
+        "mapping_step_eq4_loss": eq4,
         "keyframes_8x1280x720": keyframes,
         "bookkeeping_2M": bookkeeping,
         "collision_3M": collision,

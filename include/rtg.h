@@ -155,6 +155,23 @@ rtg_status rtg_loss(rtg_ctx *ctx, rtg_frame *f, const float *rgb, const float *d
                     const float *target_rgb, const float *target_depth, float w_depth,
                     float *d_rgb, float *d_depth, double *loss, void *stream);
 
+/* The full mapping loss of Sec. III eq. (4), per view v of P_v pixels:
+ *   L = sum_v [ (1/P_v) sum_p ( w_depth |D - D*| + lambda_1 sum_ch |C - C*| )
+ *               + lambda_2 (1 - SSIM_v(C, C*)) ]
+ * (the paper: w_depth = 1, lambda_1 = 0.4, lambda_2 = 0.1), and dL/dC, dL/dD
+ * (sign(0) = 0) in rtg_render's packed layout.  SSIM_v is the mean over the
+ * three channels and P_v pixels of the structural similarity index of Wang
+ * et al. with an 11x11 Gaussian window (sigma 1.5, separable, normalised),
+ * pixels outside the view read as 0, C1 = 0.01^2, C2 = 0.03^2 (colours in
+ * [0, 1]).  Binary32 filtering; the loss is summed in binary64 in a fixed
+ * order.  loss: device pointer to one double (written).  d_rgb / d_depth may
+ * be NULL (both NULL: the loss only).  Scratch: 36 bytes per pixel, kept in
+ * the frame. */
+rtg_status rtg_loss_ssim(rtg_ctx *ctx, rtg_frame *f, const float *rgb, const float *depth,
+                         const float *target_rgb, const float *target_depth, float w_depth,
+                         float lambda_1, float lambda_2, float *d_rgb, float *d_depth, double *loss,
+                         void *stream);
+
 /* Reverse mode of rtg_render and rtg_project (the map is "refined through
  * backpropagation", Sec. IV-A): given dL/d(image) in rtg_render's layout
  * (d_alpha and d_unc nullable = zero), ADDS dL/d(means, log_scales, raw
@@ -233,6 +250,16 @@ rtg_status rtg_map_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_
                                 const float *target_rgb, const float *target_depth, float w_depth,
                                 float *rgb, float *depth, double *loss, const rtg_grads *grads,
                                 rtg_graph **out, void *stream);
+/* The same captured mapping iteration with the full loss of eq. (4) as
+ * computed by rtg_loss_ssim (L1 depth weighted by w_depth, L1 colour by
+ * lambda_1, 1 - SSIM by lambda_2; the paper: 1, 0.4, 0.1).  Launch, status
+ * and destroy as for rtg_map_graph_create. */
+rtg_status rtg_map_graph_create_ssim(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
+                                     int32_t n_views, const rtg_settings *settings,
+                                     const float *target_rgb, const float *target_depth,
+                                     float w_depth, float lambda_1, float lambda_2, float *rgb,
+                                     float *depth, double *loss, const rtg_grads *grads,
+                                     rtg_graph **out, void *stream);
 rtg_status rtg_map_graph_launch(rtg_graph *gr, void *stream);
 rtg_status rtg_map_graph_status(rtg_graph *gr);
 void rtg_map_graph_destroy(rtg_graph *gr);

@@ -70,6 +70,8 @@ SIGNATURES = {
     "rtg_frame_stats": (i32, [vp, vp, _c.POINTER(i64), vp]),
     "rtg_map_graph_create": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, _c.POINTER(Settings),
                                    vp, vp, f32, vp, vp, vp, _c.POINTER(Grads), _c.POINTER(vp), vp]),
+    "rtg_map_graph_create_ssim": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, _c.POINTER(Settings),
+                                        vp, vp, f32, f32, f32, vp, vp, vp, _c.POINTER(Grads), _c.POINTER(vp), vp]),
     "rtg_map_graph_launch": (i32, [vp, vp]),
     "rtg_map_graph_status": (i32, [vp]),
     "rtg_map_graph_destroy": (None, [vp]),
@@ -80,6 +82,7 @@ SIGNATURES = {
     "rtg_uncertainty_update": (i32, [vp, i64, vp, vp, vp, i32, vp, vp]),
     "rtg_region_grid": (i32, [_c.POINTER(_c.c_double), _c.c_double, _c.POINTER(i32)]),
     "rtg_region_utility": (i32, [vp, i64, vp, vp, _c.POINTER(_c.c_double), _c.c_double, vp, vp, vp, vp]),
+    "rtg_loss_ssim": (i32, [vp, vp, vp, vp, vp, vp, f32, f32, f32, vp, vp, vp, vp]),
     "rtg_collision_check": (i32, [vp, _c.POINTER(Gaussians), vp, i64, f32, f32, vp, vp, vp]),
     "rtg_timing_enable": (i32, [vp, i32]),
     "rtg_timing_read": (i32, [vp, i32, _c.POINTER(_c.c_double), _c.POINTER(i64)]),

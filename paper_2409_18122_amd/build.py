@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rtg_kernels.hip", "rtg_collision.hip", "rtg_abi.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rtg_kernels.hip", "rtg_ssim.hip", "rtg_collision.hip", "rtg_abi.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "rtg_internal.h"),
            os.path.join(os.path.dirname(HERE), "include", "rtg.h")]
 LIB = os.path.join(HERE, "librtg.so")

@@ -345,7 +345,7 @@ struct rtg_frame {
     Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist;
     Buf geo0, geo1, q64, attr, unc, gid, view, rect, pbox, dkey, ntiles, skey, skey2, order, order2;
     Buf inst_off, tkey, tkey2, irec, irec2, ranges;
-    Buf T_final, n_last, g2d, loss_part, score_part;
+    Buf T_final, n_last, g2d, loss_part, score_part, ssim_maps;
 
     Records records() const {
         return Records{geo0.as<float4>(), geo1.as<float4>(), q64.as<double4>(), attr.as<float4>(), unc.as<float>(),
@@ -649,6 +649,31 @@ rtg_status rtg_loss(rtg_ctx* ctx, rtg_frame* f, const float* rgb, const float* d
     loss_l1(f->views.as<ViewDev>(), f->n_views, f->L.max_pix, rgb, depth, target_rgb, target_depth, w_depth, d_rgb,
             d_depth, f->loss_part.as<double>(), bx * f->n_views, loss, (hipStream_t)stream);
     return check_launch("loss");
+}
+
+rtg_status rtg_loss_ssim(rtg_ctx* ctx, rtg_frame* f, const float* rgb, const float* depth, const float* target_rgb,
+                         const float* target_depth, float w_depth, float lambda_1, float lambda_2, float* d_rgb,
+                         float* d_depth, double* loss, void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (!f) return set_err(RTG_ERR_INVALID, "frame is NULL");
+    if (!rgb || !depth || !target_rgb || !target_depth || !loss)
+        return set_err(RTG_ERR_INVALID, "rgb, depth, targets and loss must be non-NULL");
+    if (!std::isfinite(w_depth) || !std::isfinite(lambda_1) || !std::isfinite(lambda_2))
+        return set_err(RTG_ERR_INVALID, "w_depth, lambda_1 and lambda_2 must be finite");
+    int max_w = 0, max_h = 0;
+    for (const ViewDev& v : f->L.views) {
+        max_w = std::max(max_w, (int)v.W);
+        max_h = std::max(max_h, (int)v.H);
+    }
+    const int bpv = ssim_blocks_per_view(max_w, max_h);
+    const uint64_t P = f->L.hdr.pix_total;
+    RTG_TRY(f->loss_part.ensure(ctx, sizeof(double) * (size_t)std::max(1, bpv * f->n_views)));
+    RTG_TRY(f->ssim_maps.ensure(ctx, sizeof(float) * 9 * (size_t)std::max<uint64_t>(P, 1)));
+    Timer tm(ctx, 4, (hipStream_t)stream);
+    loss_ssim(f->views.as<ViewDev>(), f->n_views, bpv, P, rgb, depth, target_rgb, target_depth, w_depth, lambda_1,
+              lambda_2, f->ssim_maps.as<float>(), f->loss_part.as<double>(), d_rgb, d_depth, loss,
+              (hipStream_t)stream);
+    return check_launch("loss with SSIM");
 }
 
 rtg_status rtg_render_backward(rtg_ctx* ctx, rtg_frame* f, const float* d_rgb, const float* d_depth,
@@ -1029,10 +1054,11 @@ rtg_status rtg_score_graph_status(rtg_graph* gr) {
 
 void rtg_score_graph_destroy(rtg_graph* gr) { graph_free(gr); }
 
-rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int32_t n_views,
-                                const rtg_settings* settings, const float* target_rgb, const float* target_depth,
-                                float w_depth, float* rgb, float* depth, double* loss, const rtg_grads* grads,
-                                rtg_graph** out, void* stream) {
+// The captured mapping iteration, with the loss of rtg_loss (eq4 false) or rtg_loss_ssim (eq4 true).
+static rtg_status map_graph_build(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int32_t n_views,
+                                  const rtg_settings* settings, const float* target_rgb, const float* target_depth,
+                                  float w_depth, bool eq4, float lambda_1, float lambda_2, float* rgb, float* depth,
+                                  double* loss, const rtg_grads* grads, rtg_graph** out, void* stream) {
     if (!out) return set_err(RTG_ERR_INVALID, "out is NULL");
     *out = nullptr;
     RTG_TRY(ctx_ok(ctx));
@@ -1040,7 +1066,8 @@ rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_
     RTG_TRY(check_cams(cams, n_views));
     if (!target_rgb || !target_depth || !rgb || !depth || !loss || !grads)
         return set_err(RTG_ERR_INVALID, "targets, outputs, loss and grads must be non-NULL");
-    if (!std::isfinite(w_depth)) return set_err(RTG_ERR_INVALID, "w_depth is not finite");
+    if (!std::isfinite(w_depth) || !std::isfinite(lambda_1) || !std::isfinite(lambda_2))
+        return set_err(RTG_ERR_INVALID, "w_depth, lambda_1 and lambda_2 must be finite");
     rtg_settings st;
     RTG_TRY(resolve_settings(ctx, settings, &st));
     hipStream_t s = (hipStream_t)stream;
@@ -1082,11 +1109,20 @@ rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_
     };
     const uint64_t P = f->L.hdr.pix_total;
     const int bx = (f->L.max_pix + 255) / 256;
+    int max_w = 0, max_h = 0;
+    for (const ViewDev& v : f->L.views) {
+        max_w = std::max(max_w, (int)v.W);
+        max_h = std::max(max_h, (int)v.H);
+    }
+    const int bpv = ssim_blocks_per_view(max_w, max_h);
+    const int n_part = std::max(1, (eq4 ? bpv : bx) * n_views);
+    if (eq4 && (rs = f->ssim_maps.ensure(ctx, sizeof(float) * 9 * (size_t)std::max<uint64_t>(P, 1))) != RTG_OK)
+        return fail(rs);
     if ((rs = alloc_records(f, (uint32_t)rec_cap)) != RTG_OK) return fail(rs);
     if ((rs = alloc_instances(f, (uint32_t)inst_cap, f->L.hdr.tiles_total)) != RTG_OK) return fail(rs);
     if ((rs = ensure_pixel_state(f)) != RTG_OK) return fail(rs);
     if ((rs = f->g2d.ensure(ctx, sizeof(double) * G2D_STRIDE * (size_t)rec_cap)) != RTG_OK) return fail(rs);
-    if ((rs = f->loss_part.ensure(ctx, sizeof(double) * (size_t)std::max(1, bx * n_views))) != RTG_OK) return fail(rs);
+    if ((rs = f->loss_part.ensure(ctx, sizeof(double) * (size_t)n_part)) != RTG_OK) return fail(rs);
     if ((rs = f->d_img.ensure(ctx, sizeof(float) * 4 * (size_t)std::max<uint64_t>(P, 1))) != RTG_OK) return fail(rs);
     f->R = (uint32_t)rec_cap;
     f->K = inst_cap;
@@ -1114,8 +1150,13 @@ rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_
                     f->n_contrib.as<uint32_t>()};
         render_forward(st.tile_w, st.tile_h, st.batch, f->views.as<ViewDev>(), n_views, f->L.hdr.tiles_total,
                        f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(st), o, f->ctr(C_FLAGS), cs);
-        loss_l1(f->views.as<ViewDev>(), n_views, f->L.max_pix, rgb, depth, target_rgb, target_depth, w_depth, d_rgb,
-                d_dep, f->loss_part.as<double>(), bx * n_views, loss, cs);
+        if (eq4)
+            loss_ssim(f->views.as<ViewDev>(), n_views, bpv, P, rgb, depth, target_rgb, target_depth, w_depth,
+                      lambda_1, lambda_2, f->ssim_maps.as<float>(), f->loss_part.as<double>(), d_rgb, d_dep, loss,
+                      cs);
+        else
+            loss_l1(f->views.as<ViewDev>(), n_views, f->L.max_pix, rgb, depth, target_rgb, target_depth, w_depth,
+                    d_rgb, d_dep, f->loss_part.as<double>(), bx * n_views, loss, cs);
         fill_u32(f->g2d.as<uint32_t>(), 0u, (uint64_t)2 * G2D_STRIDE * rec_cap, cs);
         render_backward(st.tile_w, st.tile_h, st.batch, f->views.as<ViewDev>(), n_views, f->L.hdr.tiles_total,
                         f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(st), f->T_final.as<float>(),
@@ -1147,6 +1188,22 @@ rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_
     }
     *out = gr;
     return RTG_OK;
+}
+
+rtg_status rtg_map_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int32_t n_views,
+                                const rtg_settings* settings, const float* target_rgb, const float* target_depth,
+                                float w_depth, float* rgb, float* depth, double* loss, const rtg_grads* grads,
+                                rtg_graph** out, void* stream) {
+    return map_graph_build(ctx, g, cams, n_views, settings, target_rgb, target_depth, w_depth, false, 1.0f, 0.0f,
+                           rgb, depth, loss, grads, out, stream);
+}
+
+rtg_status rtg_map_graph_create_ssim(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cams, int32_t n_views,
+                                     const rtg_settings* settings, const float* target_rgb, const float* target_depth,
+                                     float w_depth, float lambda_1, float lambda_2, float* rgb, float* depth,
+                                     double* loss, const rtg_grads* grads, rtg_graph** out, void* stream) {
+    return map_graph_build(ctx, g, cams, n_views, settings, target_rgb, target_depth, w_depth, true, lambda_1,
+                           lambda_2, rgb, depth, loss, grads, out, stream);
 }
 
 rtg_status rtg_map_graph_launch(rtg_graph* gr, void* stream) {

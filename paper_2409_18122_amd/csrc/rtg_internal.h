@@ -165,6 +165,14 @@ void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_
                  const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s);
 int score_persistent_blocks(int tw, int th, int batch);
+// Mapping loss of eq. (4) with SSIM over packed views: blocks_per_view from
+// ssim_blocks_per_view(widest, tallest view); maps: 9 x pix_total floats of
+// scratch; partial: blocks_per_view x n_views doubles; d_rgb / d_depth may be
+// NULL; loss: one device double.
+int ssim_blocks_per_view(int max_w, int max_h);
+void loss_ssim(const ViewDev* views, int n_views, int blocks_per_view, uint64_t pix_total, const float* rgb,
+               const float* depth, const float* trgb, const float* tdepth, float w_depth, float l1, float l2,
+               float* maps, double* partial, float* d_rgb, float* d_depth, double* loss, hipStream_t s);
 // Collision check of np points (planar 3 x np) against the map; packed,
 // bound: n float4 / float2 scratch, collide: np int32 (required), clear_key:
 // np uint32 scratch, clearance: np floats or NULL.

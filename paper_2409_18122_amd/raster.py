@@ -174,6 +174,18 @@ class Frame:
                              _ptr(loss), _stream()))
         return loss, d_rgb, d_depth
 
+    def loss_ssim(self, rgb, depth, target_rgb, target_depth, w_depth=1.0, lambda1=0.4, lambda2=0.1,
+                  want_grad=True):
+        """The full loss of eq. (4): L1 depth + lambda1 L1 colour + lambda2 (1 - SSIM), per view."""
+        dev = rgb.device
+        loss = torch.empty(1, device=dev, dtype=torch.float64)
+        d_rgb = torch.empty_like(rgb) if want_grad else None
+        d_depth = torch.empty_like(depth) if want_grad else None
+        check(lib().rtg_loss_ssim(self.ctx.handle, self.handle, _ptr(rgb), _ptr(depth), _ptr(target_rgb),
+                                  _ptr(target_depth), float(w_depth), float(lambda1), float(lambda2),
+                                  _ptr(d_rgb), _ptr(d_depth), _ptr(loss), _stream()))
+        return loss, d_rgb, d_depth
+
     def backward(self, d_rgb, d_depth, d_alpha=None, d_unc=None, grads=None):
         """Adds dL/dparams into `grads` (dict of tensors shaped like the map)."""
         if grads is None:
@@ -307,10 +319,13 @@ class ScoreGraph:
 
 
 class MapGraph:
-    """One mapping iteration (render, L1 loss, backward) on fixed keyframes,
-    captured once and replayed; gradients are added into `grads`."""
+    """One mapping iteration (render, loss, backward) on fixed keyframes,
+    captured once and replayed; gradients are added into `grads`.  The loss is
+    the L1 form of rtg_loss, or with lambda1 / lambda2 given the full eq. (4)
+    of rtg_loss_ssim."""
 
-    def __init__(self, ctx, g, cams, target_rgb, target_depth, w_depth=0.5, settings=None, grads=None):
+    def __init__(self, ctx, g, cams, target_rgb, target_depth, w_depth=0.5, settings=None, grads=None,
+                 lambda1=None, lambda2=None):
         self.ctx = ctx
         self._g = g
         self._gs = make_gaussians(g)
@@ -326,10 +341,18 @@ class MapGraph:
         self._targets = (target_rgb, target_depth)
         gr = Grads(*[_ptr(self.grads.get(k)) for k in GRAD_KEYS])
         h = ctypes.c_void_p()
-        check(lib().rtg_map_graph_create(ctx.handle, ctypes.byref(self._gs), self._cams, len(cams),
-                                         ctypes.byref(self.settings), _ptr(target_rgb), _ptr(target_depth),
-                                         float(w_depth), _ptr(self.rgb), _ptr(self.depth), _ptr(self.loss),
-                                         ctypes.byref(gr), ctypes.byref(h), _stream()))
+        if lambda1 is None and lambda2 is None:
+            check(lib().rtg_map_graph_create(ctx.handle, ctypes.byref(self._gs), self._cams, len(cams),
+                                             ctypes.byref(self.settings), _ptr(target_rgb), _ptr(target_depth),
+                                             float(w_depth), _ptr(self.rgb), _ptr(self.depth), _ptr(self.loss),
+                                             ctypes.byref(gr), ctypes.byref(h), _stream()))
+        else:
+            check(lib().rtg_map_graph_create_ssim(ctx.handle, ctypes.byref(self._gs), self._cams, len(cams),
+                                                  ctypes.byref(self.settings), _ptr(target_rgb), _ptr(target_depth),
+                                                  float(w_depth), float(0.4 if lambda1 is None else lambda1),
+                                                  float(0.1 if lambda2 is None else lambda2), _ptr(self.rgb),
+                                                  _ptr(self.depth), _ptr(self.loss), ctypes.byref(gr),
+                                                  ctypes.byref(h), _stream()))
         self.handle = h
 
     def launch(self):

@@ -63,6 +63,7 @@ def test_null_arguments_rejected_on_host(L):
     assert L.rtg_bin_sort(None, None, None, None) == -1
     assert L.rtg_render(None, None, None, None, None, None, None) == -1
     assert L.rtg_loss(None, None, None, None, None, None, 0.5, None, None, None, None) == -1
+    assert L.rtg_loss_ssim(None, None, None, None, None, None, 1.0, 0.4, 0.1, None, None, None, None) == -1
     assert L.rtg_render_backward(None, None, None, None, None, None, None, None) == -1
     assert L.rtg_score_views(None, None, None, 1, None, None, 1, 0, None) == -1
     assert L.rtg_score_graph_create(None, None, 1, 1, 1, None, 0, None, 0, ctypes.byref(out), None) == -1
@@ -74,6 +75,8 @@ def test_null_arguments_rejected_on_host(L):
     assert L.rtg_autotune(None, None, None, 1, 0, None, None) == -1
     assert L.rtg_map_graph_create(None, None, None, 1, None, None, None, 0.5, None, None, None, None,
                                   ctypes.byref(out), None) == -1
+    assert L.rtg_map_graph_create_ssim(None, None, None, 1, None, None, None, 1.0, 0.4, 0.1, None, None, None,
+                                       None, ctypes.byref(out), None) == -1
     assert L.rtg_map_graph_launch(None, None) == -1
     assert L.rtg_map_graph_status(None) == -1
     assert L.rtg_view_utility(None, None, None, 1, None, 5.0, None, 1.0, None, None, None, None, None) == -1

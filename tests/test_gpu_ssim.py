@@ -1,0 +1,210 @@
+"""GPU parity of the full mapping loss of eq. (4) (L1 depth + lambda1 L1
+colour + lambda2 (1 - SSIM)) against the oracle, through the C ABI: the loss
+within 1e-6 relative (plus 2e-7 per view for the binary32 filtering), its
+image gradient per element within 1e-3 (|g| + rms(g)), and the parameter
+gradients of a whole mapping step with this loss within 1e-3 relative."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from gpu_util import GRAD_REL_TOL, elementwise_violations, grad_rel_errors, grads_to_numpy
+
+pytestmark = pytest.mark.gpu
+
+W_DEPTH, L1, L2 = 1.0, 0.4, 0.1
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def raster():
+    from paper_2409_18122_amd import raster as r
+    return r
+
+
+@pytest.fixture(scope="module")
+def rctx(raster):
+    return raster.Context(0)
+
+
+def S(**kw):
+    return dict(scenes.DEFAULT_SETTINGS, **kw)
+
+
+def cams_of(sizes):
+    out = []
+    for w, h in sizes:
+        fx, fy, cx, cy = scenes.default_intrinsics(w, h)
+        out.append(scenes.make_camera(w, h, fx, fy, cx, cy))
+    return out
+
+
+def random_images(sizes, seed):
+    rng = np.random.default_rng(seed)
+    P = sum(w * h for w, h in sizes)
+    x = rng.random((3 * P,)).astype(np.float32)
+    d = rng.uniform(1, 5, P).astype(np.float32)
+    # views packed: 3 planes per view, view after view; the target is a noisy copy
+    y = np.clip(x + rng.normal(0, 0.1, x.shape), 0, 1).astype(np.float32)
+    td = (d + rng.normal(0, 0.1, P)).astype(np.float32)
+    return x, d, y, td
+
+
+def oracle_packed(sizes, x, d, y, td, **kw):
+    """Sum of the per-view oracle losses and the packed gradients."""
+    L, gx, gd = 0.0, [], []
+    o3 = o1 = 0
+    for w, h in sizes:
+        P = w * h
+        l, g, g_d = oracle.loss_ssim(x[o3:o3 + 3 * P].reshape(3, P), d[o1:o1 + P], y[o3:o3 + 3 * P].reshape(3, P),
+                                     td[o1:o1 + P], w, h, **kw)
+        L += l
+        gx.append(g.reshape(-1))
+        gd.append(g_d)
+        o3 += 3 * P
+        o1 += P
+    return L, np.concatenate(gx), np.concatenate(gd)
+
+
+def assert_grad_close(gpu, ref, label):
+    rms = np.sqrt(np.mean(ref * ref))
+    bad = np.abs(gpu - ref) > GRAD_REL_TOL * (np.abs(ref) + rms)
+    rel = np.linalg.norm(gpu - ref) / (np.linalg.norm(ref) + 1e-300)
+    say(f"  {label}: relative error {rel:.2e}, element violations {int(bad.sum())}")
+    assert rel <= GRAD_REL_TOL and not bad.any()
+
+
+def frame_for(raster, rctx, sizes):
+    g, _ = scenes.tiny_scene(20, 5)
+    f = raster.Frame(rctx, raster.to_device(g), cams_of(sizes), S())
+    return f
+
+
+@pytest.mark.parametrize("sizes", [
+    [(37, 23)],                          # ragged 16x16 tiles
+    [(64, 48), (16, 16), (100, 7)],      # packed views of different sizes, one shorter than the window
+    [(640, 480)],
+])
+def test_loss_ssim_random_images(raster, rctx, sizes):
+    say(f"SSIM loss on random images {sizes}")
+    x, d, y, td = random_images(sizes, len(sizes) * 7 + sizes[0][0])
+    f = frame_for(raster, rctx, sizes)
+    t = lambda a: torch.as_tensor(a).cuda()
+    loss, g_rgb, g_dep = f.loss_ssim(t(x), t(d), t(y), t(td), W_DEPTH, L1, L2)
+    torch.cuda.synchronize()
+    L_ref, gx_ref, gd_ref = oracle_packed(sizes, x, d, y, td, w_depth=W_DEPTH, lambda1=L1, lambda2=L2)
+    say(f"  loss gpu {loss.item():.9f} oracle {L_ref:.9f}")
+    assert abs(loss.item() - L_ref) <= 1e-6 * abs(L_ref) + 2e-7 * len(sizes)
+    assert_grad_close(g_rgb.cpu().numpy().astype(np.float64), gx_ref, "d_rgb")
+    np.testing.assert_allclose(g_dep.cpu().numpy(), gd_ref, rtol=1e-6, atol=0)
+    # the loss alone, without gradients, is the same value
+    loss2, a, b = f.loss_ssim(t(x), t(d), t(y), t(td), W_DEPTH, L1, L2, want_grad=False)
+    assert a is None and b is None and loss2.item() == loss.item()
+    f.close()
+
+
+def test_loss_ssim_weights(raster, rctx):
+    sizes = [(48, 40)]
+    x, d, y, td = random_images(sizes, 99)
+    f = frame_for(raster, rctx, sizes)
+    t = lambda a: torch.as_tensor(a).cuda()
+    for w_d, l1, l2 in ((0.0, 0.0, 1.0), (0.5, 1.0, 0.0), (2.0, 0.3, 0.7)):
+        loss, g_rgb, g_dep = f.loss_ssim(t(x), t(d), t(y), t(td), w_d, l1, l2)
+        L_ref, gx_ref, gd_ref = oracle_packed(sizes, x, d, y, td, w_depth=w_d, lambda1=l1, lambda2=l2)
+        assert abs(loss.item() - L_ref) <= 1e-6 * abs(L_ref) + 2e-7
+        assert_grad_close(g_rgb.cpu().numpy().astype(np.float64), gx_ref, f"weights {w_d, l1, l2}")
+    # with lambda2 = 0 the loss is the config-form L1 loss of rtg_loss
+    l_a, gr_a, gd_a = f.loss_ssim(t(x), t(d), t(y), t(td), 0.5, 1.0, 0.0)
+    l_b, gr_b, gd_b = f.loss(t(x), t(d), t(y), t(td), 0.5)
+    assert abs(l_a.item() - l_b.item()) <= 1e-12 * abs(l_b.item())
+    assert torch.equal(gr_a, gr_b) and torch.equal(gd_a, gd_b)
+    f.close()
+
+
+def test_loss_ssim_identical_images(raster, rctx):
+    sizes = [(40, 30), (17, 33)]
+    x, d, _, _ = random_images(sizes, 5)
+    f = frame_for(raster, rctx, sizes)
+    t = lambda a: torch.as_tensor(a).cuda()
+    loss, g_rgb, g_dep = f.loss_ssim(t(x), t(d), t(x), t(d), W_DEPTH, L1, L2)
+    # S = 1 up to binary32 rounding of the local statistics
+    assert abs(loss.item()) < 1e-6
+    assert float(g_dep.abs().max()) == 0.0
+    assert float(g_rgb.abs().max()) < 1e-4
+    f.close()
+
+
+def test_invalid_weights(raster, rctx):
+    sizes = [(16, 16)]
+    x, d, y, td = random_images(sizes, 1)
+    f = frame_for(raster, rctx, sizes)
+    t = lambda a: torch.as_tensor(a).cuda()
+    with pytest.raises(raster.RtgError):
+        f.loss_ssim(t(x), t(d), t(y), t(td), W_DEPTH, float("nan"), L2)
+    f.close()
+
+
+def test_c2_mapping_step_with_ssim(raster, rctx):
+    # the full paper-faithful step on the 640x480 frame: render, eq. (4), backward
+    g, cams, target = scenes.config2()
+    say("C2 mapping step with the SSIM loss")
+    dev = raster.to_device(g)
+    f = raster.Frame(rctx, dev, cams, S())
+    f.bin_sort()
+    out = f.render()
+    rt = oracle.render(target, cams[0], S())
+    trgb = rt["rgb"].astype(np.float32)
+    tdep = rt["depth"].astype(np.float32)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1)).cuda()
+    loss, d_rgb, d_dep = f.loss_ssim(out["rgb"], out["depth"], t(trgb), t(tdep), W_DEPTH, L1, L2)
+    x = out["rgb"].cpu().numpy().astype(np.float64).reshape(3, -1)
+    dd = out["depth"].cpu().numpy().astype(np.float64)
+    L_ref, gr, gd = oracle.loss_ssim(x, dd, trgb.reshape(3, -1), tdep.reshape(-1), 640, 480,
+                                     w_depth=W_DEPTH, lambda1=L1, lambda2=L2)
+    say(f"  loss gpu {loss.item():.9f} oracle {L_ref:.9f}")
+    assert abs(loss.item() - L_ref) <= 1e-6 * abs(L_ref) + 2e-7
+    assert_grad_close(d_rgb.cpu().numpy().astype(np.float64), gr.reshape(-1), "d_rgb")
+    # parameter gradients: the GPU backward of its own image gradient vs the
+    # oracle adjoint of the oracle's image gradient
+    grads = f.backward(d_rgb, d_dep)
+    ref = oracle.adjoint(g, cams[0], S(), g_rgb=gr.reshape(3, 480, 640), g_depth=gd.reshape(480, 640))
+    gpu = grads_to_numpy(grads)
+    rel = grad_rel_errors(gpu, ref)
+    say(f"  parameter gradients: relative errors {rel}, element violations {elementwise_violations(gpu, ref)}")
+    for k, v in rel.items():
+        assert v <= GRAD_REL_TOL, (k, v)
+    f.close()
+
+
+def test_map_graph_with_ssim_matches_eager(raster, rctx):
+    g, cams, target = scenes.config4(n=80_000, n_views=2, width=320, height=180)
+    dev = raster.to_device(g)
+    tdev = raster.to_device(target)
+    timg, tf = raster.render(rctx, tdev, cams, S(), want=("rgb", "depth"))
+    tf.close()
+    say("SSIM map graph: eager reference step")
+    f = raster.Frame(rctx, dev, cams, S())
+    f.bin_sort()
+    out = f.render(("rgb", "depth"))
+    loss, d_rgb, d_dep = f.loss_ssim(out["rgb"], out["depth"], timg["rgb"], timg["depth"], W_DEPTH, L1, L2)
+    ref = f.backward(d_rgb, d_dep)
+    f.close()
+    say("SSIM map graph: capture and replay 3 times")
+    mg = raster.MapGraph(rctx, dev, cams, timg["rgb"], timg["depth"], W_DEPTH, S(), lambda1=L1, lambda2=L2)
+    for rep in range(3):
+        lv = mg.launch()
+        assert mg.status()
+        torch.cuda.synchronize()
+        _ = (dev["means"] * 1.0).sum().item()  # eager work between replays
+        assert torch.equal(mg.rgb, out["rgb"]) and torch.equal(mg.depth, out["depth"]), rep
+        assert lv.item() == loss.item(), rep
+    for k in ref:
+        a = mg.grads[k].double().cpu().numpy()
+        b = 3.0 * ref[k].double().cpu().numpy()
+        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-300)
+        assert rel <= 1e-5, (k, rel)
+    mg.close()
