@@ -110,14 +110,16 @@ class _G:
     def __init__(self, s):
         self.n = int(np.asarray(s["opacity"]).shape[0])
         self.means = _d(s["means"]).reshape(3, self.n)
-        self.ls = _d(s["log_scales"]).reshape(3, self.n)
-        self.q = _d(s["quats"]).reshape(4, self.n)
+        # isotropic scenes carry one log-radius per Gaussian (1 x N) and no quaternion
+        ls = _d(s["log_scales"])
+        self.ls = ls.reshape(-1, self.n)
+        self.q = _d(s["quats"]).reshape(4, self.n) if s.get("quats") is not None else None
         self.o = _d(s["opacity"]).reshape(self.n)
         self.c = _d(s.get("colors", np.zeros((3, self.n)))).reshape(3, self.n)
         self.u = _d(s.get("uncert", np.zeros(self.n))).reshape(self.n)
 
     def geo(self):
-        return [_ptr(self.means), _ptr(self.ls), _ptr(self.q), _ptr(self.o)]
+        return [_ptr(self.means), _ptr(self.ls), _ptr(self.q) if self.q is not None else None, _ptr(self.o)]
 
     def all(self):
         return self.geo() + [_ptr(self.c), _ptr(self.u)]
@@ -133,7 +135,8 @@ def cam_array(cam):
 def set_array(settings):
     """Settings are taken at their binary32 values, as the library receives them."""
     f = lambda k: float(np.float32(settings[k]))
-    return _d([f("T_min"), f("alpha_min"), f("alpha_max"), f("z_near"), f("eps2d")])
+    return _d([f("T_min"), f("alpha_min"), f("alpha_max"), f("z_near"), f("eps2d"),
+               1.0 if settings.get("isotropic", 0) else 0.0])
 
 
 def project(scene, cam, settings):

@@ -56,9 +56,10 @@ typedef struct {
     double T[3];
 } ocam;
 
-/* settings array layout: T_min, alpha_min, alpha_max, z_near, eps2d */
+/* settings array layout: T_min, alpha_min, alpha_max, z_near, eps2d, isotropic */
 typedef struct {
     double T_min, alpha_min, alpha_max, z_near, eps2d;
+    int iso; /* the paper's 8-parameter isotropic Gaussians (Sec. III) */
 } oset;
 
 /* Gaussians: planar arrays of N entries each */
@@ -91,6 +92,7 @@ static void read_set(const double *a, oset *s)
     s->alpha_max = a[2];
     s->z_near = a[3];
     s->eps2d = a[4];
+    s->iso = a[5] != 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -116,13 +118,17 @@ typedef struct {
     int u0, u1, v0, v1; /* inclusive pixel box, clipped to the image */
 } oproj;
 
-static int finite_geometry(const ogauss *g, int64_t i)
+/* Isotropic Gaussians read one log-radius per Gaussian (the first n
+ * log-scale values) and no quaternion. */
+static int finite_geometry(const ogauss *g, int64_t i, int iso)
 {
     int64_t n = g->n;
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < 3; k++)
         if (!isfinite(g->means[k * n + i])) return 0;
+    if (iso)
+        return isfinite(g->log_scales[i]) && isfinite(g->opacity[i]);
+    for (int k = 0; k < 3; k++)
         if (!isfinite(g->log_scales[k * n + i])) return 0;
-    }
     for (int k = 0; k < 4; k++)
         if (!isfinite(g->quats[k * n + i])) return 0;
     return isfinite(g->opacity[i]);
@@ -136,14 +142,81 @@ static uint32_t f32_bits(double d)
     return b;
 }
 
+/* Projected mean, inverse covariance and the pixel box of {alpha >= alpha_min}
+ * (d^T Q d <= 2 ln(o / alpha_min), exact half extents sqrt(rho^2 Sigma_aa)),
+ * from p->t and p->cov; sets p->valid. */
+static void finish_projection(const ocam *c, const oset *st, double o, oproj *p)
+{
+    double cxx = p->cov[0], cxy = p->cov[1], cyy = p->cov[2];
+    double det = cxx * cyy - cxy * cxy;
+    if (!(det > 0.0) || !isfinite(det)) return;
+    p->con[0] = cyy / det;
+    p->con[1] = -cxy / det;
+    p->con[2] = cxx / det;
+    double tx = p->t[0], ty = p->t[1], tz = p->t[2];
+    p->mx = c->fx * tx / tz + c->cx;
+    p->my = c->fy * ty / tz + c->cy;
+    double rho2 = 2.0 * log(o / st->alpha_min);
+    p->hx = sqrt(rho2 * cxx);
+    p->hy = sqrt(rho2 * cyy);
+    double ulo = ceil(p->mx - p->hx), uhi = floor(p->mx + p->hx);
+    double vlo = ceil(p->my - p->hy), vhi = floor(p->my + p->hy);
+    if (!(ulo <= uhi) || !(vlo <= vhi)) return;
+    if (ulo < 0.0) ulo = 0.0;
+    if (vlo < 0.0) vlo = 0.0;
+    if (uhi > (double)(c->w - 1)) uhi = (double)(c->w - 1);
+    if (vhi > (double)(c->h - 1)) vhi = (double)(c->h - 1);
+    if (ulo > uhi || vlo > vhi) return;
+    p->u0 = (int)ulo; p->u1 = (int)uhi;
+    p->v0 = (int)vlo; p->v1 = (int)vhi;
+    p->valid = 1;
+}
+
+/* camera-frame mean t = R^T (mu - T); depth d = t_z written in a fixed order.
+ * Returns 0 if the Gaussian is at or before the near plane. */
+static int camera_mean(const ogauss *g, int64_t i, const ocam *c, const oset *st, oproj *p)
+{
+    int64_t n = g->n;
+    double dx = g->means[0 * n + i] - c->T[0];
+    double dy = g->means[1 * n + i] - c->T[1];
+    double dz = g->means[2 * n + i] - c->T[2];
+    const double *R = c->R;
+    p->t[0] = (dx * R[0] + dy * R[3]) + dz * R[6];
+    p->t[1] = (dx * R[1] + dy * R[4]) + dz * R[7];
+    p->t[2] = (dx * R[2] + dy * R[5]) + dz * R[8];
+    p->depth = p->t[2];
+    if (!(p->depth > st->z_near)) return 0;
+    p->dbits = f32_bits(p->depth);
+    return 1;
+}
+
+/* The paper's isotropic splat (Sec. III): radius r = exp(log-radius),
+ * projected radius r_2D = f r / d per image axis, so
+ * Sigma_2D = diag((fx r / d)^2, (fy r / d)^2) (+ eps2d). */
+static void project_isotropic(const ogauss *g, int64_t i, const ocam *c, const oset *st, oproj *p)
+{
+    double r = exp(g->log_scales[i]);
+    p->s[0] = p->s[1] = p->s[2] = r;
+    if (!camera_mean(g, i, c, st, p)) return;
+    double rx = c->fx * r / p->t[2], ry = c->fy * r / p->t[2];
+    p->cov[0] = rx * rx + st->eps2d;
+    p->cov[1] = 0.0;
+    p->cov[2] = ry * ry + st->eps2d;
+    finish_projection(c, st, g->opacity[i], p);
+}
+
 static void project_one(const ogauss *g, int64_t i, const ocam *c, const oset *st, oproj *p)
 {
     int64_t n = g->n;
     memset(p, 0, sizeof(*p));
     p->valid = 0;
-    if (!finite_geometry(g, i)) return;
+    if (!finite_geometry(g, i, st->iso)) return;
     double o = g->opacity[i];
     if (o < st->alpha_min) return;
+    if (st->iso) {
+        project_isotropic(g, i, c, st, p);
+        return;
+    }
 
     /* quaternion -> rotation (w, x, y, z), normalised first */
     double qw = g->quats[0 * n + i], qx = g->quats[1 * n + i];
@@ -173,17 +246,8 @@ static void project_one(const ogauss *g, int64_t i, const ocam *c, const oset *s
             p->Sw[a * 3 + b] = acc;
         }
 
-    /* camera-frame mean t = R^T (mu - T); depth d = t_z written in a fixed order */
-    double dx = g->means[0 * n + i] - c->T[0];
-    double dy = g->means[1 * n + i] - c->T[1];
-    double dz = g->means[2 * n + i] - c->T[2];
+    if (!camera_mean(g, i, c, st, p)) return;
     const double *R = c->R;
-    p->t[0] = (dx * R[0] + dy * R[3]) + dz * R[6];
-    p->t[1] = (dx * R[1] + dy * R[4]) + dz * R[7];
-    p->t[2] = (dx * R[2] + dy * R[5]) + dz * R[8];
-    p->depth = p->t[2];
-    if (!(p->depth > st->z_near)) return;
-    p->dbits = f32_bits(p->depth);
 
     /* Sc = R^T Sw R */
     double tmp[9];
@@ -221,30 +285,7 @@ static void project_one(const ogauss *g, int64_t i, const ocam *c, const oset *s
     cxx += st->eps2d;
     cyy += st->eps2d;
     p->cov[0] = cxx; p->cov[1] = cxy; p->cov[2] = cyy;
-    double det = cxx * cyy - cxy * cxy;
-    if (!(det > 0.0) || !isfinite(det)) return;
-    p->con[0] = cyy / det;
-    p->con[1] = -cxy / det;
-    p->con[2] = cxx / det;
-
-    p->mx = c->fx * tx / tz + c->cx;
-    p->my = c->fy * ty / tz + c->cy;
-
-    /* exact bounding box of {alpha >= alpha_min}: d^T Q d <= 2 ln(o / alpha_min) */
-    double rho2 = 2.0 * log(o / st->alpha_min);
-    p->hx = sqrt(rho2 * cxx);
-    p->hy = sqrt(rho2 * cyy);
-    double ulo = ceil(p->mx - p->hx), uhi = floor(p->mx + p->hx);
-    double vlo = ceil(p->my - p->hy), vhi = floor(p->my + p->hy);
-    if (!(ulo <= uhi) || !(vlo <= vhi)) return;
-    if (ulo < 0.0) ulo = 0.0;
-    if (vlo < 0.0) vlo = 0.0;
-    if (uhi > (double)(c->w - 1)) uhi = (double)(c->w - 1);
-    if (vhi > (double)(c->h - 1)) vhi = (double)(c->h - 1);
-    if (ulo > uhi || vlo > vhi) return;
-    p->u0 = (int)ulo; p->u1 = (int)uhi;
-    p->v0 = (int)vlo; p->v1 = (int)vhi;
-    p->valid = 1;
+    finish_projection(c, st, o, p);
 }
 
 /* Depth order: ascending binary32 depth bits, ties by Gaussian index. */
@@ -972,6 +1013,26 @@ static void project_adjoint(const oview *V, int64_t i, const double *G2,
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++) GS[a * 2 + b] = -(Q[a * 2 + 0] * tmp[0 * 2 + b] + Q[a * 2 + 1] * tmp[1 * 2 + b]);
 
+    double tx = p->t[0], ty = p->t[1], tz = p->t[2];
+    double fx = c->fx, fy = c->fy;
+    double gt[3] = {0.0, 0.0, 0.0};
+    if (V->s.iso) {
+        /* Sigma_aa = (f_a r / t_z)^2 + eps2d: d/dlog r = 2 (Sigma_aa - eps2d),
+         * d/dt_z = -2 (Sigma_aa - eps2d) / t_z; Sigma_xy = 0 is constant */
+        double gsum = GS[0] * (p->cov[0] - V->s.eps2d) + GS[3] * (p->cov[2] - V->s.eps2d);
+        gls[i] += 2.0 * gsum;
+        gt[2] += -2.0 * gsum / tz;
+        gt[0] += G2[0] * fx / tz;
+        gt[2] += G2[0] * (-fx * tx / (tz * tz));
+        gt[1] += G2[1] * fy / tz;
+        gt[2] += G2[1] * (-fy * ty / (tz * tz));
+        gt[2] += G2[9];
+        const double *R = c->R;
+        for (int a = 0; a < 3; a++)
+            gm[a * N + i] += R[a * 3 + 0] * gt[0] + R[a * 3 + 1] * gt[1] + R[a * 3 + 2] * gt[2];
+        return;
+    }
+
     const double *J = p->J, *Sc = p->Sc;
     /* G_Sc = J^T G_S J (3x3) */
     double GSc[9];
@@ -992,9 +1053,6 @@ static void project_adjoint(const oview *V, int64_t i, const double *G2,
             GJ[r * 3 + b] = 2.0 * acc;
         }
     /* camera-frame mean */
-    double tx = p->t[0], ty = p->t[1], tz = p->t[2];
-    double fx = c->fx, fy = c->fy;
-    double gt[3] = {0.0, 0.0, 0.0};
     gt[2] += GJ[0] * (-fx / (tz * tz));
     gt[0] += GJ[2] * (-fx / (tz * tz));
     gt[2] += GJ[2] * (2.0 * fx * tx / (tz * tz * tz));
