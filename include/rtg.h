@@ -68,12 +68,21 @@ typedef struct rtg_camera {
  *   z_near = 0.2: Gaussians with camera depth <= z_near are culled;
  *   eps2d = 0: added to the diagonal of the 2D covariance;
  *   max_instances: capacity of (tile, Gaussian) pairs for captured graphs
- *     (0 = sized by a first eager pass). */
+ *     (0 = sized by a first eager pass);
+ *   isotropic = 0: 1 selects the paper's 8-parameter Gaussian of Sec. III
+ *     (colour, mean, radius, opacity): the first n log_scales values are the
+ *     log-radii, quats is not read (may be NULL) and the splat projects with
+ *     r_2D = f r / d per image axis, Sigma_2D = diag((fx r/d)^2, (fy r/d)^2)
+ *     (+ eps2d); the backward then writes only the first n log-scale
+ *     gradients and no quaternion gradient;
+ *   reserved: 0. */
 typedef struct rtg_settings {
     int32_t tile_w, tile_h;
     int32_t batch;
     float T_min, alpha_min, alpha_max, z_near, eps2d;
     int64_t max_instances;
+    int32_t isotropic;
+    int32_t reserved;
 } rtg_settings;
 
 /* The Gaussian map (Sec. III: colour, position, size, opacity; the
@@ -82,7 +91,9 @@ typedef struct rtg_settings {
  *   means 3 x n, log_scales 3 x n, quats 4 x n (w, x, y, z; any norm),
  *   opacity n (activated, in (0, 1]), colors 3 x n, uncert n (per-Gaussian
  *   uncertainty u_i of Sec. IV-A; may be NULL when no uncertainty image or
- *   score is requested). */
+ *   score is requested).  With settings.isotropic = 1, log_scales holds n
+ *   log-radii (1 x n; a 3 x n array is read in its first row) and quats may
+ *   be NULL. */
 typedef struct rtg_gaussians {
     int64_t n;
     const float *means, *log_scales, *quats, *opacity, *colors, *uncert;

@@ -29,7 +29,8 @@ class Camera(_c.Structure):
 
 class Settings(_c.Structure):
     _fields_ = [("tile_w", i32), ("tile_h", i32), ("batch", i32), ("T_min", f32), ("alpha_min", f32),
-                ("alpha_max", f32), ("z_near", f32), ("eps2d", f32), ("max_instances", i64)]
+                ("alpha_max", f32), ("z_near", f32), ("eps2d", f32), ("max_instances", i64),
+                ("isotropic", i32), ("reserved", i32)]
 
 
 class Gaussians(_c.Structure):

@@ -230,8 +230,8 @@ rtg_status check_gauss(const rtg_gaussians* g, bool need_colors, bool need_unc) 
     if (g->n < 0) return set_err(RTG_ERR_INVALID, "n = %lld < 0", (long long)g->n);
     if (g->n >= (int64_t)1 << 31) return set_err(RTG_ERR_UNSUPPORTED, "n = %lld exceeds 2^31 - 1", (long long)g->n);
     if (g->n > 0) {
-        if (!g->means || !g->log_scales || !g->quats || !g->opacity)
-            return set_err(RTG_ERR_INVALID, "a required Gaussian array (means, log_scales, quats, opacity) is NULL");
+        if (!g->means || !g->log_scales || !g->opacity)
+            return set_err(RTG_ERR_INVALID, "a required Gaussian array (means, log_scales, opacity) is NULL");
         if (need_colors && !g->colors) return set_err(RTG_ERR_INVALID, "colors is NULL");
         if (need_unc && !g->uncert) return set_err(RTG_ERR_INVALID, "uncert is NULL");
     }
@@ -273,6 +273,7 @@ rtg_status resolve_settings(rtg_ctx* ctx, const rtg_settings* in, rtg_settings* 
     if (!(out->T_min > 0.0f) || !(out->T_min < 1.0f)) return set_err(RTG_ERR_INVALID, "need 0 < T_min < 1");
     if (!(out->z_near > 0.0f)) return set_err(RTG_ERR_INVALID, "need z_near > 0");
     if (out->eps2d < 0.0f) return set_err(RTG_ERR_INVALID, "need eps2d >= 0");
+    if (out->isotropic != 0 && out->isotropic != 1) return set_err(RTG_ERR_INVALID, "isotropic must be 0 or 1");
     const int b = out->batch;
     if (b != 0 && ((b != 32 && b != 64 && b != 128 && b != 256) || b > out->tile_w * out->tile_h))
         return set_err(RTG_ERR_INVALID, "batch %d is not 0 or one of 32, 64, 128, 256 within the tile's %d pixels", b,
@@ -281,7 +282,8 @@ rtg_status resolve_settings(rtg_ctx* ctx, const rtg_settings* in, rtg_settings* 
 }
 
 SetDev to_dev(const rtg_settings& s) {
-    return SetDev{s.T_min, s.alpha_min, s.alpha_max, s.z_near, s.eps2d, (float)std::log2((double)s.alpha_min)};
+    return SetDev{s.T_min, s.alpha_min, s.alpha_max, s.z_near, s.eps2d, (float)std::log2((double)s.alpha_min),
+                  s.isotropic};
 }
 
 GaussDev to_dev(const rtg_gaussians& g) {
@@ -508,6 +510,8 @@ rtg_status new_frame(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* cam
     f->stream = s;
     f->g = *g;
     RTG_TRY(resolve_settings(ctx, settings, &f->st));
+    if (!f->st.isotropic && g->n > 0 && !g->quats)
+        return set_err(RTG_ERR_INVALID, "quats is NULL (required unless isotropic)");
     make_layout(cams, n_views, f->st.tile_w, f->st.tile_h, f->L);
     f->n_views = n_views;
     RTG_TRY(frame_setup(f.get(), n_views, s));
@@ -549,6 +553,8 @@ rtg_status rtg_default_settings(rtg_settings* s) {
     s->z_near = 0.2f;
     s->eps2d = 0.0f;
     s->max_instances = 0;
+    s->isotropic = 0;
+    s->reserved = 0;
     return RTG_OK;
 }
 

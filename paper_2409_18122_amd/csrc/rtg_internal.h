@@ -30,6 +30,7 @@ struct Header {
 struct SetDev {
     float T_min, alpha_min, alpha_max, z_near, eps2d;
     float log2_amin;  // log2(alpha_min)
+    int32_t isotropic;  // 1: one log-radius per Gaussian, no quaternion, r_2D = f r / d
 };
 
 struct GaussDev {

@@ -42,7 +42,9 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
 // ------------------------------------------------------------- projection
 // Sec. III (Gaussian Splatting paragraph): t = R^T (mu - T), d = t_z,
 // mu_2D = (fx t_x / d + cx, fy t_y / d + cy); the 2D covariance is the EWA
-// form J R^T Sigma R J^T of the cited 3DGS work, with Sigma = Rq S^2 Rq^T.
+// form J R^T Sigma R J^T of the cited 3DGS work, with Sigma = Rq S^2 Rq^T,
+// or, for the paper's isotropic Gaussians, diag((fx r / d)^2, (fy r / d)^2)
+// (r_2D = f r / d; one log-radius per Gaussian, no quaternion).
 
 struct GPre {
     double mu[3];
@@ -53,7 +55,30 @@ struct GPre {
     float reach;  // rho * max scale: bound on the support radius in 3D
 };
 
+// The isotropic form: s = (r, r, r) and Rq = I; only the first n log-scale values are read.
+__device__ inline bool pre_gauss_iso(const GaussDev& g, int64_t i, const SetDev& st, GPre& P) {
+    const int64_t n = g.n;
+    const float m0 = g.means[i], m1 = g.means[n + i], m2 = g.means[2 * n + i];
+    const float lr = g.log_scales[i];
+    const float op = g.opacity[i];
+    if (!(isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(lr) && isfinite(op))) return false;
+    if (op < st.alpha_min) return false;
+#pragma unroll
+    for (int k = 0; k < 9; k++) P.Rq[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    const double r = exp((double)lr);
+    P.s[0] = r;
+    P.s[1] = r;
+    P.s[2] = r;
+    P.mu[0] = m0; P.mu[1] = m1; P.mu[2] = m2;
+    P.mu_f[0] = m0; P.mu_f[1] = m1; P.mu_f[2] = m2;
+    P.o = op;
+    P.rho2 = 2.0 * log((double)op / (double)st.alpha_min);
+    P.reach = (float)(sqrt(P.rho2) * r);
+    return true;
+}
+
 __device__ inline bool pre_gauss(const GaussDev& g, int64_t i, const SetDev& st, GPre& P) {
+    if (st.isotropic) return pre_gauss_iso(g, i, st, P);
     const int64_t n = g.n;
     float m0 = g.means[i], m1 = g.means[n + i], m2 = g.means[2 * n + i];
     float l0 = g.log_scales[i], l1 = g.log_scales[n + i], l2 = g.log_scales[2 * n + i];
@@ -139,17 +164,26 @@ __device__ inline bool project_exact(const GPre& P, const ViewDev& V, const SetD
     double tz = (dx * R[2] + dy * R[5]) + dz * R[8];
     if (!(tz > (double)st.z_near)) return false;
     q.t[0] = tx; q.t[1] = ty; q.t[2] = tz;
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-        for (int b = 0; b < 3; b++)
-            q.A[a * 3 + b] = fma(R[0 * 3 + a], P.Rq[0 * 3 + b],
-                                 fma(R[1 * 3 + a], P.Rq[1 * 3 + b], R[2 * 3 + a] * P.Rq[2 * 3 + b]));
     double iz = 1.0 / tz;
     q.j0 = V.fx * iz;
-    q.j2 = -V.fx * tx * iz * iz;
     q.j4 = V.fy * iz;
-    q.j5 = -V.fy * ty * iz * iz;
+    if (st.isotropic) {
+        // Sigma_2D = diag(j0^2, j4^2) r^2: the EWA form below with A = I and
+        // no off-axis Jacobian terms (which the backward then treats as constant)
+#pragma unroll
+        for (int k = 0; k < 9; k++) q.A[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        q.j2 = 0.0;
+        q.j5 = 0.0;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+                q.A[a * 3 + b] = fma(R[0 * 3 + a], P.Rq[0 * 3 + b],
+                                     fma(R[1 * 3 + a], P.Rq[1 * 3 + b], R[2 * 3 + a] * P.Rq[2 * 3 + b]));
+        q.j2 = -V.fx * tx * iz * iz;
+        q.j5 = -V.fy * ty * iz * iz;
+    }
     // B = J A scaled by s per column; cov = B S^2 B^T
     double cxx = 0.0, cxy = 0.0, cyy = 0.0;
 #pragma unroll
@@ -1623,6 +1657,22 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
         gtz += gdepth;
 #pragma unroll
         for (int a = 0; a < 3; a++) gm[a] += R[a * 3 + 0] * gtx + R[a * 3 + 1] * gty + R[a * 3 + 2] * gtz;
+    }
+    if (st.isotropic) {
+        // one radius for the three axes; no rotation
+        if (d_means) {
+            d_means[i] += (float)gm[0];
+            d_means[n + i] += (float)gm[1];
+            d_means[2 * n + i] += (float)gm[2];
+        }
+        if (d_ls) d_ls[i] += (float)((gs[0] + gs[1] + gs[2]) * P.s[0]);
+        if (d_op) d_op[i] += (float)go;
+        if (d_col) {
+            d_col[i] += (float)gc[0];
+            d_col[n + i] += (float)gc[1];
+            d_col[2 * n + i] += (float)gc[2];
+        }
+        return;
     }
     // rotation matrix -> normalised quaternion -> raw quaternion
     double w = g.quats[i], x = g.quats[n + i], y = g.quats[2 * n + i], z = g.quats[3 * n + i];

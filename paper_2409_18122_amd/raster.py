@@ -17,7 +17,7 @@ from ._lib import (Camera, Gaussians, Grads, RtgError, Settings, check, lib, RTG
 DEFAULTS = {
     "tile_w": 16, "tile_h": 16, "batch": 0,
     "T_min": 1e-4, "alpha_min": 1.0 / 255.0, "alpha_max": 0.99,
-    "z_near": 0.2, "eps2d": 0.0, "max_instances": 0,
+    "z_near": 0.2, "eps2d": 0.0, "max_instances": 0, "isotropic": 0,
 }
 
 GAUSS_KEYS = ("means", "log_scales", "quats", "opacity", "colors", "uncert")
@@ -43,7 +43,7 @@ def make_settings(settings=None) -> Settings:
         s.update({k: v for k, v in settings.items() if k in DEFAULTS})
     return Settings(int(s["tile_w"]), int(s["tile_h"]), int(s["batch"]), float(s["T_min"]),
                     float(s["alpha_min"]), float(s["alpha_max"]), float(s["z_near"]),
-                    float(s["eps2d"]), int(s["max_instances"]))
+                    float(s["eps2d"]), int(s["max_instances"]), int(s["isotropic"]), 0)
 
 
 def make_cameras(cams):
@@ -189,7 +189,7 @@ class Frame:
     def backward(self, d_rgb, d_depth, d_alpha=None, d_unc=None, grads=None):
         """Adds dL/dparams into `grads` (dict of tensors shaped like the map)."""
         if grads is None:
-            grads = {k: torch.zeros_like(self._g[k]) for k in GRAD_KEYS}
+            grads = {k: torch.zeros_like(self._g[k]) for k in GRAD_KEYS if self._g.get(k) is not None}
         gr = Grads(*[_ptr(grads.get(k)) for k in GRAD_KEYS])
         check(lib().rtg_render_backward(self.ctx.handle, self.handle, _ptr(d_rgb), _ptr(d_depth),
                                         _ptr(d_alpha), _ptr(d_unc), ctypes.byref(gr), _stream()))
@@ -233,7 +233,8 @@ class RasterizeFn(torch.autograd.Function):
 
     @staticmethod
     def forward(fctx, means, log_scales, quats, opacity, colors, uncert, cams, settings, rctx):
-        g = {"means": means.detach(), "log_scales": log_scales.detach(), "quats": quats.detach(),
+        g = {"means": means.detach(), "log_scales": log_scales.detach(),
+             "quats": None if quats is None else quats.detach(),
              "opacity": opacity.detach(), "colors": colors.detach(),
              "uncert": None if uncert is None else uncert.detach()}
         frame = Frame(rctx, g, cams, settings)
@@ -251,12 +252,12 @@ class RasterizeFn(torch.autograd.Function):
                                d_unc.contiguous() if fctx.has_unc else None)
         frame.close()
         fctx.frame = None
-        return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity"],
+        return (grads["means"], grads["log_scales"], grads.get("quats"), grads["opacity"],
                 grads["colors"], None, None, None, None)
 
 
 def rasterize(rctx, g, cams, settings=None):
-    return RasterizeFn.apply(g["means"], g["log_scales"], g["quats"], g["opacity"], g["colors"],
+    return RasterizeFn.apply(g["means"], g["log_scales"], g.get("quats"), g["opacity"], g["colors"],
                              g.get("uncert"), cams, settings, rctx)
 
 
@@ -337,7 +338,8 @@ class MapGraph:
         self.rgb = torch.empty(3 * P, device=dev, dtype=torch.float32)
         self.depth = torch.empty(P, device=dev, dtype=torch.float32)
         self.loss = torch.zeros(1, device=dev, dtype=torch.float64)
-        self.grads = grads if grads is not None else {k: torch.zeros_like(g[k]) for k in GRAD_KEYS}
+        self.grads = grads if grads is not None else {k: torch.zeros_like(g[k]) for k in GRAD_KEYS
+                                                      if g.get(k) is not None}
         self._targets = (target_rgb, target_depth)
         gr = Grads(*[_ptr(self.grads.get(k)) for k in GRAD_KEYS])
         h = ctypes.c_void_p()

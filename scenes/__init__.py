@@ -275,6 +275,15 @@ def tiny_scene(n, seed, width=32, height=24, depth=(1.5, 4.0), ls=(-2.5, 0.5),
     return g, [cam]
 
 
+def isotropic_scene(scene):
+    """The same map as the paper's isotropic Gaussians (Sec. III): one
+    log-radius per Gaussian (the first log-scale row, 1 x N) and no
+    quaternion."""
+    out = {k: v for k, v in scene.items() if k != "quats"}
+    out["log_scales"] = np.ascontiguousarray(scene["log_scales"][:1])
+    return out
+
+
 def subset(scene, idx):
     """Gaussians at positions idx (keeps planar layout)."""
     out = {}

@@ -42,6 +42,7 @@ def test_default_settings(L):
     assert (s.tile_w, s.tile_h, s.batch) == (16, 16, 0)
     assert s.T_min == pytest.approx(1e-4) and s.alpha_max == pytest.approx(0.99)
     assert s.alpha_min == pytest.approx(1 / 255) and s.z_near == pytest.approx(0.2)
+    assert s.isotropic == 0 and s.reserved == 0 and ctypes.sizeof(s) == 48
     assert L.rtg_default_settings(None) == -1
 
 
