@@ -33,17 +33,20 @@ METRIC = "render+backward Mpix/s and candidate views scored/s, batched vs plain,
 OPS_PER_PAIR = {"render": 20.0, "render_backward": 55.0}
 # MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s
 # (unpacked FP32; the packed 157.3 TFLOP/s peak counts 2 lanes x FMA = 4 flops).
-ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# FP32 vector peak in lane-operations per second: 256 CUs x 4 SIMDs x 32 lanes
+# per cycle (a wave64 instruction every 2 cycles) x 2.4 GHz = 78.6e12, i.e. the
+# 157.3 TFLOP/s FP32 vector figure counting a fused multiply-add as one operation
+ALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (20496.0 * 2.0 * 1024 + 26269.2 * 1024,
-                        "2114ca5356faeef6597ae5b191da0ba1ab834e598c0d3817c67fb2208038c233"),
-    "render": (20790.8 * 2.0 * 1024 + 8400.0 * 1024,
-               "2114ca5356faeef6597ae5b191da0ba1ab834e598c0d3817c67fb2208038c233"),
+    "render_backward": (20498.6 * 2.0 * 1024 + 26269.2 * 1024,
+                        "ee6017182ffd138fb352d08c18603ea447c6cd3bea1a91f7ce936d6cbbeff990"),
+    "render": (20786.9 * 2.0 * 1024 + 8400.0 * 1024,
+               "ee6017182ffd138fb352d08c18603ea447c6cd3bea1a91f7ce936d6cbbeff990"),
 }
 
 
