@@ -455,8 +455,8 @@ rtg_status enqueue_project(rtg_frame* f, bool eager, hipStream_t s) {
         RTG_TRY(alloc_records(f, f->R));
     }
     project_emit(gd, views, hdr, f->views_cap, sd, f->st.tile_w, f->st.tile_h, f->mask.as<uint32_t>(),
-                 f->rec_off.as<uint32_t>(), f->rec_cap, f->records(), f->skey.as<uint32_t>(), f->order.as<uint32_t>(),
-                 f->ctr(C_FLAGS), s);
+                 f->rec_off.as<uint32_t>(), f->ctr(C_REC), f->rec_cap, f->records(), f->skey.as<uint32_t>(),
+                 f->order.as<uint32_t>(), f->ctr(C_FLAGS), s);
     return check_launch("projection emit");
 }
 

@@ -91,8 +91,8 @@ void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, i
 // Writes records at rec_off[i] .. for the visible views of Gaussian i.
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap,
                   SetDev st, int tw, int th, const uint32_t* mask, const uint32_t* rec_off,
-                  uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order, uint32_t* flags,
-                  hipStream_t s);
+                  const uint32_t* R_dev, uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order,
+                  uint32_t* flags, hipStream_t s);
 
 // Exclusive prefix sum of in[0..n) (n = min(*n_dev, cap)) into out; *total =
 // the full sum.  If gather != NULL the input is in[gather[i]].

@@ -367,78 +367,6 @@ __global__ __launch_bounds__(256) void k_project_count(GaussDev g, const ViewDev
     cnt[i] = c;
 }
 
-__global__ __launch_bounds__(256) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
-                                                      int words, SetDev st, int tws, int ths,
-                                                      const uint32_t* __restrict__ mask,
-                                                      const uint32_t* __restrict__ rec_off,
-                                                      uint32_t rec_cap, Records rec,
-                                                      uint32_t* __restrict__ sortkey,
-                                                      uint32_t* __restrict__ order,
-                                                      uint32_t* __restrict__ flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
-    uint32_t pos = rec_off[i];
-    GPre P;
-    bool first = true;
-    const int64_t n = g.n;
-    for (int w = 0; w < words; w++) {
-        uint32_t vis = mask[(int64_t)w * n + i];
-        while (vis) {
-            int b = __ffs(vis) - 1;
-            vis &= vis - 1;
-            if (first) {
-                pre_gauss(g, i, st, P);
-                first = false;
-            }
-            int v = 32 * w + b;
-            const ViewDev& V = views[v];
-            GProj q;
-            project_exact(P, V, st, q);
-            if (pos >= rec_cap) {
-                atomicOr(flags, FLAG_REC_OVERFLOW);
-                return;
-            }
-            float mxh = (float)q.mx, myh = (float)q.my;
-            const float4 g0 = make_float4(mxh, myh, (float)(q.mx - (double)mxh), (float)(q.my - (double)myh));
-            rec.geo0[pos] = g0;
-            double det = q.cxx * q.cyy - q.cxy * q.cxy;
-            // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
-            double c00 = sqrt(q.cxx);
-            double c10 = q.cxy / c00;
-            double c11 = sqrt(det / q.cxx);
-            double sl = sqrt(0.5 * LOG2E);
-            const float4 g1 = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
-                                          (float)P.o);
-            rec.geo1[pos] = g1;
-            rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
-            float depth = (float)q.t[2];
-            if (g.colors)
-                rec.attr[pos] = make_float4(g.colors[i], g.colors[n + i], g.colors[2 * n + i], depth);
-            else
-                rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
-            rec.unc[pos] = g.uncert ? g.uncert[i] : 0.0f;
-            rec.gid[pos] = (uint32_t)i;
-            rec.view[pos] = (uint32_t)v;
-            uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
-            uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
-            rec.rect[pos] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-            const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
-                                        (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
-            rec.pbox[pos] = pb;
-            rec.dkey[pos] = __float_as_uint(depth);
-            sortkey[pos] = __float_as_uint(depth);
-            // pairs: the tiles the support meets (a subset of the box's
-            // tiles); at least one, so that every record owns a pair
-            uint32_t nt = 0;
-            const SupportRows S = support_setup(g0, g1, pb, st.log2_amin);
-            for (uint32_t ty = ty0; ty <= ty1; ty++) nt += support_row(S, ty, tws, ths).y;
-            rec.ntiles[pos] = max(nt, 1u);
-            order[pos] = pos;
-            pos++;
-        }
-    }
-}
-
 // -------------------------------------------------------------- prefix sum
 
 constexpr int SC_THREADS = 256;
@@ -866,6 +794,107 @@ __device__ __forceinline__ void cursor_next(PairCursor& c, int tws, int ths) {
     c.rem = 0;
     c.ty++;
     cursor_row(c, tws, ths);  // the caller knows the record has another pair
+}
+
+// Record emission, one thread per record so that the record arrays are
+// written in contiguous runs: the records of Gaussian i are rec_off[i] ...
+// rec_off[i] + cnt[i] - 1, one per visible view in view order.  A block finds
+// the Gaussians spanning its records with two wave searches and stages their
+// offsets in LDS (a span wider than PE_LDS, i.e. a long run of culled
+// Gaussians, is searched in global memory instead).
+constexpr int PE_THREADS = 256;
+constexpr uint32_t PE_LDS = 2048;
+
+__global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
+                                                             int words, SetDev st, int tws, int ths,
+                                                             const uint32_t* __restrict__ mask,
+                                                             const uint32_t* __restrict__ rec_off,
+                                                             const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
+                                                             Records rec, uint32_t* __restrict__ sortkey,
+                                                             uint32_t* __restrict__ order,
+                                                             uint32_t* __restrict__ flags) {
+    __shared__ uint32_t s_off[PE_LDS];
+    __shared__ uint32_t s_lo, s_hi;
+    const uint32_t Rall = *R_dev;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && Rall > rec_cap) atomicOr(flags, FLAG_REC_OVERFLOW);
+    const uint32_t R = min(Rall, rec_cap);
+    const uint32_t n = (uint32_t)g.n;
+    for (uint32_t k0 = blockIdx.x * PE_THREADS; k0 < R; k0 += gridDim.x * PE_THREADS) {
+        const uint32_t k1 = min(k0 + PE_THREADS, R);  // exclusive
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const uint32_t lo = wave_last_le(rec_off, n, k0);
+            if (threadIdx.x == 0) s_lo = lo;
+        } else if (threadIdx.x < 128) {
+            const uint32_t hi = wave_last_le(rec_off, n, k1 - 1);
+            if (threadIdx.x == 64) s_hi = hi;
+        }
+        __syncthreads();
+        const uint32_t lo = s_lo, ng = s_hi - s_lo + 1;
+        const bool staged = ng <= PE_LDS;
+        if (staged)
+            for (uint32_t j = threadIdx.x; j < ng; j += PE_THREADS) s_off[j] = rec_off[lo + j];
+        __syncthreads();
+        const uint32_t pos = k0 + threadIdx.x;
+        if (pos >= k1) continue;
+        // owner Gaussian: the last one whose first record is at or before pos
+        const uint32_t i = lo + (staged ? last_le(s_off, ng, pos) : last_le(rec_off + lo, ng, pos));
+        // its (pos - rec_off[i])-th visible view
+        uint32_t kk = pos - rec_off[i];
+        int v = 0;
+        for (int w = 0; w < words; w++) {
+            uint32_t vis = mask[(int64_t)w * n + i];
+            const uint32_t c = (uint32_t)__popc(vis);
+            if (kk < c) {
+                for (; kk; kk--) vis &= vis - 1;
+                v = 32 * w + __ffs(vis) - 1;
+                break;
+            }
+            kk -= c;
+        }
+        GPre P;
+        pre_gauss(g, i, st, P);
+        const ViewDev& V = views[v];
+        GProj q;
+        project_exact(P, V, st, q);
+        float mxh = (float)q.mx, myh = (float)q.my;
+        const float4 g0 = make_float4(mxh, myh, (float)(q.mx - (double)mxh), (float)(q.my - (double)myh));
+        rec.geo0[pos] = g0;
+        double det = q.cxx * q.cyy - q.cxy * q.cxy;
+        // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
+        double c00 = sqrt(q.cxx);
+        double c10 = q.cxy / c00;
+        double c11 = sqrt(det / q.cxx);
+        double sl = sqrt(0.5 * LOG2E);
+        const float4 g1 = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
+                                      (float)P.o);
+        rec.geo1[pos] = g1;
+        rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
+        float depth = (float)q.t[2];
+        const int64_t gi = i;
+        if (g.colors)
+            rec.attr[pos] = make_float4(g.colors[gi], g.colors[g.n + gi], g.colors[2 * g.n + gi], depth);
+        else
+            rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
+        rec.unc[pos] = g.uncert ? g.uncert[gi] : 0.0f;
+        rec.gid[pos] = i;
+        rec.view[pos] = (uint32_t)v;
+        uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
+        uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
+        rec.rect[pos] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
+                                    (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
+        rec.pbox[pos] = pb;
+        rec.dkey[pos] = __float_as_uint(depth);
+        sortkey[pos] = __float_as_uint(depth);
+        // pairs: the tiles the support meets (a subset of the box's
+        // tiles); at least one, so that every record owns a pair
+        uint32_t nt = 0;
+        const SupportRows S = support_setup(g0, g1, pb, st.log2_amin);
+        for (uint32_t ty = ty0; ty <= ty1; ty++) nt += support_row(S, ty, tws, ths).y;
+        rec.ntiles[pos] = max(nt, 1u);
+        order[pos] = pos;
+    }
 }
 
 __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* __restrict__ order,
@@ -2270,13 +2299,13 @@ static int ilog2(int x) {
 }
 
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap, SetDev st,
-                  int tw, int th, const uint32_t* mask, const uint32_t* rec_off, uint32_t rec_cap, Records rec,
-                  uint32_t* sortkey, uint32_t* order, uint32_t* flags, hipStream_t s) {
+                  int tw, int th, const uint32_t* mask, const uint32_t* rec_off, const uint32_t* R_dev,
+                  uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order, uint32_t* flags, hipStream_t s) {
     (void)hdr;
-    if (g.n == 0) return;
+    if (g.n == 0 || rec_cap == 0) return;
     int words = (n_views_cap + 31) / 32;
-    k_project_emit<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, words, st, ilog2(tw), ilog2(th), mask, rec_off,
-                                                      rec_cap, rec, sortkey, order, flags);
+    k_project_emit<<<grid_for(rec_cap, PE_THREADS, 32768), PE_THREADS, 0, s>>>(
+        g, views, words, st, ilog2(tw), ilog2(th), mask, rec_off, R_dev, rec_cap, rec, sortkey, order, flags);
 }
 
 int scan_blocks(uint64_t cap) {
