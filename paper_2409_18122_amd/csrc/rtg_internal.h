@@ -38,6 +38,15 @@ struct GaussDev {
     const float *means, *log_scales, *quats, *opacity, *colors, *uncert;
 };
 
+// The fields pair emission reads, packed in one 64-byte line per record
+// (emission visits records in depth order, i.e. at random).
+struct alignas(16) EmitRec {
+    float4 g0, g1;
+    uint2 pbox;
+    uint2 rect;  // tile rectangle: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
+    uint32_t ntiles, view, pad0, pad1;
+};
+
 // Projected (view, Gaussian) records, structure of arrays.
 //   geo0 = (mean_x hi, mean_y hi, mean_x lo, mean_y lo): the binary64 mean as
 //          a sum of two binary32 values, so per-pixel offsets are exact;
@@ -47,8 +56,10 @@ struct GaussDev {
 //          between terms for elongated splats);
 //   q64  = binary64 Sigma_2D^-1 (xx, xy, yy, 0), read only to re-take the
 //          alpha_min decision in binary64 when binary32 alpha is near it;
-//   attr = (r, g, b, camera depth); unc = per-Gaussian uncertainty.
+//   attr = (r, g, b, camera depth); unc = per-Gaussian uncertainty;
+//   emit = the copy of the fields pair emission reads.
 struct Records {
+    EmitRec* emit;
     float4* geo0;
     float4* geo1;
     double4* q64;
@@ -56,7 +67,6 @@ struct Records {
     float* unc;
     uint32_t* gid;
     uint32_t* view;
-    uint2* rect;       // tile rectangle: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
     uint2* pbox;       // pixel box of alpha >= alpha_min: x = u0 | u1 << 16, y = v0 | v1 << 16
     uint32_t* dkey;    // binary32 bits of the camera depth (sort key)
     uint32_t* ntiles;  // tiles covered

@@ -752,18 +752,19 @@ __device__ __forceinline__ bool cursor_row(PairCursor& c, int tws, int ths) {
 __device__ __forceinline__ void cursor_open(PairCursor& c, const Records& rec, const ViewDev* views, uint32_t r,
                                             uint32_t li, int tws, int ths, float log2_amin, uint32_t* flags) {
     c.r = r;
-    const uint2 rc = rec.rect[r];
+    const EmitRec e = rec.emit[r];
+    const uint2 rc = e.rect;
     c.tx0 = rc.x & 0xffffu;
     c.nx = (rc.x >> 16) - c.tx0 + 1;
     c.ty0 = rc.y & 0xffffu;
     c.ty1 = rc.y >> 16;
-    const ViewDev& V = views[rec.view[r]];
+    const ViewDev& V = views[e.view];
     c.tile_off = V.tile_off;
     c.tiles_x = (uint32_t)V.tiles_x;
-    c.full = rec.ntiles[r] == c.nx * (c.ty1 - c.ty0 + 1);
+    c.full = e.ntiles == c.nx * (c.ty1 - c.ty0 + 1);
     c.li = li;
     if (c.full) return;
-    c.S = support_setup(rec.geo0[r], rec.geo1[r], rec.pbox[r], log2_amin);
+    c.S = support_setup(e.g0, e.g1, e.pbox, log2_amin);
     c.ty = c.ty0;
     uint32_t rem = li;
     while (cursor_row(c, tws, ths)) {
@@ -881,7 +882,6 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         rec.view[pos] = (uint32_t)v;
         uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
         uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
-        rec.rect[pos] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
         const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
                                     (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
         rec.pbox[pos] = pb;
@@ -893,6 +893,15 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         const SupportRows S = support_setup(g0, g1, pb, st.log2_amin);
         for (uint32_t ty = ty0; ty <= ty1; ty++) nt += support_row(S, ty, tws, ths).y;
         rec.ntiles[pos] = max(nt, 1u);
+        EmitRec e;
+        e.g0 = g0;
+        e.g1 = g1;
+        e.pbox = pb;
+        e.rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        e.ntiles = max(nt, 1u);
+        e.view = (uint32_t)v;
+        e.pad0 = e.pad1 = 0;
+        rec.emit[pos] = e;
         order[pos] = pos;
     }
 }
@@ -953,8 +962,11 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
             tr[q] = c.r;
         }
         if (n == EM_RUN) {
-            *reinterpret_cast<uint4*>(tile_key + kb) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
-            *reinterpret_cast<uint4*>(inst_rec + kb) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
+#pragma unroll
+            for (int q = 0; q < EM_RUN; q += 4) {
+                *reinterpret_cast<uint4*>(tile_key + kb + q) = make_uint4(tk[q], tk[q + 1], tk[q + 2], tk[q + 3]);
+                *reinterpret_cast<uint4*>(inst_rec + kb + q) = make_uint4(tr[q], tr[q + 1], tr[q + 2], tr[q + 3]);
+            }
         } else {
             for (int q = 0; q < n; q++) {
                 tile_key[kb + q] = tk[q];
