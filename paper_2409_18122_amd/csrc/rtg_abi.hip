@@ -345,14 +345,13 @@ struct rtg_frame {
     int order_in_alt = 0, inst_in_alt = 0;
 
     Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist;
-    Buf emit, geo0, geo1, q64, attr, unc, gid, view, pbox, dkey, ntiles, skey, skey2, order, order2;
+    Buf emit, q64, attr, gid, view, dkey, ntiles, skey, skey2, order, order2;
     Buf inst_off, tkey, tkey2, irec, irec2, ranges;
     Buf T_final, n_last, g2d, loss_part, score_part, ssim_maps;
 
     Records records() const {
-        return Records{emit.as<EmitRec>(), geo0.as<float4>(), geo1.as<float4>(), q64.as<double4>(), attr.as<float4>(), unc.as<float>(),
-                       gid.as<uint32_t>(),  view.as<uint32_t>(), pbox.as<uint2>(), dkey.as<uint32_t>(),
-                       ntiles.as<uint32_t>()};
+        return Records{emit.as<EmitRec>(), q64.as<double4>(), attr.as<float4>(), gid.as<uint32_t>(),
+                       view.as<uint32_t>(), dkey.as<uint32_t>(), ntiles.as<uint32_t>()};
     }
     uint32_t* sorted_order() const { return order_in_alt ? order2.as<uint32_t>() : order.as<uint32_t>(); }
     uint32_t* sorted_tkey() const { return inst_in_alt ? tkey2.as<uint32_t>() : tkey.as<uint32_t>(); }
@@ -399,14 +398,10 @@ rtg_status alloc_records(rtg_frame* f, uint32_t rc) {
     rtg_ctx* ctx = f->ctx;
     size_t r = std::max<uint32_t>(rc, 1);
     RTG_TRY(f->emit.ensure(ctx, sizeof(EmitRec) * r));
-    RTG_TRY(f->geo0.ensure(ctx, 16 * r));
-    RTG_TRY(f->geo1.ensure(ctx, 16 * r));
     RTG_TRY(f->q64.ensure(ctx, 32 * r));
     RTG_TRY(f->attr.ensure(ctx, 16 * r));
-    RTG_TRY(f->unc.ensure(ctx, 4 * r));
     RTG_TRY(f->gid.ensure(ctx, 4 * r));
     RTG_TRY(f->view.ensure(ctx, 4 * r));
-    RTG_TRY(f->pbox.ensure(ctx, 8 * r));
     RTG_TRY(f->dkey.ensure(ctx, 4 * r));
     RTG_TRY(f->ntiles.ensure(ctx, 4 * r));
     RTG_TRY(f->skey.ensure(ctx, 4 * r));

@@ -38,38 +38,39 @@ struct GaussDev {
     const float *means, *log_scales, *quats, *opacity, *colors, *uncert;
 };
 
-// The fields pair emission reads, packed in one 64-byte line per record
-// (emission visits records in depth order, i.e. at random).
+// The fields pair emission and the compositing kernels' staging read, packed
+// in one 64-byte line per record (both visit records at random: emission in
+// depth order, compositing through the tile lists).
 struct alignas(16) EmitRec {
     float4 g0, g1;
     uint2 pbox;
     uint2 rect;  // tile rectangle: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
-    uint32_t ntiles, view, pad0, pad1;
+    uint32_t ntiles, view;
+    uint32_t unc;  // binary32 bits of the uncertainty
+    uint32_t pad;
 };
 
 // Projected (view, Gaussian) records, structure of arrays.
-//   geo0 = (mean_x hi, mean_y hi, mean_x lo, mean_y lo): the binary64 mean as
-//          a sum of two binary32 values, so per-pixel offsets are exact;
-//   geo1 = (m00, m10, m11, opacity): the lower-triangular whitening M with
-//          M^T M = log2(e)/2 * Sigma_2D^-1, so that with w = M d the splat is
-//          G = exp2(-|w|^2) = exp(-d^T Sigma_2D^-1 d / 2) (no cancellation
+//   emit = EmitRec: geo0, geo1, pixel box, tile rectangle, pair count, view,
+//          uncertainty, where
+//          geo0 = (mean_x hi, mean_y hi, mean_x lo, mean_y lo): the binary64
+//          mean as a sum of two binary32 values, so per-pixel offsets are exact;
+//          geo1 = (m00, m10, m11, opacity): the lower-triangular whitening M
+//          with M^T M = log2(e)/2 * Sigma_2D^-1, so that with w = M d the splat
+//          is G = exp2(-|w|^2) = exp(-d^T Sigma_2D^-1 d / 2) (no cancellation
 //          between terms for elongated splats);
+//          pixel box of alpha >= alpha_min: x = u0 | u1 << 16, y = v0 | v1 << 16;
 //   q64  = binary64 Sigma_2D^-1 (xx, xy, yy, 0), read only to re-take the
 //          alpha_min decision in binary64 when binary32 alpha is near it;
-//   attr = (r, g, b, camera depth); unc = per-Gaussian uncertainty;
-//   emit = the copy of the fields pair emission reads.
+//   attr = (r, g, b, camera depth).
 struct Records {
     EmitRec* emit;
-    float4* geo0;
-    float4* geo1;
     double4* q64;
     float4* attr;
-    float* unc;
     uint32_t* gid;
     uint32_t* view;
-    uint2* pbox;       // pixel box of alpha >= alpha_min: x = u0 | u1 << 16, y = v0 | v1 << 16
     uint32_t* dkey;    // binary32 bits of the camera depth (sort key)
-    uint32_t* ntiles;  // tiles covered
+    uint32_t* ntiles;  // pairs (support tiles) of the record
 };
 
 // Screen-space gradient per record, binary64, 16 entries (one 128-byte line):

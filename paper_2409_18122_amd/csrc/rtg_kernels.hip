@@ -860,7 +860,6 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         project_exact(P, V, st, q);
         float mxh = (float)q.mx, myh = (float)q.my;
         const float4 g0 = make_float4(mxh, myh, (float)(q.mx - (double)mxh), (float)(q.my - (double)myh));
-        rec.geo0[pos] = g0;
         double det = q.cxx * q.cyy - q.cxy * q.cxy;
         // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
         double c00 = sqrt(q.cxx);
@@ -869,7 +868,6 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         double sl = sqrt(0.5 * LOG2E);
         const float4 g1 = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
                                       (float)P.o);
-        rec.geo1[pos] = g1;
         rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
         float depth = (float)q.t[2];
         const int64_t gi = i;
@@ -877,14 +875,12 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
             rec.attr[pos] = make_float4(g.colors[gi], g.colors[g.n + gi], g.colors[2 * g.n + gi], depth);
         else
             rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
-        rec.unc[pos] = g.uncert ? g.uncert[gi] : 0.0f;
         rec.gid[pos] = i;
         rec.view[pos] = (uint32_t)v;
         uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
         uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
         const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
                                     (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
-        rec.pbox[pos] = pb;
         rec.dkey[pos] = __float_as_uint(depth);
         sortkey[pos] = __float_as_uint(depth);
         // pairs: the tiles the support meets (a subset of the box's
@@ -900,7 +896,8 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         e.rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
         e.ntiles = max(nt, 1u);
         e.view = (uint32_t)v;
-        e.pad0 = e.pad1 = 0;
+        e.unc = __float_as_uint(g.uncert ? g.uncert[gi] : 0.0f);
+        e.pad = 0;
         rec.emit[pos] = e;
         order[pos] = pos;
     }
@@ -1131,11 +1128,12 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restric
         if (threadIdx.x < (uint32_t)B && idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
-            s_pb[threadIdx.x] = rec.pbox[r];
-            s_g0[threadIdx.x] = rec.geo0[r];
-            s_g1[threadIdx.x] = rec.geo1[r];
+            const EmitRec e = rec.emit[r];
+            s_pb[threadIdx.x] = e.pbox;
+            s_g0[threadIdx.x] = e.g0;
+            s_g1[threadIdx.x] = e.g1;
             s_at[threadIdx.x] = rec.attr[r];
-            s_u[threadIdx.x] = rec.unc[r];
+            s_u[threadIdx.x] = __uint_as_float(e.unc);
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);
@@ -1508,11 +1506,12 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
             if (e < bend) {
                 const uint32_t r = inst_rec[rg.x + (uint32_t)e];
                 s_r[threadIdx.x] = r;
-                s_pb[threadIdx.x] = rec.pbox[r];
-                s_g0[threadIdx.x] = rec.geo0[r];
-                s_g1[threadIdx.x] = rec.geo1[r];
+                const EmitRec e = rec.emit[r];
+                s_pb[threadIdx.x] = e.pbox;
+                s_g0[threadIdx.x] = e.g0;
+                s_g1[threadIdx.x] = e.g1;
                 s_at[threadIdx.x] = rec.attr[r];
-                s_u[threadIdx.x] = rec.unc[r];
+                s_u[threadIdx.x] = __uint_as_float(e.unc);
             }
         }
         __syncthreads();
@@ -1787,10 +1786,11 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
         if (threadIdx.x < (uint32_t)B && idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
-            s_pb[threadIdx.x] = rec.pbox[r];
-            s_g0[threadIdx.x] = rec.geo0[r];
-            s_g1[threadIdx.x] = rec.geo1[r];
-            s_u[threadIdx.x] = rec.unc[r];
+            const EmitRec e = rec.emit[r];
+            s_pb[threadIdx.x] = e.pbox;
+            s_g0[threadIdx.x] = e.g0;
+            s_g1[threadIdx.x] = e.g1;
+            s_u[threadIdx.x] = __uint_as_float(e.unc);
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);

@@ -123,6 +123,34 @@ def pair_ids(keys, vals):
     return (keys >> np.uint64(32)) << np.uint64(32) | vals.astype(np.uint64)
 
 
+def test_sparse_visibility_records(raster, rctx):
+    # one Gaussian in 40 in front of the camera, the rest behind it: 256
+    # consecutive records then span ~10k Gaussians, more than a projection
+    # block stages, so record emission takes its global-memory search
+    g, cams = scenes.config1(n=100_000)
+    g = {k: v.copy() for k, v in g.items()}
+    behind = np.ones(100_000, bool)
+    behind[::40] = False
+    g["means"][2, behind] = -g["means"][2, behind]
+    say("sparse visibility: 100k Gaussians, 2.5k in front")
+    dev = raster.to_device(g)
+    f = raster.Frame(rctx, dev, cams, S())
+    f.bin_sort()
+    keys, vals, _ = f.export()
+    keys = keys.cpu().numpy().view(np.uint64)
+    vals = vals.cpu().numpy().view(np.uint32)
+    k_box, v_box = oracle.keys(g, cams, S(), (16, 16))
+    keep = np.isin(pair_ids(k_box, v_box), pair_ids(keys, vals))
+    assert keep.sum() == len(keys) > 0
+    assert np.array_equal(keys, k_box[keep]) and np.array_equal(vals, v_box[keep])
+    assert np.all(np.isin(vals, np.nonzero(~behind)[0]))
+    out = f.render()
+    f.close()
+    imgs = raster.unpack_images(out, cams)
+    r = oracle.render(g, cams[0], S())
+    assert_images_close(gpu_stack(imgs[0], cams[0]), r, label="sparse")
+
+
 @pytest.mark.parametrize("tile", TILES)
 def test_keys_bit_exact(raster, rctx, tile):
     g, cams = scenes.config1(n=1500)
