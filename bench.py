@@ -27,12 +27,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "render+backward Mpix/s and candidate views scored/s, batched vs plain, 1 GPU"
 
-# Algorithmic work per unit ("Roofline"):
+# Algorithmic work per unit:
 #  forward compositing: 20 FP32 VALU operations per contributing pixel-splat pair;
 #  backward compositing: 55 FP32 VALU operations per contributing pair.
 OPS_PER_PAIR = {"render": 20.0, "render_backward": 55.0}
-# MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s
-# (unpacked FP32; the packed 157.3 TFLOP/s peak counts 2 lanes x FMA = 4 flops).
 # FP32 vector peak in lane-operations per second: 256 CUs x 4 SIMDs x 32 lanes
 # per cycle (a wave64 instruction every 2 cycles) x 2.4 GHz = 78.6e12, i.e. the
 # 157.3 TFLOP/s FP32 vector figure counting a fused multiply-add as one operation
