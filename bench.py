@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (20498.6 * 2.0 * 1024 + 26269.2 * 1024,
-                        "ee6017182ffd138fb352d08c18603ea447c6cd3bea1a91f7ce936d6cbbeff990"),
-    "render": (20786.9 * 2.0 * 1024 + 8400.0 * 1024,
-               "ee6017182ffd138fb352d08c18603ea447c6cd3bea1a91f7ce936d6cbbeff990"),
+    "render_backward": (14166.7 * 2.0 * 1024 + 26269.2 * 1024,
+                        "48f4c383e73f0571b4778409eaa3235b3e10e7680793b2ba2963d03b6376e50d"),
+    "render": (11407.5 * 2.0 * 1024 + 8400.0 * 1024,
+               "48f4c383e73f0571b4778409eaa3235b3e10e7680793b2ba2963d03b6376e50d"),
 }
 
 
