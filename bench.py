@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (14166.7 * 2.0 * 1024 + 26269.2 * 1024,
-                        "48f4c383e73f0571b4778409eaa3235b3e10e7680793b2ba2963d03b6376e50d"),
-    "render": (11407.5 * 2.0 * 1024 + 8400.0 * 1024,
-               "48f4c383e73f0571b4778409eaa3235b3e10e7680793b2ba2963d03b6376e50d"),
+    "render_backward": (14167.1 * 2.0 * 1024 + 26269.2 * 1024,
+                        "c28f50537ab42f6c320704a2a878e3d9db621f394a19163aa583933e71f65183"),
+    "render": (11406.7 * 2.0 * 1024 + 8400.0 * 1024,
+               "c28f50537ab42f6c320704a2a878e3d9db621f394a19163aa583933e71f65183"),
 }
 
 
