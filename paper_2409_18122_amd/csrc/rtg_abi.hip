@@ -307,6 +307,9 @@ void make_layout(const rtg_camera* cams, int n, int tw, int th, Layout& L) {
         for (int k = 0; k < 9; k++) d.R[k] = (double)c.R[k];
         for (int k = 0; k < 3; k++) d.T[k] = (double)c.T[k];
         d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+        for (int k = 0; k < 9; k++) d.Rf[k] = c.R[k];
+        for (int k = 0; k < 3; k++) d.Tf[k] = c.T[k];
+        d.fxf = c.fx; d.fyf = c.fy; d.cxf = c.cx; d.cyf = c.cy;
         d.W = c.width; d.H = c.height;
         d.tiles_x = (c.width + tw - 1) / tw;
         d.tiles_y = (c.height + th - 1) / th;

@@ -13,6 +13,7 @@ struct ViewDev {
     double R[9];  // camera-to-world rotation, row-major
     double T[3];  // camera centre in the world
     double fx, fy, cx, cy;
+    float Rf[9], Tf[3], fxf, fyf, cxf, cyf;  // the same in binary32 (the camera's own values)
     int32_t W, H, tiles_x, tiles_y;
     uint32_t tile_off;  // first global tile id of this view
     uint32_t pad;

@@ -52,7 +52,8 @@ struct GPre {
     double s[3];
     double o, rho2;
     float mu_f[3];
-    float reach;  // rho * max scale: bound on the support radius in 3D
+    float reach;           // rho * max scale: bound on the support radius in 3D
+    float rho_f, rho2_f;   // binary32 rho = sqrt(2 ln(o / alpha_min)) and rho^2, for the bound
 };
 
 // The isotropic form: s = (r, r, r) and Rq = I; only the first n log-scale values are read.
@@ -74,6 +75,8 @@ __device__ inline bool pre_gauss_iso(const GaussDev& g, int64_t i, const SetDev&
     P.o = op;
     P.rho2 = 2.0 * log((double)op / (double)st.alpha_min);
     P.reach = (float)(sqrt(P.rho2) * r);
+    P.rho_f = (float)sqrt(P.rho2);
+    P.rho2_f = (float)P.rho2;
     return true;
 }
 
@@ -108,6 +111,8 @@ __device__ inline bool pre_gauss(const GaussDev& g, int64_t i, const SetDev& st,
     P.rho2 = 2.0 * log((double)op / (double)st.alpha_min);
     double smax = fmax(P.s[0], fmax(P.s[1], P.s[2]));
     P.reach = (float)(sqrt(P.rho2) * smax);
+    P.rho_f = (float)sqrt(P.rho2);
+    P.rho2_f = (float)P.rho2;
     return true;
 }
 
@@ -116,26 +121,29 @@ __device__ inline bool pre_gauss(const GaussDev& g, int64_t i, const SetDev& st,
 // the image).  The half extent of the support box is bounded through
 // Sigma_xx <= s_max^2 |J_row0|^2 = s_max^2 fx^2 / t_z^2 (1 + t_x^2 / t_z^2).
 __device__ inline bool may_be_visible(const GPre& P, const ViewDev& V, const SetDev& st) {
-    float dx = P.mu_f[0] - (float)V.T[0];
-    float dy = P.mu_f[1] - (float)V.T[1];
-    float dz = P.mu_f[2] - (float)V.T[2];
+    float dx = P.mu_f[0] - V.Tf[0];
+    float dy = P.mu_f[1] - V.Tf[1];
+    float dz = P.mu_f[2] - V.Tf[2];
     float mag = fabsf(dx) + fabsf(dy) + fabsf(dz) + 1.0f;
-    float tz = dx * (float)V.R[2] + dy * (float)V.R[5] + dz * (float)V.R[8];
+    float tz = dx * V.Rf[2] + dy * V.Rf[5] + dz * V.Rf[8];
     float err = 1e-5f * mag;
     if (tz + err <= st.z_near) return false;
     if (tz <= 0.5f * st.z_near) return true;  // let the exact test decide
-    float tx = dx * (float)V.R[0] + dy * (float)V.R[3] + dz * (float)V.R[6];
-    float ty = dx * (float)V.R[1] + dy * (float)V.R[4] + dz * (float)V.R[7];
-    float iz = 1.0f / tz;
+    float tx = dx * V.Rf[0] + dy * V.Rf[3] + dz * V.Rf[6];
+    float ty = dx * V.Rf[1] + dy * V.Rf[4] + dz * V.Rf[7];
+    // hardware reciprocal and square root (within an ulp or two): the slack
+    // below is a relative 1e-3 plus a pixel
+    float iz = __builtin_amdgcn_rcpf(tz);
     float ux = tx * iz, uy = ty * iz;
-    float fx = (float)V.fx, fy = (float)V.fy;
-    float ax = fx * ux + (float)V.cx;
-    float ay = fy * uy + (float)V.cy;
+    float fx = V.fxf, fy = V.fyf;
+    float ax = fx * ux + V.cxf;
+    float ay = fy * uy + V.cyf;
     float rx = P.reach * fx * iz, ry = P.reach * fy * iz;
-    float hx = sqrtf(rx * rx * (1.0f + ux * ux) + 2.0f * (float)sqrt(P.rho2) * st.eps2d + st.eps2d * (float)P.rho2);
-    float hy = sqrtf(ry * ry * (1.0f + uy * uy) + 2.0f * (float)sqrt(P.rho2) * st.eps2d + st.eps2d * (float)P.rho2);
-    float slack_x = 1e-3f * (fabsf(ax - (float)V.cx) + hx) + 1.0f + err * fx * iz * 4.0f;
-    float slack_y = 1e-3f * (fabsf(ay - (float)V.cy) + hy) + 1.0f + err * fy * iz * 4.0f;
+    const float ep = 2.0f * P.rho_f * st.eps2d + st.eps2d * P.rho2_f;
+    float hx = __builtin_amdgcn_sqrtf(rx * rx * (1.0f + ux * ux) + ep);
+    float hy = __builtin_amdgcn_sqrtf(ry * ry * (1.0f + uy * uy) + ep);
+    float slack_x = 1e-3f * (fabsf(ax - V.cxf) + hx) + 1.0f + err * fx * iz * 4.0f;
+    float slack_y = 1e-3f * (fabsf(ay - V.cyf) + hy) + 1.0f + err * fy * iz * 4.0f;
     if (ax + hx + slack_x < 0.0f) return false;
     if (ax - hx - slack_x > (float)(V.W - 1)) return false;
     if (ay + hy + slack_y < 0.0f) return false;
