@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
     "render_backward": (14167.1 * 2.0 * 1024 + 26269.2 * 1024,
-                        "c28f50537ab42f6c320704a2a878e3d9db621f394a19163aa583933e71f65183"),
-    "render": (11406.7 * 2.0 * 1024 + 8400.0 * 1024,
-               "c28f50537ab42f6c320704a2a878e3d9db621f394a19163aa583933e71f65183"),
+                        "f1a0c597e5ed1d83c919e3596100b48f7d581828e2ccf022335a715dc87b7abc"),
+    "render": (11410.5 * 2.0 * 1024 + 8400.0 * 1024,
+               "f1a0c597e5ed1d83c919e3596100b48f7d581828e2ccf022335a715dc87b7abc"),
 }
 
 
