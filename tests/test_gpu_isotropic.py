@@ -163,3 +163,39 @@ def test_anisotropic_needs_quaternions(raster, rctx):
         raster.Frame(rctx, raster.to_device(g), cams, dict(scenes.DEFAULT_SETTINGS))
     with pytest.raises(raster.RtgError):
         raster.Frame(rctx, raster.to_device(g), cams, S(isotropic=2))
+
+
+def test_isotropic_graphs_match_eager(raster, rctx):
+    # the captured mapping step and the captured scoring pipeline take the setting too
+    g, cams, target = scenes.config4(n=60_000, n_views=2, width=256, height=144)
+    g, target = scenes.isotropic_scene(g), scenes.isotropic_scene(target)
+    dev = raster.to_device(g)
+    timg, tf = raster.render(rctx, raster.to_device(target), cams, S(), want=("rgb", "depth"))
+    tf.close()
+    say("isotropic map graph vs eager")
+    f = raster.Frame(rctx, dev, cams, S())
+    f.bin_sort()
+    out = f.render(("rgb", "depth"))
+    loss, d_rgb, d_dep = f.loss(out["rgb"], out["depth"], timg["rgb"], timg["depth"], 0.5)
+    ref = f.backward(d_rgb, d_dep)
+    f.close()
+    assert "quats" not in ref
+    mg = raster.MapGraph(rctx, dev, cams, timg["rgb"], timg["depth"], 0.5, S())
+    for rep in range(2):
+        lv = mg.launch()
+        assert mg.status()
+        torch.cuda.synchronize()
+        assert torch.equal(mg.rgb, out["rgb"]) and lv.item() == loss.item(), rep
+    for k in ref:
+        a = mg.grads[k].double().cpu().numpy()
+        b = 2.0 * ref[k].double().cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-5 * (np.linalg.norm(b) + 1e-300), k
+    mg.close()
+    say("isotropic score graph vs eager")
+    eager = raster.score_views(rctx, dev, cams, S()).cpu().numpy()
+    gr = raster.ScoreGraph(rctx, dev, 4, 256, 144, S(), probe=cams)
+    for rep in range(2):
+        got = gr.launch(cams).cpu().numpy()
+        assert gr.status()
+        assert np.array_equal(got, eager), rep
+    gr.close()
