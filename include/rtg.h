@@ -29,6 +29,7 @@
 #ifndef RTG_H
 #define RTG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -121,6 +122,20 @@ int32_t rtg_device_count(void);
 /* Creates a context on `device`.  RTG_ERR_HIP if there is no such device. */
 rtg_status rtg_create(int32_t device, rtg_ctx **out);
 void rtg_destroy(rtg_ctx *ctx);
+
+/* Device allocator of a context's scratch (projected records, pair lists,
+ * sort buffers, per-pixel state, gradients in screen space).  By default the
+ * library calls hipMalloc and keeps released blocks for reuse; with an
+ * allocator set, blocks come from alloc(user, bytes) (device memory of the
+ * context's device, 256-byte aligned, or NULL when it cannot allocate) and go
+ * back through free(user, ptr) when the context trims its cache or is
+ * destroyed; a caching allocator such as PyTorch's can serve them.  Both
+ * NULL restores hipMalloc.  RTG_ERR_INVALID while any frame or graph of the
+ * context holds scratch (destroy them first), or if only one of alloc / free
+ * is given.  Synchronises the device. */
+typedef void *(*rtg_alloc_fn)(void *user, size_t bytes);
+typedef void (*rtg_free_fn)(void *user, void *ptr);
+rtg_status rtg_set_allocator(rtg_ctx *ctx, rtg_alloc_fn alloc, rtg_free_fn free, void *user);
 
 /* Projection and culling (Sec. III: mu_2D = K R^T (mu - T) / d with the EWA
  * 2D covariance).  Projects every Gaussian into each of the n_views cameras

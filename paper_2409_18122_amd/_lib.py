@@ -43,8 +43,13 @@ class Grads(_c.Structure):
                 ("d_colors", vp)]
 
 
+# device scratch allocator callbacks (rtg_set_allocator)
+ALLOC_FN = _c.CFUNCTYPE(_c.c_void_p, _c.c_void_p, _c.c_size_t)
+FREE_FN = _c.CFUNCTYPE(None, _c.c_void_p, _c.c_void_p)
+
 # name -> (restype, argtypes)
 SIGNATURES = {
+    "rtg_set_allocator": (i32, [vp, ALLOC_FN, FREE_FN, vp]),
     "rtg_last_error": (_c.c_char_p, []),
     "rtg_default_settings": (i32, [_c.POINTER(Settings)]),
     "rtg_device_count": (i32, []),

@@ -58,10 +58,28 @@ rtg_status check_launch(const char* what) {
 // Grow-only caching allocator: released blocks are kept and reused for
 // requests of at most their size (and at least half of it).  Blocks are
 // reused in stream order, which is safe because a context serves one stream.
+// Blocks come from hipMalloc, or from the caller's allocator when one is set.
 struct Pool {
     std::multimap<size_t, void*> free_;
     std::map<void*, size_t> size_;
     size_t bytes_live = 0, bytes_cached = 0;
+    rtg_alloc_fn alloc_fn = nullptr;
+    rtg_free_fn free_fn = nullptr;
+    void* user = nullptr;
+
+    void* raw_alloc(size_t bytes) {
+        if (alloc_fn) return alloc_fn(user, bytes);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void raw_free(void* p) {
+        if (free_fn) free_fn(user, p);
+        else (void)hipFree(p);
+    }
 
     rtg_status get(size_t bytes, void** out) {
         bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
@@ -73,17 +91,12 @@ struct Pool {
             free_.erase(it);
             return RTG_OK;
         }
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
+        void* p = raw_alloc(bytes);
+        if (!p) {
             // release the cache and retry once
             trim();
-            e = hipMalloc(&p, bytes);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return set_err(RTG_ERR_OOM, "device allocation of %zu bytes failed", bytes);
-            }
+            p = raw_alloc(bytes);
+            if (!p) return set_err(RTG_ERR_OOM, "device allocation of %zu bytes failed", bytes);
         }
         size_[p] = bytes;
         bytes_live += bytes;
@@ -100,7 +113,7 @@ struct Pool {
     }
     void trim() {
         for (auto& kv : free_) {
-            (void)hipFree(kv.second);
+            raw_free(kv.second);
             size_.erase(kv.second);
         }
         free_.clear();
@@ -108,7 +121,7 @@ struct Pool {
     }
     ~Pool() {
         trim();
-        for (auto& kv : size_) (void)hipFree(kv.first);
+        for (auto& kv : size_) raw_free(kv.first);
     }
 };
 
@@ -579,6 +592,21 @@ rtg_status rtg_create(int32_t device, rtg_ctx** out) {
     c->cu = device_cu_count();
     HIP_TRY(hipHostMalloc((void**)&c->pinned, sizeof(uint32_t) * 64, hipHostMallocDefault));
     *out = c.release();
+    return RTG_OK;
+}
+
+rtg_status rtg_set_allocator(rtg_ctx* ctx, rtg_alloc_fn alloc, rtg_free_fn free, void* user) {
+    RTG_TRY(ctx_ok(ctx));
+    if ((alloc == nullptr) != (free == nullptr))
+        return set_err(RTG_ERR_INVALID, "alloc and free must both be set or both be NULL");
+    if (ctx->pool.bytes_live)
+        return set_err(RTG_ERR_INVALID, "%zu bytes are in use by frames or graphs of this context; destroy them first",
+                       ctx->pool.bytes_live);
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->pool.trim();  // cached blocks go back to the allocator they came from
+    ctx->pool.alloc_fn = alloc;
+    ctx->pool.free_fn = free;
+    ctx->pool.user = user;
     return RTG_OK;
 }
 

@@ -6,12 +6,15 @@ Tensors must be float32, contiguous and on the context's device.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import json
 import os
+import weakref
 
 import torch
 
+from . import _lib as _lib_mod
 from ._lib import (Camera, Gaussians, Grads, RtgError, Settings, check, lib, RTG_ERR_CAPACITY)
 
 DEFAULTS = {
@@ -76,6 +79,18 @@ def image_sizes(cams):
     return [int(c["width"]) * int(c["height"]) for c in cams]
 
 
+# contexts whose scratch comes from PyTorch: closed at exit while torch is still alive
+_TORCH_ALLOC_CTXS = weakref.WeakSet()
+
+
+def _close_torch_alloc_contexts():
+    for c in list(_TORCH_ALLOC_CTXS):
+        c.close()
+
+
+atexit.register(_close_torch_alloc_contexts)
+
+
 class Context:
     """One library context bound to a device (one per stream)."""
 
@@ -84,6 +99,32 @@ class Context:
         check(lib().rtg_create(int(device), ctypes.byref(h)))
         self.handle = h
         self.device = device
+        self._callbacks = None
+
+    def use_torch_allocator(self):
+        """Serve this context's device scratch from PyTorch's caching
+        allocator (rtg_set_allocator); no frame or graph may be alive."""
+        dev = self.device
+
+        def _alloc(user, nbytes):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev,
+                                                          stream=torch.cuda.current_stream(dev))
+            except RuntimeError:  # out of memory: the library reports RTG_ERR_OOM
+                return None
+
+        def _free(user, ptr):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        cbs = (_lib_mod.ALLOC_FN(_alloc), _lib_mod.FREE_FN(_free))
+        check(lib().rtg_set_allocator(self.handle, cbs[0], cbs[1], None))
+        self._callbacks = cbs  # kept alive as long as the library may call them
+        _TORCH_ALLOC_CTXS.add(self)
+
+    def use_hip_allocator(self):
+        """Back to the library's own hipMalloc-based cache."""
+        check(lib().rtg_set_allocator(self.handle, _lib_mod.ALLOC_FN(), _lib_mod.FREE_FN(), None))
+        self._callbacks = None
 
     def close(self):
         if self.handle:

@@ -89,6 +89,8 @@ def test_null_arguments_rejected_on_host(L):
     assert L.rtg_collision_check(None, None, None, 4, 0.25, 3.0, None, None, None) == -1
     stats = (ctypes.c_int64 * 4)()
     assert L.rtg_frame_stats(None, None, stats, None) == -1
+    from paper_2409_18122_amd._lib import ALLOC_FN, FREE_FN
+    assert L.rtg_set_allocator(None, ALLOC_FN(), FREE_FN(), None) == -1
     assert L.rtg_timing_enable(None, 1) == -1
     assert L.rtg_timing_reset(None) == -1
     ms = ctypes.c_double()
