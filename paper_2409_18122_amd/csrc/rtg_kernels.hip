@@ -1385,12 +1385,15 @@ __device__ __forceinline__ void add_g2d(double* g2d, uint32_t r, const float* t)
 // One pixel's step of the reverse compositing recursion for a kept splat:
 // restores T and the running sums S of the splats behind it, and adds the
 // pixel's contributions to the splat's per-lane sums acc (same order as
-// add_g2d).  T_i = T_{i+1} / (1 - a_i); w = a_i T_i.
+// add_g2d).  T_i = T_{i+1} / (1 - a_i); w = a_i T_i.  Since a_i <= alpha_max
+// < 1, 1 - a_i is a normal number well away from zero and the hardware
+// reciprocal (within 1 ulp) stands in for the correctly rounded division; T
+// only scales gradient terms here and decides nothing.
 __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float w1, float w2, float4 g1,
                                           float4 at, float ui, float amax, float kq, float gr, float gg, float gb,
                                           float gd, float ga, float gu, float& T, float& S0, float& S1, float& S2,
                                           float& S3, float& S4, float& S5, float* acc) {
-    const float inv = 1.0f / (1.0f - a);
+    const float inv = __builtin_amdgcn_rcpf(1.0f - a);
     const float Ti = T * inv;
     const float w = a * Ti;
     float da = gr * (at.x * Ti - S0 * inv);
