@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (14167.1 * 2.0 * 1024 + 26269.2 * 1024,
-                        "f1a0c597e5ed1d83c919e3596100b48f7d581828e2ccf022335a715dc87b7abc"),
+    "render_backward": (14164.1 * 2.0 * 1024 + 26269.2 * 1024,
+                        "53b6497efb9d9980ab67eb4f64ef6430618c5cb17ea130f24d0fe2b457b23eb8"),
     "render": (11410.5 * 2.0 * 1024 + 8400.0 * 1024,
-               "f1a0c597e5ed1d83c919e3596100b48f7d581828e2ccf022335a715dc87b7abc"),
+               "53b6497efb9d9980ab67eb4f64ef6430618c5cb17ea130f24d0fe2b457b23eb8"),
 }
 
 
