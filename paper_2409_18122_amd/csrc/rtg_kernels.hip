@@ -1323,10 +1323,15 @@ __device__ __forceinline__ void wave_sum_dpp_n(float* x) {
 // and adds the partner's copy of the kept half.  Partners must agree on every
 // earlier choice, so the DPP pairings that flip several lane bits come first:
 // row_mirror (decided by lane bit 3), row_half_mirror (bit 2), then quad
-// swaps xor 2 (bit 1) and xor 1 (bit 0), then shuffles across 16 (bit 4) and
-// 32 lanes (sum).  Lane l ends with the total of value
+// swaps xor 2 (bit 1) and xor 1 (bit 0), then the row swaps of gfx950 across
+// 16 lanes (bit 4) and 32 lanes (sum).  Lane l ends with the total of value
 // v = 10 b3 + 5 b2 + 3 b1 + 2 b0 + b4, valid when 2 b0 + b4 < (b1 ? 2 : 3)
 // (else v = -1); lanes l and l + 32 hold the same total.
+//
+// v_permlane16_swap(x, y) exchanges the odd 16-lane rows of x with the even
+// rows of y, so the two results add up, in every lane, to x[l] + x[l ^ 16] on
+// even rows and y[l ^ 16] + y[l] on odd rows; v_permlane32_swap(x, x) likewise
+// gives x[l] + x[l ^ 32].  Both are VALU moves, not LDS round trips.
 __device__ __forceinline__ float wave_sum_halving20(const float* x, int lane, int& v) {
     const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1,
                b4 = (lane >> 4) & 1;
@@ -1353,11 +1358,12 @@ __device__ __forceinline__ float wave_sum_halving20(const float* x, int lane, in
         const float keep = b0 ? hi : d[j], send = b0 ? d[j] : hi;
         e[j] = keep + dpp_mov<0xb1>(send);  // quad_perm [1, 0, 3, 2]
     }
-    const float keep = b4 ? e[1] : e[0], send = b4 ? e[0] : e[1];
-    const float f = keep + __shfl_xor(send, 16, 64);
+    const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(e[0]), __float_as_uint(e[1]), false, false);
+    const float f = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
     const int pos = 2 * (int)b0 + (int)b4;
     v = pos < (b1 ? 2 : 3) ? 10 * (int)b3 + 5 * (int)b2 + 3 * (int)b1 + pos : -1;
-    return f + __shfl_xor(f, 32, 64);
+    const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(f), __float_as_uint(f), false, false);
+    return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
 }
 
 // Highest set bit of a wave-uniform mask array, cleared; -1 if none.
