@@ -506,7 +506,7 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
     Timer tm(f->ctx, 2, s);
     emit_instances(f->sorted_order(), f->ctr(C_REC), rc, f->ctr(C_INST), f->records(), f->views.as<ViewDev>(),
                    f->inst_off.as<uint32_t>(), f->st.tile_w, f->st.tile_h, to_dev(f->st), f->inst_cap,
-                   f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(),
+                   f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(), f->ranges.as<uint2>(), f->tiles_cap,
                    f->ctr(C_FLAGS), s);
     int tbits = bits_for(std::max<uint32_t>(f->tiles_cap, 2));
     f->inst_in_alt = radix_sort(f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(), f->tkey2.as<uint32_t>(),

@@ -130,12 +130,14 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
                uint32_t cap, int nbits, int max_db, SortWs ws, hipStream_t s);
 
 // Instances of the depth-ordered records: tile keys and record ids, one per
-// tile a record's support meets (tiles tw x th).
+// tile a record's support meets (tiles tw x th).  Also empties ranges[0,
+// tiles_cap) for tile_ranges.
 void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, const uint32_t* K_dev,
                     Records rec, const ViewDev* views, const uint32_t* inst_off, int tw, int th, SetDev st,
-                    uint32_t inst_cap,
-                    uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s);
-// ranges[t] = [start, end) over the tile-sorted keys; ranges pre-zeroed here.
+                    uint32_t inst_cap, uint32_t* tile_key, uint32_t* inst_rec, uint2* ranges, uint32_t tiles_cap,
+                    uint32_t* flags, hipStream_t s);
+// ranges[t] = [start, end) over the tile-sorted keys, for the occupied tiles;
+// emit_instances has emptied them all.
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap,
                  uint2* ranges, uint32_t tiles_cap, const uint32_t* flags, hipStream_t s);
 

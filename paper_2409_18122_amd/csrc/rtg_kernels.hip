@@ -427,7 +427,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __re
                                                             const uint32_t* __restrict__ n_dev,
                                                             uint32_t cap, uint32_t* __restrict__ partial) {
     __shared__ uint32_t ws[SC_THREADS / 64];
-    uint32_t n = min(*n_dev, cap);
+    const uint32_t n = n_dev ? min(*n_dev, cap) : cap;
     uint32_t begin, end;
     chunk_of(n, gridDim.x, begin, end);
     uint32_t acc = 0;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
                                                           const uint32_t* __restrict__ partial,
                                                           uint32_t* __restrict__ total_out) {
     __shared__ uint32_t ws[SC_THREADS / 64];
-    uint32_t n = min(*n_dev, cap);
+    const uint32_t n = n_dev ? min(*n_dev, cap) : cap;
     uint32_t begin, end;
     chunk_of(n, gridDim.x, begin, end);
     uint32_t before = 0, all = 0;
@@ -919,9 +919,14 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
                                                                int tws, int ths, float log2_amin,
                                                                uint32_t inst_cap, uint32_t* __restrict__ tile_key,
                                                                uint32_t* __restrict__ inst_rec,
+                                                               uint2* __restrict__ ranges, uint32_t tiles_cap,
                                                                uint32_t* __restrict__ flags) {
     __shared__ uint32_t s_off[EM_ITEMS + 1];
     __shared__ uint32_t s_lo, s_n;
+    // every tile starts empty; k_tile_ranges later fills the occupied ones
+    // (nothing reads the ranges in between), and an overflow leaves them empty
+    for (uint32_t t = blockIdx.x * EM_THREADS + threadIdx.x; t < tiles_cap; t += gridDim.x * EM_THREADS)
+        ranges[t] = make_uint2(0u, 0u);
     if (*flags & FLAG_REC_OVERFLOW) return;
     const uint32_t R = min(*R_dev, rec_cap);
     const uint32_t Kall = *K_dev;
@@ -993,11 +998,6 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
         if (i == 0 || key[i - 1] != t) ranges[t].x = i;
         if (i + 1 == K || key[i + 1] != t) ranges[t].y = i + 1;
     }
-}
-
-__global__ void k_zero_ranges(uint2* ranges, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        ranges[i] = make_uint2(0u, 0u);
 }
 
 // ------------------------------------------------------------ compositing
@@ -2376,13 +2376,12 @@ static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, cons
     const int fused = nb <= RS_FUSED_BLOCKS;
     k_rs_upsweep<DB><<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, bits, ws.hist, fused);
     if (!fused) {
-        // table of 2^DB * nb counts: the multi-block scan, in place
+        // table of 2^DB * nb counts, a size known here: the multi-block scan,
+        // in place
         const uint32_t count = (uint32_t)((1u << DB) * nb);
         int sb = scan_blocks(count);
-        k_fill_u32<<<1, 64, 0, s>>>(ws.partial + SC_MAX_BLOCKS, count, 1);
-        k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.partial + SC_MAX_BLOCKS, count, ws.partial);
-        k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, ws.partial + SC_MAX_BLOCKS, count,
-                                              ws.partial, nullptr);
+        k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, nullptr, count, ws.partial);
+        k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, nullptr, count, ws.partial, nullptr);
     }
     k_rs_scatter<DB><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused);
 }
@@ -2410,15 +2409,16 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
 
 void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_cap, const uint32_t* K_dev,
                     Records rec, const ViewDev* views, const uint32_t* inst_off, int tw, int th, SetDev st,
-                    uint32_t inst_cap, uint32_t* tile_key, uint32_t* inst_rec, uint32_t* flags, hipStream_t s) {
+                    uint32_t inst_cap, uint32_t* tile_key, uint32_t* inst_rec, uint2* ranges, uint32_t tiles_cap,
+                    uint32_t* flags, hipStream_t s) {
     unsigned grid = grid_for(std::max<uint32_t>(inst_cap, 1), EM_ITEMS, 16384);
     k_emit_instances<<<grid, EM_THREADS, 0, s>>>(order, R_dev, rec_cap, K_dev, rec, views, inst_off, ilog2(tw),
-                                                 ilog2(th), st.log2_amin, inst_cap, tile_key, inst_rec, flags);
+                                                 ilog2(th), st.log2_amin, inst_cap, tile_key, inst_rec, ranges,
+                                                 tiles_cap, flags);
 }
 
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap, uint2* ranges,
                  uint32_t tiles_cap, const uint32_t* flags, hipStream_t s) {
-    k_zero_ranges<<<grid_for(tiles_cap, 256, 4096), 256, 0, s>>>(ranges, tiles_cap);
     k_tile_ranges<<<grid_for(inst_cap, 256, 8192), 256, 0, s>>>(tile_key, K_dev, inst_cap, ranges, tiles_cap,
                                                                 flags);
 }
