@@ -1103,8 +1103,10 @@ __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __re
 }
 
 // B splats are staged per batch (B <= TW * TH; threads below B load them).
+// At most 96 VGPRs (five waves per SIMD): a 640x480 frame of 16x16 tiles has
+// 4.7 waves per SIMD, all resident only at that occupancy.
 template <int TW, int TH, int B>
-__global__ __launch_bounds__(TW * TH) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
+__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5))) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec,
                                                         Records rec, SetDev st, RenderOut out,
