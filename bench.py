@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (14164.1 * 2.0 * 1024 + 26269.2 * 1024,
-                        "53b6497efb9d9980ab67eb4f64ef6430618c5cb17ea130f24d0fe2b457b23eb8"),
-    "render": (11410.5 * 2.0 * 1024 + 8400.0 * 1024,
-               "53b6497efb9d9980ab67eb4f64ef6430618c5cb17ea130f24d0fe2b457b23eb8"),
+    "render_backward": (14164.6 * 2.0 * 1024 + 26269.2 * 1024,
+                        "51e092c672ddc11d0f7be07bd46a421a3c0f5cbdcb1acfdb3ec7470a8609fded"),
+    "render": (11406.3 * 2.0 * 1024 + 8400.0 * 1024,
+               "51e092c672ddc11d0f7be07bd46a421a3c0f5cbdcb1acfdb3ec7470a8609fded"),
 }
 
 
