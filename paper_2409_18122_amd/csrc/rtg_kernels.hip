@@ -1103,10 +1103,11 @@ __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __re
 }
 
 // B splats are staged per batch (B <= TW * TH; threads below B load them).
-// At most 96 VGPRs (five waves per SIMD): a 640x480 frame of 16x16 tiles has
-// 4.7 waves per SIMD, all resident only at that occupancy.
+// Register budget: at most 80 VGPRs, six waves per SIMD (a 640x480 frame of
+// 16x16 tiles brings 4.7 waves per SIMD, larger frames many more); the
+// 128-splat batch would spill there and keeps 96 VGPRs, five waves.
 template <int TW, int TH, int B>
-__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5))) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
+__global__ __launch_bounds__(TW * TH, B == 128 ? 5 : 6) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec,
                                                         Records rec, SetDev st, RenderOut out,
@@ -1889,7 +1890,7 @@ __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restri
 }
 
 template <int TW, int TH, int B>
-__global__ __launch_bounds__(TW * TH) void k_score_persistent(const ViewDev* __restrict__ views,
+__global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) void k_score_persistent(const ViewDev* __restrict__ views,
                                                               const Header* __restrict__ hdr,
                                                               const uint2* __restrict__ ranges,
                                                               const uint32_t* __restrict__ inst_rec, Records rec,
