@@ -501,9 +501,11 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
 // blocks splits the input into equal chunks; per pass: per-block digit
 // histograms (upsweep), the offsets of every (digit, block), and a scatter in
 // which every wave ranks its items with 64-lane ballots (peers with the same
-// digit), preserving input order within the block.  Up to 128 blocks compute
-// their offsets themselves from the block-major histogram table; more blocks
-// scan a digit-major table with the multi-block scan.
+// digit), preserving input order within the block; with 8-bit digits the
+// block then sorts its tile in LDS and writes each digit's run from
+// consecutive lanes.  Up to 128 blocks compute their offsets themselves from
+// the block-major histogram table; more blocks scan a digit-major table with
+// the multi-block scan.
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
@@ -571,7 +573,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
     }
 }
 
-template <int DB>
+// STAGE: a tile's items are first placed at their block-local sorted positions
+// in LDS and written out in that order, so that consecutive lanes write the
+// consecutive addresses of a digit's run; otherwise each item is written from
+// where its wave ranked it.
+template <int DB, bool STAGE>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            uint32_t* __restrict__ kout,
@@ -584,6 +590,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     __shared__ uint32_t wh[RS_WAVES][NB];
     __shared__ uint32_t bbase[NB];
     __shared__ uint32_t ws[RS_WAVES];
+    constexpr int SB = STAGE ? NB : 1, ST = STAGE ? RS_TILE : 1;
+    __shared__ uint32_t lst[SB], tcnt[SB];
+    __shared__ uint32_t s_k[ST], s_v[ST];
     const int tid = threadIdx.x, wv = tid >> 6;
     const uint32_t lane = lane_id();
     const uint32_t mask = (1u << bits) - 1u;
@@ -667,26 +676,88 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
             if (valid && lane == (uint32_t)__builtin_ctzll(m)) wh[wv][d] = before + (uint32_t)__popcll(m);
         }
         __syncthreads();
-        for (int d = tid; d < NB; d += RS_THREADS) {
-            uint32_t run = bbase[d];
+        if constexpr (!STAGE) {
+            for (int d = tid; d < NB; d += RS_THREADS) {
+                uint32_t run = bbase[d];
 #pragma unroll
-            for (int w = 0; w < RS_WAVES; w++) {
-                uint32_t c = wh[w][d];
-                wh[w][d] = run;
-                run += c;
+                for (int w = 0; w < RS_WAVES; w++) {
+                    uint32_t c = wh[w][d];
+                    wh[w][d] = run;
+                    run += c;
+                }
+                bbase[d] = run;
             }
-            bbase[d] = run;
-        }
-        __syncthreads();
+            __syncthreads();
 #pragma unroll
-        for (int j = 0; j < RS_IPT; j++) {
-            uint32_t idx = seg + j * 64 + lane;
-            if (idx < end) {
-                uint32_t d = (k[j] >> shift) & mask;
-                uint32_t dst = wh[wv][d] + pos[j];
-                kout[dst] = k[j];
-                vout[dst] = v[j];
+            for (int j = 0; j < RS_IPT; j++) {
+                uint32_t idx = seg + j * 64 + lane;
+                if (idx < end) {
+                    uint32_t d = (k[j] >> shift) & mask;
+                    uint32_t dst = wh[wv][d] + pos[j];
+                    kout[dst] = k[j];
+                    vout[dst] = v[j];
+                }
             }
+        } else {
+            // per digit: the waves' offsets inside the tile's run of the digit, and the run length
+            for (int d = tid; d < NB; d += RS_THREADS) {
+                uint32_t run = 0;
+#pragma unroll
+                for (int w = 0; w < RS_WAVES; w++) {
+                    uint32_t c = wh[w][d];
+                    wh[w][d] = run;
+                    run += c;
+                }
+                tcnt[d] = run;
+            }
+            __syncthreads();
+            // lst[d]: start of digit d's run in the tile's sorted order (thread tid owns
+            // the DPT consecutive digits from tid * DPT)
+            {
+                uint32_t c[DPT];
+                uint32_t mine = 0;
+#pragma unroll
+                for (int j = 0; j < DPT; j++) {
+                    c[j] = tid * DPT < NB ? tcnt[tid * DPT + j] : 0u;
+                    mine += c[j];
+                }
+                const uint32_t inc = wave_incl_scan(mine);
+                if (lane == 63) ws[wv] = inc;
+                __syncthreads();
+                uint32_t base = inc - mine;
+#pragma unroll
+                for (int w = 0; w < RS_WAVES; w++)
+                    if (w < wv) base += ws[w];
+                if (tid * DPT < NB) {
+#pragma unroll
+                    for (int j = 0; j < DPT; j++) {
+                        lst[tid * DPT + j] = base;
+                        base += c[j];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RS_IPT; j++) {
+                uint32_t idx = seg + j * 64 + lane;
+                if (idx < end) {
+                    uint32_t d = (k[j] >> shift) & mask;
+                    uint32_t lp = lst[d] + wh[wv][d] + pos[j];
+                    s_k[lp] = k[j];
+                    s_v[lp] = v[j];
+                }
+            }
+            __syncthreads();
+            const uint32_t tn = min<uint32_t>(RS_TILE, end - t0);
+            for (uint32_t i = tid; i < tn; i += RS_THREADS) {
+                const uint32_t kk = s_k[i];
+                const uint32_t d = (kk >> shift) & mask;
+                const uint32_t dst = bbase[d] + (i - lst[d]);
+                kout[dst] = kk;
+                vout[dst] = s_v[i];
+            }
+            __syncthreads();
+            for (int d = tid; d < NB; d += RS_THREADS) bbase[d] += tcnt[d];
         }
         __syncthreads();
     }
@@ -2386,7 +2457,9 @@ static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, cons
         k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, nullptr, count, ws.partial);
         k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, nullptr, count, ws.partial, nullptr);
     }
-    k_rs_scatter<DB><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused);
+    // 8-bit passes stage their scatter in LDS; the 11-bit one writes directly (its
+    // per-wave tables already take 32 KB of LDS)
+    k_rs_scatter<DB, DB == 8><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused);
 }
 
 // The nbits are split into the fewest passes of at most max_db bits, as
