@@ -499,7 +499,8 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
 // ------------------------------------------------------------- radix sort
 // Stable LSD sort with digits of up to 11 bits (2048 bins).  A fixed grid of
 // blocks splits the input into equal chunks; per pass: per-block digit
-// histograms (upsweep), the offsets of every (digit, block), and a scatter in
+// histograms (upsweep, one LDS atomic add per item into per-wave tables), the
+// offsets of every (digit, block), and a scatter in
 // which every wave ranks its items with 64-lane ballots (peers with the same
 // digit), preserving input order within the block; with 8-bit digits the
 // block then sorts its tile in LDS and writes each digit's run from
@@ -555,11 +556,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
     rs_chunk(n, begin, end);
     for (uint32_t base = begin + wv * 64; base < end; base += RS_THREADS) {
         uint32_t idx = base + lane_id();
-        bool valid = idx < end;
-        uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
-        uint64_t vm = __ballot(valid);
-        uint64_t m = digit_peers<DB>(d, vm);
-        if (valid && lane_id() == (uint32_t)__builtin_ctzll(m)) h[wv][d] += (uint32_t)__popcll(m);
+        if (idx < end) atomicAdd(&h[wv][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = tid; d < NB; d += RS_THREADS) {
