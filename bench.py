@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
     "render_backward": (14164.6 * 2.0 * 1024 + 26269.2 * 1024,
-                        "581e9ed9a5a2240c07f323a55838aa4e9e62725652eb5483b9908e40b26fdc44"),
-    "render": (11404.2 * 2.0 * 1024 + 8400.0 * 1024,
-               "581e9ed9a5a2240c07f323a55838aa4e9e62725652eb5483b9908e40b26fdc44"),
+                        "3699c7faacd9297f849cb6a31ee6e65a9bfaa0578c2829fde2daeed7a488eb59"),
+    "render": (11406.8 * 2.0 * 1024 + 8400.0 * 1024,
+               "3699c7faacd9297f849cb6a31ee6e65a9bfaa0578c2829fde2daeed7a488eb59"),
 }
 
 
