@@ -1140,7 +1140,8 @@ __device__ __forceinline__ void pop_n(uint64_t& mm, int base, int (&ks)[P]) {
 
 // Splats evaluated per step of the front-to-back loops: their alphas are
 // independent of the pixel state, so they overlap; the updates follow in order.
-constexpr int FWD_STEP = 4;
+// At six waves per SIMD two per step measured 1% faster than four.
+constexpr int FWD_STEP = 2;
 // The scoring loop's (it keeps only T and one sum per pixel): 2 measured 3%
 // faster than 1, 4 or 8 on 64 and 256 views.
 constexpr int SCORE_STEP = 2;
