@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the counter readings of a plain 256 MiB copy (fetch x2.0, write x1.0); valid
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
-    "render_backward": (14164.6 * 2.0 * 1024 + 26269.2 * 1024,
-                        "3699c7faacd9297f849cb6a31ee6e65a9bfaa0578c2829fde2daeed7a488eb59"),
-    "render": (11406.8 * 2.0 * 1024 + 8400.0 * 1024,
-               "3699c7faacd9297f849cb6a31ee6e65a9bfaa0578c2829fde2daeed7a488eb59"),
+    "render_backward": (14164.1 * 2.0 * 1024 + 26269.2 * 1024,
+                        "f5bb94e067ef6eb1e9ebc52f2e51d81945ea9c81c13c22367e276f73a5bd18bb"),
+    "render": (11344.5 * 2.0 * 1024 + 8400.0 * 1024,
+               "f5bb94e067ef6eb1e9ebc52f2e51d81945ea9c81c13c22367e276f73a5bd18bb"),
 }
 
 
