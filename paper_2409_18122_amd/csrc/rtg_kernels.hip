@@ -1173,10 +1173,9 @@ __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __re
 
 // B splats are staged per batch (B <= TW * TH; threads below B load them).
 // Register budget: at most 80 VGPRs, six waves per SIMD (a 640x480 frame of
-// 16x16 tiles brings 4.7 waves per SIMD, larger frames many more); the
-// 128-splat batch would spill there and keeps 96 VGPRs, five waves.
+// 16x16 tiles brings 4.7 waves per SIMD, larger frames many more).
 template <int TW, int TH, int B>
-__global__ __launch_bounds__(TW * TH, B == 128 ? 5 : 6) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
+__global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec,
                                                         Records rec, SetDev st, RenderOut out,
