@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
     "render_backward": (14164.1 * 2.0 * 1024 + 26269.2 * 1024,
-                        "f5bb94e067ef6eb1e9ebc52f2e51d81945ea9c81c13c22367e276f73a5bd18bb"),
-    "render": (11344.5 * 2.0 * 1024 + 8400.0 * 1024,
-               "f5bb94e067ef6eb1e9ebc52f2e51d81945ea9c81c13c22367e276f73a5bd18bb"),
+                        "69c0a7de96db82fb70b0a3dd68a1196e0cc4cc8b957a3c9966d13e64bee4e6ad"),
+    "render": (11344.3 * 2.0 * 1024 + 8400.0 * 1024,
+               "69c0a7de96db82fb70b0a3dd68a1196e0cc4cc8b957a3c9966d13e64bee4e6ad"),
 }
 
 
