@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel source they were taken on (sha256 of rtg_kernels.hip).
 TRAFFIC = {
     "render_backward": (14164.1 * 2.0 * 1024 + 26269.2 * 1024,
-                        "69c0a7de96db82fb70b0a3dd68a1196e0cc4cc8b957a3c9966d13e64bee4e6ad"),
+                        "8688c1a69e5f0abad5b50452373e61095f5155f9e2f29d933a93c772b0acf344"),
     "render": (11344.3 * 2.0 * 1024 + 8400.0 * 1024,
-               "69c0a7de96db82fb70b0a3dd68a1196e0cc4cc8b957a3c9966d13e64bee4e6ad"),
+               "8688c1a69e5f0abad5b50452373e61095f5155f9e2f29d933a93c772b0acf344"),
 }
 
 

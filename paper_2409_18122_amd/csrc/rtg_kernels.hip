@@ -422,6 +422,9 @@ __device__ __forceinline__ uint32_t scan_in(const uint32_t* in, const uint32_t* 
     return gather ? in[gather[i]] : in[i];
 }
 
+// Multi-block exclusive scan of n = min(*n_dev, cap) items (n = cap when n_dev is
+// null), in[gather[i]] when gather is given: per-block totals here, then
+// k_scan_down.
 __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
                                                             const uint32_t* __restrict__ gather,
                                                             const uint32_t* __restrict__ n_dev,
