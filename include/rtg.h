@@ -350,13 +350,15 @@ rtg_status rtg_uncertainty_update(rtg_ctx *ctx, int64_t n, const float *means_pr
                                   const float *means_cur, const float *u_prev, int32_t squared,
                                   float *u_out, void *stream);
 
-/* Region grid of Sec. IV-C (host only): the box [lo, hi) (box = lo x, y, z,
- * hi x, y, z) is partitioned into cuboids of edge `size` (2.5 m in the
- * paper), dims[a] = ceil((hi_a - lo_a) / size).  RTG_ERR_INVALID for a
+/* Region grid of Sec. IV-B (high-level planner: the known enclosing space
+ * evenly partitioned into cuboids), host only: the box [lo, hi) (box = lo x,
+ * y, z, hi x, y, z) is partitioned into cuboids of edge `size` (2.5 m, set in
+ * Sec. IV-C), dims[a] = ceil((hi_a - lo_a) / size).  RTG_ERR_INVALID for a
  * non-positive size or extent. */
 rtg_status rtg_region_grid(const double *box, double size, int32_t *dims);
 
-/* Region utility of Sec. IV-C: for each cuboid region r = ix + nx (iy + ny iz)
+/* Region utility Omega_k of Sec. IV-B (high-level planner; region size from
+ * Sec. IV-C): for each cuboid region r = ix + nx (iy + ny iz)
  * of rtg_region_grid(box, size), count[r] = M = the number of Gaussians whose
  * mean lies in it (i = floor((mu_a - lo_a) / size) in binary64, half-open
  * cells; means outside the grid count nowhere), sum[r] = the sum of their u,
@@ -370,8 +372,8 @@ rtg_status rtg_region_utility(rtg_ctx *ctx, int64_t n, const float *means, const
                               const double *box, double size, int64_t *count, double *sum,
                               double *mean, void *stream);
 
-/* Collision check of Sec. IV-D: a Gaussian is treated as a sphere about its
- * mean of radius lambda_g r_i, r_i = exp(max of its three log-scales) (the
+/* Collision check of Sec. IV-B (trajectory planner, Collision Checking): a
+ * Gaussian is treated as a sphere about its mean of radius lambda_g r_i, r_i = exp(max of its three log-scales) (the
  * principal axis); a point sampled on a path collides when a sphere of radius
  * r_robot about it meets one of them:
  *   collide[j]   = 1 if ||p_j - mu_i||^2 < (r_robot + lambda_g r_i)^2 for

@@ -9,10 +9,12 @@ pixels); this module only marshals numpy arrays.  Float32 inputs are promoted
 exactly to float64.  See the C file's header for which passage of the paper
 each function follows.
 
-Functions: ``project``, ``render``, ``count``, ``keys``, ``loss``, ``score``,
-``adjoint``, ``thresholds``, ``view_utility``.  Parity status: every function here is pinned by the
-``-m "not gpu"`` tests (closed forms, invariants, brute force, finite
-differences); see tests/test_oracle_*.py.
+Functions: ``project``, ``render``, ``count``, ``keys``, ``loss``,
+``loss_ssim``, ``score``, ``adjoint``, ``thresholds``, ``view_utility``,
+``traj_select``, ``uncertainty_update``, ``region_utility``, ``collision``.
+Parity status: every function here is pinned by the ``-m "not gpu"`` tests
+(closed forms, invariants, brute force, finite differences); see
+tests/test_oracle_*.py.
 """
 from __future__ import annotations
 
@@ -82,6 +84,8 @@ def lib():
         L.rtgo_region_utility.restype = ctypes.c_int
         L.rtgo_collision.argtypes = [i64, p, p, i64, p, ctypes.c_double, ctypes.c_double, p, p]
         L.rtgo_collision.restype = None
+        L.rtgo_traj_select.argtypes = [ctypes.c_int, p, p, p]
+        L.rtgo_traj_select.restype = ctypes.c_int
         L.rtgo_set_threads.argtypes = [ctypes.c_int]
         L.rtgo_max_threads.restype = ctypes.c_int
         _lib = L
@@ -298,6 +302,19 @@ def view_utility(scene, cams, settings, lo, hi, range_=5.0, lam=1.0):
                             float(np.float32(range_)), float(lo), float(hi), float(lam),
                             _ptr(nh), _ptr(nl), _ptr(su), _ptr(xi))
     return nh, nl, su, xi
+
+
+def traj_select(xi, offsets):
+    """(utilities float64[n_traj], best index) of eq. (10): trajectory t sums
+    xi[offsets[t]:offsets[t+1]]; the first of the highest totals is chosen."""
+    x = _d(xi).reshape(-1)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1))
+    nt = off.size - 1
+    if nt < 1 or off[0] < 0 or off[-1] > x.size or np.any(np.diff(off) < 0):
+        raise ValueError("offsets must be non-decreasing within [0, len(xi)] with at least two entries")
+    util = np.zeros(nt)
+    best = lib().rtgo_traj_select(nt, _ptr(x), _ptr(off), _ptr(util))
+    return util, int(best)
 
 
 def uncertainty_update(means_prev, means_cur, u_prev, squared=False):

@@ -1265,8 +1265,30 @@ int rtgo_view_utility(int64_t n, const double *means, const double *u, const dou
     return 0;
 }
 
+/* Trajectory selection of Sec. IV-B eq. (10): trajectory t is evaluated by
+ * the sum of the view utilities xi of its states x_t(l tau / L), l = 0..L,
+ * which are xi[off[t]] .. xi[off[t+1] - 1] here (summed in that order), and
+ * the trajectory of highest total is chosen; among equal totals the first.
+ * util (nullable) receives every total.  Returns the chosen index, -1 when
+ * n_traj < 1. */
+int rtgo_traj_select(int n_traj, const double *xi, const int32_t *off, double *util)
+{
+    int best = -1;
+    double best_val = 0.0;
+    for (int t = 0; t < n_traj; t++) {
+        double total = 0.0;
+        for (int32_t l = off[t]; l < off[t + 1]; l++) total += xi[l];
+        if (util) util[t] = total;
+        if (best < 0 || total > best_val) {
+            best = t;
+            best_val = total;
+        }
+    }
+    return best;
+}
+
 /* ------------------------------------------------------------------------ */
-/* Uncertainty bookkeeping and region utility (Sec. IV-A, IV-C)             */
+/* Uncertainty bookkeeping and region utility (Sec. IV-A, IV-B, IV-C)      */
 /* ------------------------------------------------------------------------ */
 
 /* Per-Gaussian uncertainty after a map update: the magnitude of the change
@@ -1291,7 +1313,7 @@ void rtgo_uncertainty_update(int64_t n, const double *prev, const double *cur, c
     }
 }
 
-/* Grid of the region utility of Sec. IV-C: the enclosing box [lo, hi)
+/* Grid of the region utility of Sec. IV-B (size from Sec. IV-C): the enclosing box [lo, hi)
  * (box = lo xyz, hi xyz) is partitioned into cuboids of edge `size`,
  * dims[a] = ceil((hi_a - lo_a) / size) per axis. */
 int rtgo_region_grid(const double *box, double size, int *dims)
@@ -1305,7 +1327,8 @@ int rtgo_region_grid(const double *box, double size, int *dims)
     return 0;
 }
 
-/* Region utility of Sec. IV-C: region (ix, iy, iz), index ix + nx (iy + ny iz),
+/* Region utility Omega_k of Sec. IV-B (high-level planner; the 2.5 m size is
+ * set in Sec. IV-C): region (ix, iy, iz), index ix + nx (iy + ny iz),
  * holds the Gaussians whose mean lies in [lo + i size, lo + (i + 1) size) on
  * every axis (i = floor((mu_a - lo_a) / size) evaluated in binary64); means
  * outside the grid belong to no region.  count = M_k, sum = sum of u over the
@@ -1337,7 +1360,7 @@ int rtgo_region_utility(int64_t n, const double *means, const double *u, const d
 }
 
 /* ------------------------------------------------------------------------ */
-/* Collision checking (Sec. IV-D, Collision Checking)                       */
+/* Collision checking (Sec. IV-B, trajectory planner, Collision Checking)   */
 /* ------------------------------------------------------------------------ */
 
 /* Each test point is a sphere of radius r_robot; each Gaussian's radius is

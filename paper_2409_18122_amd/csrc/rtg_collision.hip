@@ -1,6 +1,6 @@
 // gfx950 (CDNA4) collision check of RT-GuIDE's trajectory planner (arXiv
-// 2409.18122, Sec. IV-D): points sampled on motion primitives against every
-// Gaussian of the map, each taken as a sphere of lambda_g times its principal
+// 2409.18122, Sec. IV-B, trajectory planner, Collision Checking paragraph):
+// points sampled on motion primitives against every Gaussian of the map, each taken as a sphere of lambda_g times its principal
 // axis.  Compiled without floating-point contraction, like the rasterizer.
 #include "rtg_internal.h"
 
@@ -20,8 +20,8 @@ inline unsigned grid_cap(uint64_t n, unsigned block, unsigned cap) {
     return (unsigned)g;
 }
 
-// Sec. IV-D: a sampled point (a sphere of radius r_robot) collides with a
-// Gaussian whose mean is closer than r_robot + lambda_g r, r = the Gaussian's
+// Sec. IV-B (trajectory planner, Collision Checking): a sampled point (a
+// sphere of radius r_robot) collides with a Gaussian whose mean is closer than r_robot + lambda_g r, r = the Gaussian's
 // principal axis exp(max log-scale).  Every point against every Gaussian:
 // a prep pass packs each Gaussian as (mu, w = lambda_g r) plus the squared
 // bound (r_robot + w)^2 widened down and up by a relative CC_BAND; the pair

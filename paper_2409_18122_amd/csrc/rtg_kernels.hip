@@ -2230,7 +2230,8 @@ __global__ __launch_bounds__(256) void k_uncertainty_update(int64_t n, const flo
 }
 
 // ---------------------------------------------------------- region utility
-// Sec. IV-C: cuboid regions of edge `size` over the box [lo, lo + dims size);
+// Sec. IV-B (high-level planner; the 2.5 m edge is set in Sec. IV-C): cuboid
+// regions of edge `size` over the box [lo, lo + dims size);
 // a Gaussian belongs to region (ix, iy, iz), index ix + nx (iy + ny iz), with
 // i = floor((mu - lo) / size) in binary64.  Counts are exact; sums are in
 // fixed point with 2^-32 resolution (|u| < 2^20 per value), so the result

@@ -1,5 +1,5 @@
 """GPU parity of the uncertainty bookkeeping (Sec. IV-A) and the region
-utility (Sec. IV-C) against the oracle, through the C ABI."""
+utility (Sec. IV-B, region size of Sec. IV-C) against the oracle, through the C ABI."""
 import numpy as np
 import pytest
 import torch

@@ -1,4 +1,4 @@
-"""GPU parity of the collision check (Sec. IV-D) against the oracle, through
+"""GPU parity of the collision check (Sec. IV-B, trajectory planner, Collision Checking) against the oracle, through
 the C ABI: flags bit-exact outside a 1e-12 relative tie band, clearance within
 the binary32 evaluation bound."""
 import numpy as np

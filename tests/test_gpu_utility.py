@@ -79,16 +79,18 @@ def test_view_utility_edges(raster, rctx):
 
 def test_trajectory_select(raster, rctx):
     rng = np.random.default_rng(2)
-    xi = rng.integers(-50, 50, 60).astype(np.float64)
     lens = rng.integers(1, 7, 12)
-    off = np.concatenate([[0], np.cumsum(lens)])
-    off[-1] = min(off[-1], 60)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    xi = rng.integers(-50, 50, int(off[-1])).astype(np.float64)
     util, best = raster.trajectory_select(rctx, torch.tensor(xi, device="cuda"), torch.tensor(off))
-    exp = []
-    for t in range(len(off) - 1):
-        s = 0.0
-        for k in range(off[t], off[t + 1]):
-            s += xi[k]
-        exp.append(s)
-    assert np.array_equal(util.cpu().numpy(), np.array(exp))
-    assert best.item() == int(np.argmax(exp))
+    exp, exp_best = oracle.traj_select(xi, off)
+    assert np.array_equal(util.cpu().numpy(), exp)
+    assert best.item() == exp_best
+    # non-integer utilities, summed in the same order on both sides, and ties
+    xr = rng.standard_normal(200)
+    xr[100:110] = xr[0:10]
+    offr = np.array([0, 10, 37, 100, 110, 150, 150, 200], np.int32)
+    util, best = raster.trajectory_select(rctx, torch.tensor(xr, device="cuda"), torch.tensor(offr))
+    exp, exp_best = oracle.traj_select(xr, offr)
+    assert np.array_equal(util.cpu().numpy(), exp)
+    assert best.item() == exp_best

@@ -1,6 +1,6 @@
 """Pins of the oracle's uncertainty bookkeeping (Sec. IV-A: the uncertainty
 of a Gaussian is the magnitude of the change of its mean, kept when the mean
-does not change) and region utility (Sec. IV-C: mean uncertainty over
+does not change) and region utility (Sec. IV-B, size of Sec. IV-C: mean uncertainty over
 cuboidal regions of the enclosing space)."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Pins of the oracle's collision test (Sec. IV-D, Collision Checking): a
+"""Pins of the oracle's collision test (Sec. IV-B, trajectory planner, Collision Checking): a
 sampled point of radius r_robot collides with a Gaussian whose mean is
 closer than r_robot + lambda_g r, r = the Gaussian's principal axis."""
 import math

@@ -146,6 +146,70 @@ def test_camera_pose_convention():
     assert b["depth"][0] == pytest.approx(2.7, rel=1e-6)
 
 
+def test_rotated_anisotropic_on_axis_closed_form():
+    # An on-axis Gaussian with s_x != s_y, rotated by +theta about the optical
+    # axis (right-hand rule: its first axis turns towards the camera's +y,
+    # i.e. down the image): Sigma = R_z(theta) diag(s^2) R_z(theta)^T, and with
+    # J = diag(fx, fy) / z on the axis the 2D covariance is
+    #   xx = (fx/z)^2 (sx^2 cos^2 + sy^2 sin^2), yy = (fy/z)^2 (sx^2 sin^2 + sy^2 cos^2),
+    #   xy = (fx fy / z^2) (sx^2 - sy^2) sin cos.
+    # The sign of xy fixes the orientation of the quaternion's rotation.
+    c = cam(fx=60.0, fy=45.0)
+    fx, fy = c["fx"], c["fy"]
+    ls = (-1.2, -2.4, -1.8)
+    sx, sy = math.exp(ls[0]), math.exp(ls[1])
+    z = 3.0
+    for deg in (30.0, -30.0, 75.0, 120.0):
+        th = math.radians(deg)
+        q = (math.cos(th / 2), 0.0, 0.0, math.sin(th / 2))
+        p = oracle.project(one_gaussian((0, 0, z), ls, q), c, S())
+        cs, sn = math.cos(th), math.sin(th)
+        xx = (fx / z) ** 2 * (sx * sx * cs * cs + sy * sy * sn * sn)
+        yy = (fy / z) ** 2 * (sx * sx * sn * sn + sy * sy * cs * cs)
+        xy = fx * fy / z ** 2 * (sx * sx - sy * sy) * sn * cs
+        np.testing.assert_allclose(p["cov2d"][:, 0], [xx, xy, yy], rtol=1e-12, atol=1e-12)
+        # +30 degrees with s_x > s_y: the long axis runs right-down (xy > 0)
+        if deg == 30.0:
+            assert p["cov2d"][1, 0] > 0.0
+
+
+def test_rotated_camera_equivalence_anisotropic():
+    # A Gaussian at p with rotation q seen by the identity camera must project
+    # exactly as the Gaussian at R p + T with rotation q_R * q (R applied after
+    # q) seen by the camera with pose (R, T), R = rotation of q_R.  Rotations
+    # and their composition come from scipy, not from the oracle's formulas; a
+    # transposed Gaussian rotation or a transposed camera rotation (R Sigma R^T
+    # in place of R^T Sigma R) breaks the equality.
+    from scipy.spatial.transform import Rotation
+
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        qg = rng.standard_normal(4)
+        qg /= np.linalg.norm(qg)                      # w, x, y, z
+        rot_g = Rotation.from_quat([qg[1], qg[2], qg[3], qg[0]])
+        rot_c = Rotation.from_quat(rng.standard_normal(4))
+        T = rng.standard_normal(3)
+        # the camera stores R and T in binary32: use that exact pose, and
+        # build the world rotation from it so that both sides share it
+        c1 = cam(R=rot_c.as_matrix(), T=T)
+        R32 = c1["R"].astype(np.float64).reshape(3, 3)
+        T32 = c1["T"].astype(np.float64)
+        rot_c32 = Rotation.from_matrix(R32)
+        comp = (rot_c32 * rot_g).as_quat()            # x, y, z, w
+        q_world = (comp[3], comp[0], comp[1], comp[2])
+        p_cam = np.array([0.35, -0.25, 2.6]) + 0.1 * rng.standard_normal(3)
+        ls = (-1.3, -2.6, -1.9)
+        a = oracle.project(one_gaussian(p_cam, ls, tuple(qg)), cam(), S())
+        b = oracle.project(one_gaussian(R32 @ p_cam + T32, ls, q_world), c1, S())
+        assert a["valid"][0] and b["valid"][0]
+        # R32 is orthogonal to ~1e-7 (binary32 rounding of a rotation)
+        np.testing.assert_allclose(b["mean2d"], a["mean2d"], rtol=2e-6)
+        np.testing.assert_allclose(b["cov2d"], a["cov2d"], rtol=2e-5, atol=2e-5 * np.abs(a["cov2d"]).max())
+        # the off-diagonal term is not small here, so its sign is tested too
+        assert abs(a["cov2d"][1, 0]) > 0.05 * math.sqrt(a["cov2d"][0, 0] * a["cov2d"][2, 0])
+        assert np.sign(b["cov2d"][1, 0]) == np.sign(a["cov2d"][1, 0])
+
+
 def test_depth_bits_are_binary32_of_depth():
     g, cams = scenes.config1(n=300)
     p = oracle.project(g, cams[0], S())

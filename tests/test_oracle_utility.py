@@ -87,3 +87,51 @@ def test_pose_convention_for_visibility():
     b = oracle.view_utility(points(w, u), [c1], S(), 0.4, 0.6)
     # the same points seen from the same relative pose (up to rounding at the borders)
     assert abs(int(a[0][0]) - int(b[0][0])) <= 1 and abs(int(a[1][0]) - int(b[1][0])) <= 1
+
+
+# --------------------------------------------------------------------------
+# Trajectory selection, Sec. IV-B eq. (10): argmax over trajectories of the
+# sum of xi over the trajectory's L + 1 states.
+# --------------------------------------------------------------------------
+
+def test_traj_select_hand_example():
+    # three trajectories of 3, 2 and 4 states
+    xi = [4.0, -1.0, 2.0,   7.0, -2.0,   1.0, 1.0, 1.0, 1.0]
+    off = [0, 3, 5, 9]
+    util, best = oracle.traj_select(xi, off)
+    assert util.tolist() == [5.0, 5.0, 4.0]
+    # equal totals: the first trajectory is kept
+    assert best == 0
+    util, best = oracle.traj_select(xi[:8] + [3.0], off)
+    assert util.tolist() == [5.0, 5.0, 6.0] and best == 2
+
+
+def test_traj_select_single_states_and_empty():
+    xi = [0.5, -3.0, 2.5, 2.5]
+    util, best = oracle.traj_select(xi, [0, 1, 2, 3, 4])
+    assert util.tolist() == xi and best == 2
+    # a trajectory with no states has utility 0
+    util, best = oracle.traj_select([-1.0, -2.0], [0, 1, 1, 2])
+    assert util.tolist() == [-1.0, 0.0, -2.0] and best == 1
+
+
+def test_traj_select_brute_force_integers():
+    # integer utilities: every partial sum is exact, so the totals and the
+    # choice equal a brute-force evaluation exactly
+    rng = np.random.default_rng(8)
+    for trial in range(20):
+        n_traj = int(rng.integers(1, 12))
+        lens = rng.integers(0, 9, n_traj)
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+        xi = rng.integers(-1000, 1000, int(off[-1])).astype(np.float64)
+        util, best = oracle.traj_select(xi, off)
+        ref = [sum(int(v) for v in xi[off[t]:off[t + 1]]) for t in range(n_traj)]
+        assert util.tolist() == [float(r) for r in ref]
+        top = max(ref)
+        assert best == ref.index(top)
+        # relabelling the trajectories permutes the totals
+        perm = rng.permutation(n_traj)
+        xi2 = np.concatenate([xi[off[t]:off[t + 1]] for t in perm]) if off[-1] else xi
+        off2 = np.concatenate([[0], np.cumsum(lens[perm])]).astype(np.int32)
+        util2, _ = oracle.traj_select(xi2, off2)
+        assert util2.tolist() == [util[t] for t in perm]
