@@ -41,6 +41,9 @@ typedef int32_t rtg_status;
 #define RTG_ERR_INVALID (-1)     /* bad argument (null pointer, size, tile, NaN camera) */
 #define RTG_ERR_HIP (-2)         /* a HIP runtime call failed (message has the code) */
 #define RTG_ERR_CAPACITY (-3)    /* a fixed-capacity buffer overflowed (graph replay) */
+/* RTG_ERR_UNSUPPORTED is also returned when a frame would hold 2^31 or more
+ * records (view-Gaussian pairs) or (tile, Gaussian) pairs: list offsets are
+ * 32-bit, and the count scans detect the carry in 64 bits. */
 #define RTG_ERR_OOM (-4)         /* device allocation failed */
 #define RTG_ERR_UNSUPPORTED (-5) /* request outside what this build supports */
 
@@ -144,7 +147,8 @@ rtg_status rtg_set_allocator(rtg_ctx *ctx, rtg_alloc_fn alloc, rtg_free_fn free,
  * references g's arrays: they must stay valid and unchanged until the frame
  * is destroyed.  Images of several views are packed view after view (see
  * rtg_render).  n_views in [1, 1024].  Synchronises `stream` once (to size
- * the record buffer). */
+ * the record buffer).  RTG_ERR_UNSUPPORTED when the records number 2^31 or
+ * more (nothing is allocated for them). */
 rtg_status rtg_project(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                        int32_t n_views, const rtg_settings *settings, rtg_frame **out,
                        void *stream);
@@ -159,7 +163,8 @@ rtg_status rtg_project(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *c
  * subset of the tiles its pixel box meets, and at least one tile per visible
  * Gaussian.  *n_instances (host, nullable)
  * receives the number of (tile, Gaussian) pairs.  Synchronises `stream`
- * once (to size the pair buffers). */
+ * once (to size the pair buffers).  RTG_ERR_UNSUPPORTED when the pairs
+ * number 2^31 or more (nothing is allocated for them). */
 rtg_status rtg_bin_sort(rtg_ctx *ctx, rtg_frame *f, int64_t *n_instances, void *stream);
 
 /* Forward compositing (Sec. III: C(p) = sum_i c_i a_i prod_{j<i} (1 - a_j),
@@ -219,6 +224,25 @@ void rtg_frame_destroy(rtg_frame *f);
 rtg_status rtg_frame_export(rtg_ctx *ctx, rtg_frame *f, uint64_t *keys, uint32_t *vals,
                             uint32_t *ranges, void *stream);
 
+/* Copies the frame's projected records (Sec. III projection: one per visible
+ * (view, Gaussian) pair, Gaussian-major, views ascending within a Gaussian)
+ * to caller DEVICE buffers, for inspection and key parity; any pointer may be
+ * NULL.  R = rtg_frame_info()[0]; arrays are planar:
+ *   mean2d: 2 x R doubles, mu_2D = (fx t_x / d + cx, fy t_y / d + cy), held by
+ *     the kernels as the sum of two binary32 values (about 48 bits);
+ *   conic: 3 x R doubles, Sigma_2D^-1 entries (xx, xy, yy), binary64;
+ *   pbox: 4 x R int32, (u0, u1, v0, v1): the inclusive pixel box of
+ *     {alpha >= alpha_min}, u0 = ceil(mu_x - h_x), u1 = floor(mu_x + h_x)
+ *     clipped to the image, h_x = sqrt(2 ln(o / alpha_min) Sigma_xx), and
+ *     the same in y;
+ *   depth_bits: R uint32, bits of the binary32 camera depth (the sort key);
+ *   gid, view: R uint32, Gaussian and view index;
+ *   ntiles: R uint32, (tile, Gaussian) pairs of the record.
+ * Asynchronous on `stream`. */
+rtg_status rtg_frame_export_records(rtg_ctx *ctx, rtg_frame *f, double *mean2d, double *conic,
+                                    int32_t *pbox, uint32_t *depth_bits, uint32_t *gid,
+                                    uint32_t *view, uint32_t *ntiles, void *stream);
+
 /* Host-side sizes of a frame: [0] records (visible view-Gaussian pairs),
  * [1] instances (tile-Gaussian pairs, -1 before rtg_bin_sort), [2] total
  * tiles, [3] total pixels, [4] tile_w, [5] tile_h. */
@@ -235,7 +259,8 @@ rtg_status rtg_frame_info(const rtg_frame *f, int64_t info[6]);
  * through one projection, one sort and one persistent compositing launch;
  * persistent = 0: a plain loop of per-view launches (for comparison).
  * Results are identical either way.  A mode other than 0 or 1 is
- * RTG_ERR_INVALID.  Synchronises `stream` to size buffers. */
+ * RTG_ERR_INVALID.  Synchronises `stream` to size buffers.  A view whose
+ * binning reported an internal inconsistency gets a NaN score. */
 rtg_status rtg_score_views(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                            int32_t n_views, const rtg_settings *settings, double *scores,
                            int32_t persistent, int32_t mode, void *stream);
@@ -250,9 +275,15 @@ rtg_status rtg_score_views(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camer
  * by an eager pass over the n_probe `probe` cameras, scaled to max_views
  * (probe must then be non-NULL).  launch: uploads cams (host, n_views <=
  * max_views, each within the size limits), replays the graph on `stream` and
- * copies the n_views scores to the device array `scores`.  status: waits for
- * the last replay and returns RTG_ERR_CAPACITY if a buffer overflowed during
- * it (its scores are then invalid; create a graph with larger capacity). */
+ * copies the n_views scores to the device array `scores`.  A replay whose
+ * buffers overflow writes NaN scores, and the overflow is sticky: the graph
+ * keeps reporting it until destroyed.  launch never waits for a running
+ * replay (it waits only for the one before the previous, whose pinned
+ * camera area it reuses) and returns RTG_ERR_CAPACITY, without replaying,
+ * once an earlier replay's overflow has reached the host (an overflow of
+ * 2^31 or more pairs is RTG_ERR_UNSUPPORTED); create a graph with larger
+ * capacity then.  status: waits for the last replay and returns the same
+ * codes, so it also reports an overflow of that last replay. */
 rtg_status rtg_score_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, int32_t max_views,
                                   int32_t max_width, int32_t max_height,
                                   const rtg_settings *settings, int32_t mode,
@@ -268,9 +299,12 @@ rtg_status rtg_score_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, int32_t 
  * targets, the outputs and the gradient arrays are captured by address: they
  * must stay allocated, and the map may be updated in place between replays.
  * Buffer capacities are 1.5x the counts of an eager pass at creation (or
- * settings->max_instances pairs when > 0);
- * rtg_map_graph_status reports RTG_ERR_CAPACITY if a later replay overflowed
- * (its outputs are then invalid and nothing was added to the gradients). */
+ * settings->max_instances pairs when > 0).  A replay that overflows them
+ * leaves its outputs invalid and adds nothing to the gradients, and so does
+ * every later replay (the overflow is sticky); rtg_map_graph_launch returns
+ * RTG_ERR_CAPACITY without replaying once an overflow has reached the host
+ * (it never waits), and rtg_map_graph_status waits for the last replay and
+ * reports it. */
 rtg_status rtg_map_graph_create(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                                 int32_t n_views, const rtg_settings *settings,
                                 const float *target_rgb, const float *target_depth, float w_depth,
@@ -396,7 +430,9 @@ rtg_status rtg_collision_check(rtg_ctx *ctx, const rtg_gaussians *g, const float
  *   (tile-Gaussian pairs), out[2] contributing pixel-Gaussian pairs (terms of
  *   the compositing sums of Sec. III over all pixels), out[3] splat list
  *   entries walked by the backward (sum over pixels of the position after the
- *   last contributor).  Requires rtg_render. */
+ *   last contributor).  Requires rtg_render.  Also reports a binning
+ *   inconsistency found after rtg_bin_sort returned (RTG_ERR_HIP; the
+ *   frame's images are then unwritten). */
 rtg_status rtg_frame_stats(rtg_ctx *ctx, rtg_frame *f, int64_t out[4], void *stream);
 
 /* Kernel timing for measurement: while enabled, the library brackets its

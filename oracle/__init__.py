@@ -30,8 +30,18 @@ _LIB = os.path.join(_HERE, "librtgo.so")
 
 # Relative widths of the near-threshold bands: a per-pixel decision whose
 # operand lies this close (relative) to its threshold is taken both ways by the
-# oracle, since a binary32 evaluation may legitimately fall on either side.
-EV_ALPHA = 1e-4
+# oracle, since another evaluation may legitimately fall on either side.
+#  * alpha_min: the HIP path re-takes every decision within 2e-3 of alpha_min
+#    in binary64 from the binary64 conic and a mean exact to ~2^-48, so only
+#    binary64 rounding-order differences (~1e-11 relative) separate the two:
+#    1e-5 covers them with a wide margin;
+#  * T_min: the HIP path decides it in binary32.  After the contributors of a
+#    pixel, binary32 T differs from binary64 by at most
+#    sum_i [2^-24 + eps_a a_i / (1 - a_i)] relative (eps_a ~ 2.4e-7, the
+#    relative error of binary32 alpha); with T >= T_min = 1e-4 at the stop
+#    and a_i <= 0.99 this stays below 7e-5 (two clamped splats give 5e-5,
+#    300 roundings 1.8e-5), so the band is 1e-4.
+EV_ALPHA = 1e-5
 EV_T = 1e-4
 
 
@@ -70,7 +80,7 @@ def lib():
         L.rtgo_loss_ssim.restype = ctypes.c_double
         L.rtgo_score.argtypes = [i64] + [p] * 7 + [ctypes.c_int, p, ctypes.c_int, ctypes.c_int, ctypes.c_int, p]
         L.rtgo_score.restype = ctypes.c_int
-        L.rtgo_adjoint.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 2 + [p] * 10)
+        L.rtgo_adjoint.argtypes = ([i64] + [p] * 8 + [ctypes.c_int] * 2 + [p] * 11 + [ctypes.c_double] * 2)
         L.rtgo_adjoint.restype = ctypes.c_int
         L.rtgo_thresholds.argtypes = [i64, p, ctypes.c_double, p, p]
         L.rtgo_thresholds.restype = None
@@ -263,22 +273,28 @@ def score(scene, cams, settings, tile=(16, 16), mode=0):
 def adjoint(scene, cam, settings, g_rgb=None, g_depth=None, g_alpha=None, g_unc=None,
             tile=(16, 16), want_2d=False):
     """Gradient of sum_p <g_img(p), image(p)> for one camera with respect to
-    means (3,N), log_scales (3,N), quats (4,N), opacity (N,), colors (3,N)."""
+    means (3,N), log_scales (3,N), quats (4,N), opacity (N,), colors (3,N).
+    out["touched"] (N,) bool marks the Gaussians that may contribute at a
+    pixel holding a near-threshold decision (their gradient may legitimately
+    follow another decision set)."""
     g = _G(scene)
     n = g.n
     out = {"means": np.zeros((3, n)), "log_scales": np.zeros((3, n)),
            "quats": np.zeros((4, n)), "opacity": np.zeros(n), "colors": np.zeros((3, n))}
     g2d = np.zeros((n, 10)) if want_2d else None
+    touched = np.zeros(n, np.int32)
     planes = [None if a is None else _d(a) for a in (g_rgb, g_depth, g_alpha, g_unc)]
     ca, sa = cam_array(cam), set_array(settings)
     rc = lib().rtgo_adjoint(n, *g.all(), _ptr(ca), _ptr(sa), int(tile[0]), int(tile[1]),
                             *[_ptr(a) for a in planes],
                             _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
-                            _ptr(out["opacity"]), _ptr(out["colors"]), _ptr(g2d))
+                            _ptr(out["opacity"]), _ptr(out["colors"]), _ptr(g2d), _ptr(touched),
+                            float(EV_ALPHA), float(EV_T))
     if rc:
         raise MemoryError("oracle adjoint failed")
     if want_2d:
         out["screen"] = g2d
+    out["touched"] = touched.astype(bool)
     return out
 
 

@@ -930,21 +930,28 @@ typedef struct {
 } ocontrib;
 
 /* Reverse mode of one pixel given upstream gradients g[6] for r, g, b,
- * depth, alpha, uncertainty.  acc2d is indexed by Gaussian. */
+ * depth, alpha, uncertainty.  acc2d is indexed by Gaussian.  When touched is
+ * not NULL and the pixel holds a near-threshold decision (the event bands of
+ * the forward pass), every candidate whose alpha at the pixel reaches the
+ * lower edge of the alpha_min band is marked in touched[]: the gradient of
+ * each such Gaussian may legitimately follow another decision set there. */
 static void pixel_adjoint(const oview *V, const int64_t *list, int64_t len, int u, int v,
-                          const double g6[6], double *acc2d, ocontrib *buf)
+                          const double g6[6], double *acc2d, ocontrib *buf, int32_t *touched)
 {
     const double *col = V->g.colors, *unc = V->g.uncert;
     int64_t N = V->g.n;
     double T = 1.0;
     int64_t m = 0;
+    int event = 0;
     for (int64_t k = 0; k < len; k++) {
         int64_t i = list[k];
         double a, G, dx, dy;
         int cl;
         alpha_at(V, i, (double)u, (double)v, &a, &G, &cl, &dx, &dy);
+        if (fabs(a - V->s.alpha_min) <= V->ev_a * V->s.alpha_min) event = 1;
         if (a < V->s.alpha_min) continue;
         double Tn = T * (1.0 - a);
+        if (fabs(Tn - V->s.T_min) <= V->ev_t * V->s.T_min) event = 1;
         if (Tn < V->s.T_min) break;
         buf[m].pos = i;
         buf[m].alpha = a;
@@ -955,6 +962,18 @@ static void pixel_adjoint(const oview *V, const int64_t *list, int64_t len, int 
         buf[m].dy = dy;
         m++;
         T = Tn;
+    }
+    if (event && touched) {
+        for (int64_t k = 0; k < len; k++) {
+            int64_t i = list[k];
+            double a, G, dx, dy;
+            int cl;
+            alpha_at(V, i, (double)u, (double)v, &a, &G, &cl, &dx, &dy);
+            if (a >= V->s.alpha_min * (1.0 - V->ev_a)) {
+#pragma omp atomic write
+                touched[i] = 1;
+            }
+        }
     }
     /* suffix sums S_ch = sum_{j > i} v_j w_j */
     double S[6] = {0, 0, 0, 0, 0, 0};
@@ -1132,18 +1151,23 @@ static void project_adjoint(const oview *V, int64_t i, const double *G2,
 /* Gradient of sum_p sum_ch gimg_ch(p) * image_ch(p) for one camera, added
  * into gm (3N), gls (3N), gq (4N), go (N), gc (3N).  gimg: planar
  * r, g, b, depth, alpha, uncertainty (6 x H x W); a NULL plane means zero.
- * Optional g2d (N x 10) receives the screen-space gradients. */
+ * Optional g2d (N x 10) receives the screen-space gradients; optional
+ * touched (N) is set to 1 for the Gaussians that may contribute at a pixel
+ * holding a near-threshold decision, i.e. within the relative bands ev_a of
+ * alpha_min or ev_t of T_min (never cleared here). */
 int rtgo_adjoint(int64_t n, const double *means, const double *ls, const double *q,
                  const double *o, const double *colors, const double *unc,
                  const double *cam, const double *set, int tw, int th,
                  const double *g_rgb, const double *g_depth, const double *g_alpha,
                  const double *g_unc, double *gm, double *gls, double *gq, double *go,
-                 double *gc, double *g2d)
+                 double *gc, double *g2d, int32_t *touched, double ev_a, double ev_t)
 {
     ogauss g;
     gauss_from(&g, n, means, ls, q, o, colors, unc);
     oview V;
     if (view_setup(&V, &g, cam, set)) return -1;
+    V.ev_a = ev_a;
+    V.ev_t = ev_t;
     otiles T;
     if (tiles_build(&V, tw, th, &T)) return -1;
     int W = V.c.w, H = V.c.h;
@@ -1179,7 +1203,7 @@ int rtgo_adjoint(int64_t n, const double *means, const double *ls, const double 
             if (g6[0] == 0.0 && g6[1] == 0.0 && g6[2] == 0.0 && g6[3] == 0.0 && g6[4] == 0.0 && g6[5] == 0.0)
                 continue;
             int64_t t = (int64_t)(v / th) * T.ntx + u / tw;
-            pixel_adjoint(&V, T.items + T.start[t], T.start[t + 1] - T.start[t], u, v, g6, mine, buf);
+            pixel_adjoint(&V, T.items + T.start[t], T.start[t + 1] - T.start[t], u, v, g6, mine, buf, touched);
         }
         free(buf);
     }

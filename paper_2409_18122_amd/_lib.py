@@ -63,6 +63,7 @@ SIGNATURES = {
     "rtg_render_backward": (i32, [vp, vp, vp, vp, vp, vp, _c.POINTER(Grads), vp]),
     "rtg_frame_destroy": (None, [vp]),
     "rtg_frame_export": (i32, [vp, vp, vp, vp, vp, vp]),
+    "rtg_frame_export_records": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "rtg_frame_info": (i32, [vp, _c.POINTER(i64)]),
     "rtg_score_views": (i32, [vp, _c.POINTER(Gaussians), _c.POINTER(Camera), i32, _c.POINTER(Settings),
                               vp, i32, i32, vp]),

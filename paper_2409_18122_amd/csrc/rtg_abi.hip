@@ -378,11 +378,21 @@ struct rtg_frame {
 
 namespace {
 
+rtg_status flags_status(uint32_t flags) {
+    if (flags & FLAG_COUNT_OVERFLOW)
+        return set_err(RTG_ERR_UNSUPPORTED, "2^31 or more records or pairs: the 32-bit list offsets cannot hold them");
+    if (flags & (FLAG_REC_OVERFLOW | FLAG_INST_OVERFLOW))
+        return set_err(RTG_ERR_CAPACITY, "buffers overflowed (flags 0x%x)", flags);
+    if (flags) return set_err(RTG_ERR_HIP, "pair emission disagreed with the pair count (flags 0x%x)", flags);
+    return RTG_OK;
+}
+
+// Reads the device counters (a synchronisation point) and reports any flag.
 rtg_status read_counter(rtg_ctx* ctx, const uint32_t* dev, uint32_t* host, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(ctx->pinned, dev, sizeof(uint32_t) * C_COUNT, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(host, ctx->pinned, sizeof(uint32_t) * C_COUNT);
-    return RTG_OK;
+    return flags_status(host[C_FLAGS]);
 }
 
 // Allocates the view-side and per-Gaussian buffers of a frame and uploads
@@ -453,11 +463,14 @@ rtg_status enqueue_project(rtg_frame* f, bool eager, hipStream_t s) {
     const Header* hdr = f->hdr.as<Header>();
     uint32_t n = (uint32_t)f->g.n;
     Timer tm(f->ctx, 0, s);
-    fill_u32(f->ctr(0), 0u, C_COUNT, s);
+    // a captured graph keeps its flags word across replays (an overflow stays
+    // reported until the graph is destroyed); an eager frame starts clean
+    if (eager) fill_u32(f->ctr(0), 0u, C_COUNT, s);
+    else fill_u32(f->ctr(0), 0u, C_FLAGS, s);  // records and pairs counters
     fill_u32(f->ctr(C_NG), n, 1, s);
     project_count(gd, views, hdr, f->views_cap, sd, f->cnt.as<uint32_t>(), f->mask.as<uint32_t>(), s);
     scan_u32(f->cnt.as<uint32_t>(), nullptr, f->rec_off.as<uint32_t>(), f->ctr(C_NG), std::max<uint32_t>(n, 1),
-             f->ctr(C_REC), ScanWs{f->scan_ws.as<uint32_t>()}, s);
+             f->ctr(C_REC), f->ctr(C_FLAGS), ScanWs{f->scan_ws.as<uint32_t>()}, s);
     RTG_TRY(check_launch("projection count"));
     if (eager) {
         uint32_t c[C_COUNT];
@@ -493,7 +506,7 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
                                      f->order2.as<uint32_t>(), f->ctr(C_REC), rc, 32, DEPTH_SORT_DIGIT, ws, s);
     }
     scan_u32(f->ntiles.as<uint32_t>(), f->sorted_order(), f->inst_off.as<uint32_t>(), f->ctr(C_REC), rc,
-             f->ctr(C_INST), ScanWs{f->scan_ws.as<uint32_t>()}, s);
+             f->ctr(C_INST), f->ctr(C_FLAGS), ScanWs{f->scan_ws.as<uint32_t>()}, s);
     RTG_TRY(check_launch("depth sort"));
     if (eager) {
         uint32_t c[C_COUNT];
@@ -663,7 +676,7 @@ rtg_status rtg_render(rtg_ctx* ctx, rtg_frame* f, float* rgb, float* depth, floa
     Timer tm(ctx, 3, s);
     render_forward(f->st.tile_w, f->st.tile_h, f->st.batch, f->views.as<ViewDev>(), f->n_views,
                    f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st), o,
-                   nullptr, s);
+                   f->ctr(C_FLAGS), s);
     RTG_TRY(check_launch("render"));
     f->rendered = true;
     return RTG_OK;
@@ -726,13 +739,13 @@ rtg_status rtg_render_backward(rtg_ctx* ctx, rtg_frame* f, const float* d_rgb, c
     render_backward(f->st.tile_w, f->st.tile_h, f->st.batch, f->views.as<ViewDev>(), f->n_views,
                     f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
                     f->T_final.as<float>(), f->n_last.as<uint32_t>(), d_rgb, d_depth, d_alpha, d_unc,
-                    f->g2d.as<double>(), nullptr, s);
+                    f->g2d.as<double>(), f->ctr(C_FLAGS), s);
     }
     RTG_TRY(check_launch("render backward"));
     Timer tm(ctx, 6, s);
     project_backward(to_dev(f->g), f->views.as<ViewDev>(), to_dev(f->st), f->rec_off.as<uint32_t>(),
                      f->cnt.as<uint32_t>(), f->view.as<uint32_t>(), f->g2d.as<double>(), out->d_means,
-                     out->d_log_scales, out->d_quats, out->d_opacity, out->d_colors, nullptr, s);
+                     out->d_log_scales, out->d_quats, out->d_opacity, out->d_colors, f->ctr(C_FLAGS), s);
     return check_launch("projection backward");
 }
 
@@ -751,6 +764,17 @@ rtg_status rtg_frame_export(rtg_ctx* ctx, rtg_frame* f, uint64_t* keys, uint32_t
     return check_launch("export");
 }
 
+rtg_status rtg_frame_export_records(rtg_ctx* ctx, rtg_frame* f, double* mean2d, double* conic, int32_t* pbox,
+                                    uint32_t* depth_bits, uint32_t* gid, uint32_t* view, uint32_t* ntiles,
+                                    void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    if (!f) return set_err(RTG_ERR_INVALID, "frame is NULL");
+    if (f->R == 0) return RTG_OK;
+    export_records(f->ctr(C_REC), f->rec_cap, f->records(), mean2d, conic, pbox, depth_bits, gid, view, ntiles,
+                   (hipStream_t)stream);
+    return check_launch("export records");
+}
+
 rtg_status rtg_frame_stats(rtg_ctx* ctx, rtg_frame* f, int64_t out[4], void* stream) {
     RTG_TRY(ctx_ok(ctx));
     if (!f || !out) return set_err(RTG_ERR_INVALID, "frame or out is NULL");
@@ -763,8 +787,10 @@ rtg_status rtg_frame_stats(rtg_ctx* ctx, rtg_frame* f, int64_t out[4], void* str
     RTG_TRY(check_launch("frame stats"));
     unsigned long long h[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(ctx->pinned, f->stats.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->pinned + 4, f->ctr(C_FLAGS), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(h, ctx->pinned, sizeof(h));
+    RTG_TRY(flags_status(ctx->pinned[4]));
     out[0] = f->R;
     out[1] = f->K;
     out[2] = (int64_t)h[0];
@@ -829,7 +855,8 @@ rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera*
     score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, mode, true, grid, f->views.as<ViewDev>(), f->n_views,
                 f->hdr.as<Header>(), 0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(),
                 to_dev(f->st), f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
-    score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), n_views, f->score_part.as<double>(), scores, s);
+    score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), n_views, f->score_part.as<double>(), scores,
+                 f->ctr(C_FLAGS), s);
     return check_launch("persistent scoring");
 }
 
@@ -847,7 +874,8 @@ rtg_status score_plain(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* c
                     f->hdr.as<Header>(),
                     0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
                     f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
-        score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), 1, f->score_part.as<double>(), scores + v, s);
+        score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), 1, f->score_part.as<double>(), scores + v,
+                     f->ctr(C_FLAGS), s);
         RTG_TRY(check_launch("plain scoring"));
     }
     return RTG_OK;
@@ -878,15 +906,21 @@ struct rtg_graph {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t done = nullptr;
-    ViewDev* staging = nullptr;  // pinned
-    Header* staging_hdr = nullptr;
-    uint32_t* flag_host = nullptr;  // pinned, written by the graph
+    // Two camera staging slots, so that a launch waits only for the replay
+    // before the previous one (which has normally finished) before it
+    // rewrites a slot; done[k] completes with the last replay that used slot k.
+    static constexpr int SLOTS = 2;
+    hipEvent_t done[SLOTS] = {nullptr, nullptr};
+    ViewDev* staging[SLOTS] = {nullptr, nullptr};  // pinned
+    Header* staging_hdr[SLOTS] = {nullptr, nullptr};
+    uint32_t* flag_host = nullptr;  // pinned, written at the end of every replay
     Buf scores;
     int grid = 0;
     int mode = 0;  // scoring: 0 rendered proxy, 1 binary-J trace
     int last_views = 0;
+    int64_t launches = 0;
     bool launched = false;
+    int last_slot() const { return (int)((launches - 1) % SLOTS); }
 };
 
 namespace {
@@ -894,15 +928,54 @@ namespace {
 void graph_free(rtg_graph* gr) {
     if (!gr) return;
     (void)hipSetDevice(gr->ctx->device);
-    if (gr->done) (void)hipEventSynchronize(gr->done);
+    for (int k = 0; k < rtg_graph::SLOTS; k++)
+        if (gr->done[k]) (void)hipEventSynchronize(gr->done[k]);
     if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
     if (gr->cap_stream) (void)hipStreamDestroy(gr->cap_stream);
-    if (gr->done) (void)hipEventDestroy(gr->done);
-    if (gr->staging) (void)hipHostFree(gr->staging);
-    if (gr->staging_hdr) (void)hipHostFree(gr->staging_hdr);
+    for (int k = 0; k < rtg_graph::SLOTS; k++) {
+        if (gr->done[k]) (void)hipEventDestroy(gr->done[k]);
+        if (gr->staging[k]) (void)hipHostFree(gr->staging[k]);
+        if (gr->staging_hdr[k]) (void)hipHostFree(gr->staging_hdr[k]);
+    }
     if (gr->flag_host) (void)hipHostFree(gr->flag_host);
     delete gr;
+}
+
+// Pinned flag word, events and the capture stream of a graph; the device
+// flags word starts clear and is never cleared by a replay.
+rtg_status graph_host_setup(rtg_graph* gr, bool staging, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const int max_views = std::max(gr->max_views, 1);
+    for (int k = 0; k < rtg_graph::SLOTS && e == hipSuccess; k++) {
+        if (staging) {
+            e = hipHostMalloc((void**)&gr->staging[k], sizeof(ViewDev) * max_views, hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void**)&gr->staging_hdr[k], sizeof(Header), hipHostMallocDefault);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&gr->done[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void**)&gr->flag_host, sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&gr->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return set_err(RTG_ERR_HIP, "graph setup failed: %s", hipGetErrorString(e));
+    *gr->flag_host = 0;
+    fill_u32(gr->f->ctr(0), 0u, C_COUNT, s);
+    RTG_TRY(check_launch("graph counters"));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RTG_OK;
+}
+
+// RTG_ERR_CAPACITY (RTG_ERR_UNSUPPORTED for counts of 2^31 or more) once a
+// replay has reported an overflow.  Never waits: the device flags word is
+// sticky and copied to the pinned word at the end of every replay, so the
+// pinned word only ever goes from zero to non-zero, and reading it at any time
+// reports every overflow of the replays whose copy has landed.
+rtg_status graph_check_flags(rtg_graph* gr) {
+    const uint32_t fl = *(volatile uint32_t*)gr->flag_host;
+    if (!fl) return RTG_OK;
+    if (fl & FLAG_COUNT_OVERFLOW) return flags_status(fl);
+    return set_err(RTG_ERR_CAPACITY, "a replay overflowed the graph's buffers (flags 0x%x); create a larger graph",
+                   fl);
 }
 
 // The batched scoring pipeline with fixed grids and device-side sizes.
@@ -915,7 +988,7 @@ rtg_status enqueue_graph_body(rtg_graph* gr, hipStream_t s) {
                 f->hdr.as<Header>(), 0, 0, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
                 f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
     score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), gr->max_views, f->score_part.as<double>(),
-                 gr->scores.as<double>(), s);
+                 gr->scores.as<double>(), f->ctr(C_FLAGS), s);
     HIP_TRY(hipMemcpyAsync(gr->flag_host, f->ctr(C_FLAGS), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     return check_launch("graph body");
 }
@@ -1011,20 +1084,8 @@ rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t 
     make_layout(dummy.data(), max_views, st.tile_w, st.tile_h, f->L);
     f->n_views = max_views;
     gr->grid = score_persistent_blocks(st.tile_w, st.tile_h, st.batch);
+    if ((rs = graph_host_setup(gr, true, s)) != RTG_OK) return fail(rs);
     hipError_t e;
-    if ((e = hipHostMalloc((void**)&gr->staging, sizeof(ViewDev) * max_views, hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&gr->staging_hdr, sizeof(Header), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&gr->flag_host, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&gr->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
-        graph_free(gr);
-        return set_err(RTG_ERR_HIP, "graph setup failed: %s", hipGetErrorString(e));
-    }
-    *gr->flag_host = 0;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
-        graph_free(gr);
-        return set_err(RTG_ERR_HIP, "stream sync failed: %s", hipGetErrorString(e));
-    }
     if ((e = hipStreamBeginCapture(gr->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
         graph_free(gr);
         return set_err(RTG_ERR_HIP, "begin capture failed: %s", hipGetErrorString(e));
@@ -1059,20 +1120,24 @@ rtg_status rtg_score_graph_launch(rtg_graph* gr, const rtg_camera* cams, int32_t
     RTG_TRY(check_cams(cams, n_views));
     if (n_views > gr->max_views) return set_err(RTG_ERR_INVALID, "n_views %d > graph capacity %d", n_views, gr->max_views);
     if (!scores) return set_err(RTG_ERR_INVALID, "scores is NULL");
+    RTG_TRY(graph_check_flags(gr));
     hipStream_t s = (hipStream_t)stream;
     RTG_TRY(graph_layout(gr, cams, n_views));
-    // the pinned staging area may still feed the previous replay's upload
-    if (gr->launched) HIP_TRY(hipEventSynchronize(gr->done));
-    std::memcpy(gr->staging, gr->f->L.views.data(), sizeof(ViewDev) * n_views);
-    *gr->staging_hdr = gr->f->L.hdr;
-    HIP_TRY(hipMemcpyAsync(gr->f->views.p, gr->staging, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(gr->f->hdr.p, gr->staging_hdr, sizeof(Header), hipMemcpyHostToDevice, s));
+    // this slot's pinned area may still feed the upload of the replay before
+    // the previous one
+    const int slot = (int)(gr->launches % rtg_graph::SLOTS);
+    if (gr->launches >= rtg_graph::SLOTS) HIP_TRY(hipEventSynchronize(gr->done[slot]));
+    std::memcpy(gr->staging[slot], gr->f->L.views.data(), sizeof(ViewDev) * n_views);
+    *gr->staging_hdr[slot] = gr->f->L.hdr;
+    HIP_TRY(hipMemcpyAsync(gr->f->views.p, gr->staging[slot], sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(gr->f->hdr.p, gr->staging_hdr[slot], sizeof(Header), hipMemcpyHostToDevice, s));
     {
         Timer tm(gr->ctx, 7, s);
         HIP_TRY(hipGraphLaunch(gr->exec, s));
     }
     HIP_TRY(hipMemcpyAsync(scores, gr->scores.p, sizeof(double) * n_views, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipEventRecord(gr->done, s));
+    HIP_TRY(hipEventRecord(gr->done[slot], s));
+    gr->launches++;
     gr->launched = true;
     gr->last_views = n_views;
     return RTG_OK;
@@ -1081,9 +1146,8 @@ rtg_status rtg_score_graph_launch(rtg_graph* gr, const rtg_camera* cams, int32_t
 rtg_status rtg_score_graph_status(rtg_graph* gr) {
     if (!gr) return set_err(RTG_ERR_INVALID, "graph is NULL");
     if (!gr->launched) return RTG_OK;
-    HIP_TRY(hipEventSynchronize(gr->done));
-    if (*gr->flag_host) return set_err(RTG_ERR_CAPACITY, "graph buffers overflowed (flags 0x%x)", *gr->flag_host);
-    return RTG_OK;
+    HIP_TRY(hipEventSynchronize(gr->done[gr->last_slot()]));
+    return graph_check_flags(gr);
 }
 
 void rtg_score_graph_destroy(rtg_graph* gr) { graph_free(gr); }
@@ -1160,15 +1224,8 @@ static rtg_status map_graph_build(rtg_ctx* ctx, const rtg_gaussians* g, const rt
     if ((rs = f->d_img.ensure(ctx, sizeof(float) * 4 * (size_t)std::max<uint64_t>(P, 1))) != RTG_OK) return fail(rs);
     f->R = (uint32_t)rec_cap;
     f->K = inst_cap;
+    if ((rs = graph_host_setup(gr, false, s)) != RTG_OK) return fail(rs);
     hipError_t e;
-    if ((e = hipHostMalloc((void**)&gr->flag_host, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&gr->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess) {
-        graph_free(gr);
-        return set_err(RTG_ERR_HIP, "graph setup failed: %s", hipGetErrorString(e));
-    }
-    *gr->flag_host = 0;
     if ((e = hipStreamBeginCapture(gr->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
         graph_free(gr);
         return set_err(RTG_ERR_HIP, "begin capture failed: %s", hipGetErrorString(e));
@@ -1243,12 +1300,15 @@ rtg_status rtg_map_graph_create_ssim(rtg_ctx* ctx, const rtg_gaussians* g, const
 rtg_status rtg_map_graph_launch(rtg_graph* gr, void* stream) {
     if (!gr || gr->kind != 1) return set_err(RTG_ERR_INVALID, "not a mapping graph");
     RTG_TRY(ctx_ok(gr->ctx));
+    RTG_TRY(graph_check_flags(gr));
     hipStream_t s = (hipStream_t)stream;
     {
         Timer tm(gr->ctx, 8, s);
         HIP_TRY(hipGraphLaunch(gr->exec, s));
     }
-    HIP_TRY(hipEventRecord(gr->done, s));
+    const int slot = (int)(gr->launches % rtg_graph::SLOTS);
+    HIP_TRY(hipEventRecord(gr->done[slot], s));
+    gr->launches++;
     gr->launched = true;
     return RTG_OK;
 }

@@ -88,6 +88,9 @@ constexpr uint32_t FLAG_REC_OVERFLOW = 1u;
 constexpr uint32_t FLAG_INST_OVERFLOW = 2u;
 // Pair emission found fewer support tiles than were counted (never expected).
 constexpr uint32_t FLAG_BIN_MISMATCH = 4u;
+// A count scan summed to 2^31 or more (records or pairs beyond the 32-bit
+// offsets); the scan then reports a total of 0.
+constexpr uint32_t FLAG_COUNT_OVERFLOW = 8u;
 
 // ---------------------------------------------------------------- launchers
 // All take device pointers and enqueue on `s`.  n_dev arguments are device
@@ -107,13 +110,14 @@ void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, in
                   uint32_t* flags, hipStream_t s);
 
 // Exclusive prefix sum of in[0..n) (n = min(*n_dev, cap)) into out; *total =
-// the full sum.  If gather != NULL the input is in[gather[i]].
+// the full sum.  If gather != NULL the input is in[gather[i]].  A sum of 2^31
+// or more sets FLAG_COUNT_OVERFLOW in *flags (nullable) and gives *total = 0.
 struct ScanWs {
     uint32_t* partial;  // >= scan_blocks(cap) entries
 };
 int scan_blocks(uint64_t cap);
 void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* n_dev,
-              uint32_t cap, uint32_t* total, ScanWs ws, hipStream_t s);
+              uint32_t cap, uint32_t* total, uint32_t* flags, ScanWs ws, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, nbits) of the key.
 // Result lands in (k1, v1) if the number of 8-bit passes is odd, else (k0, v0);
@@ -201,11 +205,18 @@ void uncertainty_update(int64_t n, const float* prev, const float* cur, const fl
 void region_utility(int64_t n, const float* means, const float* u, const double* lo, double size, const int* dims,
                     unsigned long long* cnt, unsigned long long* fix, unsigned int* bad, int64_t* count, double* sum,
                     double* mean, hipStream_t s);
+// scores[v] = sum of view v's tile partials, in a fixed order; NaN when
+// *flags is non-zero.
 void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, const double* partial,
-                  double* scores, hipStream_t s);
+                  double* scores, const uint32_t* flags, hipStream_t s);
 
 void export_pairs(const uint32_t* tile_key, const uint32_t* inst_rec, const uint32_t* K_dev,
                   Records rec, uint64_t* keys, uint32_t* vals, uint32_t cap, hipStream_t s);
+// Planar copies of the first min(*R_dev, cap) records' fields (outputs nullable):
+// mean2d 2 x R, conic 3 x R (binary64), pbox 4 x R (u0, u1, v0, v1), depth
+// bits, Gaussian index, view and pair count.
+void export_records(const uint32_t* R_dev, uint32_t cap, Records rec, double* mean2d, double* conic, int32_t* pbox,
+                    uint32_t* depth_bits, uint32_t* gid, uint32_t* view, uint32_t* ntiles, hipStream_t s);
 
 // Paper-literal view utility: per-view counts of visible high / low
 // uncertainty Gaussians, their uncertainty sum and xi.  acc: 3 * nv u64

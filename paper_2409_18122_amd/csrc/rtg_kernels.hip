@@ -424,58 +424,72 @@ __device__ __forceinline__ uint32_t scan_in(const uint32_t* in, const uint32_t* 
 
 // Multi-block exclusive scan of n = min(*n_dev, cap) items (n = cap when n_dev is
 // null), in[gather[i]] when gather is given: per-block totals here, then
-// k_scan_down.
-__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                            const uint32_t* __restrict__ gather,
-                                                            const uint32_t* __restrict__ n_dev,
-                                                            uint32_t cap, uint32_t* __restrict__ partial) {
-    __shared__ uint32_t ws[SC_THREADS / 64];
-    const uint32_t n = n_dev ? min(*n_dev, cap) : cap;
-    uint32_t begin, end;
-    chunk_of(n, gridDim.x, begin, end);
-    uint32_t acc = 0;
-    for (uint32_t i = begin + threadIdx.x; i < end; i += SC_THREADS) acc += scan_in(in, gather, i);
-    uint32_t total;
-    block_excl_scan(acc, ws, total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
-}
+// k_scan_down.  Totals are formed in 64 bits; a block total is stored
+// saturated at SCAN_LIMIT, so that k_scan_down can tell a sum of 2^31 or more
+// from one that merely wrapped.
+constexpr uint64_t SCAN_LIMIT = 0x80000000ull;
 
-
-// Sum of one value per thread over a 256-thread block (every thread gets it).
-__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* ws) {
+__device__ __forceinline__ uint64_t block_sum64(uint64_t x, uint64_t* ws) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+    for (int o = 32; o > 0; o >>= 1) x += (uint64_t)__shfl_xor((unsigned long long)x, o, 64);
     if (lane_id() == 0) ws[threadIdx.x >> 6] = x;
     __syncthreads();
-    uint32_t t = 0;
+    uint64_t t = 0;
 #pragma unroll
     for (int k = 0; k < SC_THREADS / 64; k++) t += ws[k];
     __syncthreads();
     return t;
 }
 
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                            const uint32_t* __restrict__ gather,
+                                                            const uint32_t* __restrict__ n_dev,
+                                                            uint32_t cap, uint32_t* __restrict__ partial) {
+    __shared__ uint64_t ws[SC_THREADS / 64];
+    const uint32_t n = n_dev ? min(*n_dev, cap) : cap;
+    uint32_t begin, end;
+    chunk_of(n, gridDim.x, begin, end);
+    uint64_t acc = 0;
+    for (uint32_t i = begin + threadIdx.x; i < end; i += SC_THREADS) acc += scan_in(in, gather, i);
+    const uint64_t total = block_sum64(acc, ws);
+    if (threadIdx.x == 0) partial[blockIdx.x] = (uint32_t)min(total, SCAN_LIMIT);
+}
+
+
 // partial[b] holds block b's total (k_scan_reduce); each block adds up the
 // totals before it, and block 0 writes the grand total to *total (nullable).
+// A grand total of 2^31 or more is not representable by the 32-bit offsets:
+// then *total is 0, flags (nullable) gets FLAG_COUNT_OVERFLOW and nothing is
+// written to out, so every consumer of the total sees an empty list.
 // in and out may be the same array (each item is read and written by one thread).
 __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
                                                           const uint32_t* __restrict__ gather,
                                                           uint32_t* out,
                                                           const uint32_t* __restrict__ n_dev, uint32_t cap,
                                                           const uint32_t* __restrict__ partial,
-                                                          uint32_t* __restrict__ total_out) {
+                                                          uint32_t* __restrict__ total_out,
+                                                          uint32_t* __restrict__ flags) {
     __shared__ uint32_t ws[SC_THREADS / 64];
+    __shared__ uint64_t ws64[SC_THREADS / 64];
     const uint32_t n = n_dev ? min(*n_dev, cap) : cap;
     uint32_t begin, end;
     chunk_of(n, gridDim.x, begin, end);
-    uint32_t before = 0, all = 0;
+    uint64_t before = 0, all = 0;
     for (uint32_t t = threadIdx.x; t < gridDim.x; t += SC_THREADS) {
-        const uint32_t p = partial[t];
+        const uint64_t p = partial[t];
         all += p;
         before += t < blockIdx.x ? p : 0u;
     }
-    uint32_t run = block_sum(before, ws);
-    all = block_sum(all, ws);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = all;
+    uint32_t run = (uint32_t)block_sum64(before, ws64);
+    all = block_sum64(all, ws64);
+    if (all >= SCAN_LIMIT) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (total_out) *total_out = 0u;
+            if (flags) atomicOr(flags, FLAG_COUNT_OVERFLOW);
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = (uint32_t)all;
     for (uint32_t t0 = begin; t0 < end; t0 += SC_TILE) {
         // thread owns SC_IPT consecutive items
         uint32_t v[SC_IPT];
@@ -1993,10 +2007,15 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
 __global__ __launch_bounds__(256) void k_score_reduce(const ViewDev* __restrict__ views,
                                                       const Header* __restrict__ hdr,
                                                       const double* __restrict__ partial,
-                                                      double* __restrict__ scores) {
+                                                      double* __restrict__ scores,
+                                                      const uint32_t* __restrict__ flags) {
     __shared__ double ws[4];
     const uint32_t v = blockIdx.x;
     if (v >= hdr->n_views) return;
+    if (*flags) {  // an overflowed or inconsistent binning: the scores are invalid
+        if (threadIdx.x == 0) scores[v] = __builtin_nan("");
+        return;
+    }
     const ViewDev& V = views[v];
     const uint32_t nt = (uint32_t)(V.tiles_x * V.tiles_y);
     double s = 0.0;
@@ -2016,6 +2035,38 @@ __global__ __launch_bounds__(256) void k_export(const uint32_t* __restrict__ til
         uint32_t r = inst_rec[i];
         if (keys) keys[i] = ((uint64_t)tile_key[i] << 32) | rec.dkey[r];
         if (vals) vals[i] = rec.gid[r];
+    }
+}
+
+// Planar copies of the record fields for inspection (all outputs nullable).
+__global__ __launch_bounds__(256) void k_export_records(const uint32_t* __restrict__ R_dev, uint32_t cap, Records rec,
+                                                        double* __restrict__ mean2d, double* __restrict__ conic,
+                                                        int32_t* __restrict__ pbox, uint32_t* __restrict__ depth_bits,
+                                                        uint32_t* __restrict__ gid, uint32_t* __restrict__ view,
+                                                        uint32_t* __restrict__ ntiles) {
+    const uint32_t R = min(*R_dev, cap);
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const EmitRec e = rec.emit[r];
+        if (mean2d) {
+            mean2d[r] = (double)e.g0.x + (double)e.g0.z;
+            mean2d[(uint64_t)R + r] = (double)e.g0.y + (double)e.g0.w;
+        }
+        if (conic) {
+            const double4 q = rec.q64[r];
+            conic[r] = q.x;
+            conic[(uint64_t)R + r] = q.y;
+            conic[2 * (uint64_t)R + r] = q.z;
+        }
+        if (pbox) {
+            pbox[r] = (int32_t)(e.pbox.x & 0xffffu);
+            pbox[(uint64_t)R + r] = (int32_t)(e.pbox.x >> 16);
+            pbox[2 * (uint64_t)R + r] = (int32_t)(e.pbox.y & 0xffffu);
+            pbox[3 * (uint64_t)R + r] = (int32_t)(e.pbox.y >> 16);
+        }
+        if (depth_bits) depth_bits[r] = rec.dkey[r];
+        if (gid) gid[r] = rec.gid[r];
+        if (view) view[r] = e.view;
+        if (ntiles) ntiles[r] = e.ntiles;
     }
 }
 
@@ -2423,10 +2474,10 @@ int scan_blocks(uint64_t cap) {
 }
 
 void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* n_dev, uint32_t cap,
-              uint32_t* total, ScanWs ws, hipStream_t s) {
+              uint32_t* total, uint32_t* flags, ScanWs ws, hipStream_t s) {
     int nb = scan_blocks(cap);
     k_scan_reduce<<<nb, SC_THREADS, 0, s>>>(in, gather, n_dev, cap, ws.partial);
-    k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, gather, out, n_dev, cap, ws.partial, total);
+    k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, gather, out, n_dev, cap, ws.partial, total, flags);
 }
 
 // Grid of a pass with digits of db bits: one block per tile of input, up to
@@ -2456,7 +2507,8 @@ static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, cons
         const uint32_t count = (uint32_t)((1u << DB) * nb);
         int sb = scan_blocks(count);
         k_scan_reduce<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, nullptr, count, ws.partial);
-        k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, nullptr, count, ws.partial, nullptr);
+        k_scan_down<<<sb, SC_THREADS, 0, s>>>(ws.hist, nullptr, ws.hist, nullptr, count, ws.partial, nullptr,
+                                              nullptr);
     }
     // 8-bit passes stage their scatter in LDS; the 11-bit one writes directly (its
     // per-wave tables already take 32 KB of LDS)
@@ -2593,8 +2645,8 @@ void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_
 }
 
 void score_reduce(const ViewDev* views, const Header* hdr, int n_views_cap, const double* partial,
-                  double* scores, hipStream_t s) {
-    k_score_reduce<<<n_views_cap, 256, 0, s>>>(views, hdr, partial, scores);
+                  double* scores, const uint32_t* flags, hipStream_t s) {
+    k_score_reduce<<<n_views_cap, 256, 0, s>>>(views, hdr, partial, scores, flags);
 }
 
 void sum_u32_pair(const uint32_t* a, const uint32_t* b, uint64_t n, unsigned long long* out, hipStream_t s) {
@@ -2626,6 +2678,12 @@ void region_utility(int64_t n, const float* means, const float* u, const double*
 void export_pairs(const uint32_t* tile_key, const uint32_t* inst_rec, const uint32_t* K_dev, Records rec,
                   uint64_t* keys, uint32_t* vals, uint32_t cap, hipStream_t s) {
     k_export<<<grid_for(cap, 256, 8192), 256, 0, s>>>(tile_key, inst_rec, K_dev, cap, rec, keys, vals);
+}
+
+void export_records(const uint32_t* R_dev, uint32_t cap, Records rec, double* mean2d, double* conic, int32_t* pbox,
+                    uint32_t* depth_bits, uint32_t* gid, uint32_t* view, uint32_t* ntiles, hipStream_t s) {
+    k_export_records<<<grid_for(std::max<uint32_t>(cap, 1), 256, 8192), 256, 0, s>>>(
+        R_dev, cap, rec, mean2d, conic, pbox, depth_bits, gid, view, ntiles);
 }
 
 }  // namespace rtg

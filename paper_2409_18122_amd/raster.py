@@ -15,7 +15,8 @@ import weakref
 import torch
 
 from . import _lib as _lib_mod
-from ._lib import (Camera, Gaussians, Grads, RtgError, Settings, check, lib, RTG_ERR_CAPACITY)
+from ._lib import (Camera, Gaussians, Grads, RtgError, Settings, check, lib, RTG_ERR_CAPACITY,
+                   RTG_ERR_UNSUPPORTED)
 
 DEFAULTS = {
     "tile_w": 16, "tile_h": 16, "batch": 0,
@@ -248,6 +249,26 @@ class Frame:
                                      _ptr(vals) if K else None,
                                      _ptr(ranges) if inf["tiles"] else None, _stream()))
         return keys, vals, ranges
+
+    def export_records(self):
+        """The projected records (Gaussian-major, views ascending): dict of
+        mean2d (2, R) and conic (3, R) float64, pbox (4, R) int32 (u0, u1, v0,
+        v1), depth_bits, gid, view and ntiles (R,) int32 views of uint32."""
+        R = max(self.info()["records"], 0)
+        dev = self._g["means"].device
+        out = {"mean2d": torch.empty(2 * R, device=dev, dtype=torch.float64),
+               "conic": torch.empty(3 * R, device=dev, dtype=torch.float64),
+               "pbox": torch.empty(4 * R, device=dev, dtype=torch.int32)}
+        for k in ("depth_bits", "gid", "view", "ntiles"):
+            out[k] = torch.empty(R, device=dev, dtype=torch.int32)
+        if R:
+            check(lib().rtg_frame_export_records(self.ctx.handle, self.handle, _ptr(out["mean2d"]),
+                                                 _ptr(out["conic"]), _ptr(out["pbox"]), _ptr(out["depth_bits"]),
+                                                 _ptr(out["gid"]), _ptr(out["view"]), _ptr(out["ntiles"]),
+                                                 _stream()))
+        for k, rows in (("mean2d", 2), ("conic", 3), ("pbox", 4)):
+            out[k] = out[k].view(rows, R)
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

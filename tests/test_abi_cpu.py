@@ -71,6 +71,7 @@ def test_null_arguments_rejected_on_host(L):
     assert L.rtg_score_graph_launch(None, None, 1, None, None) == -1
     assert L.rtg_score_graph_status(None) == -1
     assert L.rtg_frame_export(None, None, None, None, None, None) == -1
+    assert L.rtg_frame_export_records(None, None, None, None, None, None, None, None, None, None) == -1
     info = (ctypes.c_int64 * 6)()
     assert L.rtg_frame_info(None, info) == -1
     assert L.rtg_autotune(None, None, None, 1, 0, None, None) == -1

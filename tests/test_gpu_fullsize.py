@@ -15,8 +15,8 @@ import torch
 
 import oracle
 import scenes
-from gpu_util import (GRAD_REL_TOL, SCORE_TOL_PER_PIXEL, assert_images_close, gpu_stack, grad_rel_errors,
-                      grads_to_numpy)
+from gpu_util import (GRAD_REL_TOL, SCORE_TOL_PER_PIXEL, assert_elementwise, assert_images_close, gpu_stack,
+                      grad_rel_errors, grads_to_numpy)
 
 pytestmark = pytest.mark.gpu
 
@@ -147,6 +147,7 @@ def test_c4_keyframes_full_size(raster, rctx):
     say("C4: batched backward over 8 keyframes")
     grads = grads_to_numpy(f.backward(t["rgb"], t["depth"], t["alpha"], t["unc"]))
     ref = {k: np.zeros_like(np.asarray(g[k], np.float64)) for k in GROUPS}
+    touched = np.zeros(scenes.n_gaussians(g), bool)
     for v in checked_views:
         say(f"C4: oracle render + adjoint of keyframe {v}")
         r = oracle.render(g, cams[v], st)
@@ -156,10 +157,13 @@ def test_c4_keyframes_full_size(raster, rctx):
         a = oracle.adjoint(g, cams[v], st, g_rgb=w[:3], g_depth=w[3], g_alpha=w[4], g_unc=w[5], tile=tile)
         for k in GROUPS:
             ref[k] += a[k]
+        touched |= a["touched"]
     rel = grad_rel_errors(grads, ref)
     say(f"C4 gradient relative errors {rel}")
     for k, val in rel.items():
         assert val <= GRAD_REL_TOL, (k, val)
+    n_excl = assert_elementwise(grads, ref, touched, "C4")
+    say(f"C4 element-wise bar met; {n_excl} Gaussians excluded (near-threshold decisions)")
     # FP64 finite-difference spot checks on (Gaussian, parameter) pairs; a
     # stencil is used only if no threshold decision changes inside it, so more
     # pairs are drawn than must be checked
@@ -210,19 +214,30 @@ def test_c5_uneven_graph_full_size(raster, rctx):
     grb.close()
     eagerb = raster.score_views(rctx, dev, cams, S(), persistent=True, mode="binary").cpu().numpy()
     assert np.array_equal(gotb, eagerb) and np.all(gotb >= got)
-    sizes = {}
+    # 16 views, the first five or six of each resolution; the binary-J trace
+    # on the first of each resolution
+    by_size = {}
     for v, c in enumerate(cams):
-        sizes.setdefault(c["width"], v)
-    for v in sorted(sizes.values()):
+        by_size.setdefault(c["width"], []).append(v)
+    assert len(by_size) == 3
+    sample = sorted(sum((vs[:6] if w == 160 else vs[:5] for w, vs in by_size.items()), []))
+    assert len(sample) == 16
+    refs = oracle.score(g, [cams[v] for v in sample], S())
+    rel_max = 0.0
+    for v, ref in zip(sample, refs):
         c = cams[v]
-        ref = oracle.score(g, [c], S())[0]
         P = c["width"] * c["height"]
-        say(f"C5 view {v} ({c['width']}x{c['height']}): gpu {got[v]:.6f} oracle {ref:.6f} "
-            f"rel {abs(got[v] - ref) / max(abs(ref), 1e-30):.2e}")
+        rel = abs(got[v] - ref) / max(abs(ref), 1e-30)
+        rel_max = max(rel_max, rel)
+        say(f"C5 view {v} ({c['width']}x{c['height']}): gpu {got[v]:.6f} oracle {ref:.6f} rel {rel:.2e}")
         assert abs(got[v] - ref) <= SCORE_TOL_PER_PIXEL * P
-        refb = oracle.score(g, [c], S(), mode=1)[0]
-        say(f"C5 view {v} binary-J: gpu {gotb[v]:.4f} oracle {refb:.4f} diff {abs(gotb[v] - refb):.3g}")
-        assert abs(gotb[v] - refb) <= SCORE_TOL_PER_PIXEL * P
+    say(f"C5: 16 views within the bar, max relative score error {rel_max:.2e}")
+    firsts = [vs[0] for vs in by_size.values()]
+    refb = oracle.score(g, [cams[v] for v in firsts], S(), mode=1)
+    for v, rb in zip(firsts, refb):
+        P = cams[v]["width"] * cams[v]["height"]
+        say(f"C5 view {v} binary-J: gpu {gotb[v]:.4f} oracle {rb:.4f} diff {abs(gotb[v] - rb):.3g}")
+        assert abs(gotb[v] - rb) <= SCORE_TOL_PER_PIXEL * P
 
 
 def test_autotuner_choice_does_not_change_results(raster, rctx, tmp_path):

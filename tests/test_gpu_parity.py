@@ -9,8 +9,8 @@ import torch
 
 import oracle
 import scenes
-from gpu_util import (GRAD_REL_TOL, SCORE_TOL_PER_PIXEL, assert_images_close, elementwise_violations,
-                      gpu_stack, grad_rel_errors, grads_to_numpy)
+from gpu_util import (GRAD_REL_TOL, SCORE_TOL_PER_PIXEL, assert_elementwise, assert_images_close, gpu_stack,
+                      grad_rel_errors, grads_to_numpy)
 
 pytestmark = pytest.mark.gpu
 
@@ -218,6 +218,7 @@ def _backward_parity(raster, rctx, g, cams, target, tile=(16, 16), label=""):
     f.render()
     ref = {k: np.zeros_like(np.asarray(g[k], np.float64)) for k in
            ("means", "log_scales", "quats", "opacity", "colors")}
+    touched = np.zeros(scenes.n_gaussians(g), bool)
     d_rgb_all, d_dep_all, d_a_all, d_u_all = [], [], [], []
     rng = np.random.default_rng(7)
     for c in cams:
@@ -231,6 +232,7 @@ def _backward_parity(raster, rctx, g, cams, target, tile=(16, 16), label=""):
         a = oracle.adjoint(g, c, S(tile), g_rgb=gr, g_depth=gd, g_alpha=ga, g_unc=gu, tile=tile)
         for k in ref:
             ref[k] += a[k]
+        touched |= a["touched"]
         d_rgb_all.append(gr.astype(np.float32).reshape(-1))
         d_dep_all.append(gd.astype(np.float32).reshape(-1))
         d_a_all.append(ga.astype(np.float32).reshape(-1))
@@ -240,11 +242,12 @@ def _backward_parity(raster, rctx, g, cams, target, tile=(16, 16), label=""):
     grads = f.backward(t(d_rgb_all), t(d_dep_all), t(d_a_all), t(d_u_all))
     gpu = grads_to_numpy(grads)
     rel = grad_rel_errors(gpu, ref)
-    viol = elementwise_violations(gpu, ref)
-    say(f"{label} relative errors {rel} element violations {viol}")
+    say(f"{label} relative errors {rel}")
     for k, v in rel.items():
         assert v <= GRAD_REL_TOL, (label, k, v)
-    return rel, viol
+    n_excl = assert_elementwise(gpu, ref, touched, label)
+    say(f"{label} element-wise bar met; {n_excl} of {touched.size} Gaussians excluded (near-threshold decisions)")
+    return rel, n_excl
 
 
 def test_c2_gradients_full_size(raster, rctx):
@@ -295,8 +298,9 @@ def test_c3_scores(raster, rctx):
     plain = raster.score_views(rctx, dev, cams, S(), persistent=False).cpu().numpy()
     # same kernels, same per-tile sums, same fixed-order reductions
     assert np.array_equal(batched, plain)
-    for v in (0, 17, 41, 63):
-        ref = oracle.score(g, [cams[v]], S())[0]
+    sample = list(range(0, 64, 4))  # 16 of the 64 views
+    refs = oracle.score(g, [cams[v] for v in sample], S())
+    for v, ref in zip(sample, refs):
         P = cams[v]["width"] * cams[v]["height"]
         say(f"view {v}: gpu {batched[v]:.6f} oracle {ref:.6f} rel {abs(batched[v] - ref) / max(ref, 1e-30):.2e}")
         assert abs(batched[v] - ref) <= SCORE_TOL_PER_PIXEL * P

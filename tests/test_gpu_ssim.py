@@ -174,7 +174,10 @@ def test_c2_mapping_step_with_ssim(raster, rctx):
     ref = oracle.adjoint(g, cams[0], S(), g_rgb=gr.reshape(3, 480, 640), g_depth=gd.reshape(480, 640))
     gpu = grads_to_numpy(grads)
     rel = grad_rel_errors(gpu, ref)
-    say(f"  parameter gradients: relative errors {rel}, element violations {elementwise_violations(gpu, ref)}")
+    # the GPU backward takes the GPU's own image gradient (not the oracle's), so
+    # the element-wise count is reported, not held to the bar
+    say(f"  parameter gradients: relative errors {rel}, element violations "
+        f"{elementwise_violations(gpu, ref, exclude=ref['touched'])}")
     for k, v in rel.items():
         assert v <= GRAD_REL_TOL, (k, v)
     f.close()
