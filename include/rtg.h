@@ -425,6 +425,21 @@ rtg_status rtg_collision_check(rtg_ctx *ctx, const rtg_gaussians *g, const float
                                int64_t n_points, float r_robot, float lambda_g, int32_t *collide,
                                float *clearance, void *stream);
 
+/* rtg_collision_check for callers that cannot allocate device memory (code
+ * under hipGraph capture, tight planning loops, hosts that forbid
+ * allocation): the same check and results, with its scratch (24 bytes per
+ * Gaussian + 4 per point, each part 256-byte aligned) taken from a fixed
+ * 96 MiB device array that every GPU the library runs on holds from the
+ * library's load until the process ends; it calls no hipMalloc, hipFree or
+ * allocating routine.  Larger inputs return RTG_ERR_UNSUPPORTED before any
+ * launch (use rtg_collision_check).  All calls on one GPU share that array:
+ * calls that overlap on one GPU (several streams, threads or contexts) race,
+ * so the caller must order them.  The caller still passes the inputs and
+ * outputs, as for rtg_collision_check. */
+rtg_status rtg_collision_check_noalloc(rtg_ctx *ctx, const rtg_gaussians *g, const float *points,
+                                       int64_t n_points, float r_robot, float lambda_g,
+                                       int32_t *collide, float *clearance, void *stream);
+
 /* Work counters of a rendered frame (host output, synchronises `stream`):
  *   out[0] records (visible view-Gaussian pairs), out[1] instances
  *   (tile-Gaussian pairs), out[2] contributing pixel-Gaussian pairs (terms of

@@ -91,6 +91,7 @@ SIGNATURES = {
     "rtg_region_utility": (i32, [vp, i64, vp, vp, _c.POINTER(_c.c_double), _c.c_double, vp, vp, vp, vp]),
     "rtg_loss_ssim": (i32, [vp, vp, vp, vp, vp, vp, f32, f32, f32, vp, vp, vp, vp]),
     "rtg_collision_check": (i32, [vp, _c.POINTER(Gaussians), vp, i64, f32, f32, vp, vp, vp]),
+    "rtg_collision_check_noalloc": (i32, [vp, _c.POINTER(Gaussians), vp, i64, f32, f32, vp, vp, vp]),
     "rtg_timing_enable": (i32, [vp, i32]),
     "rtg_timing_read": (i32, [vp, i32, _c.POINTER(_c.c_double), _c.POINTER(i64)]),
     "rtg_timing_reset": (i32, [vp]),

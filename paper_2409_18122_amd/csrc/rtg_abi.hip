@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -138,6 +139,7 @@ struct PendingTimer {
 struct rtg_ctx {
     int device = 0;
     int cu = 0;
+    void* scratch = nullptr;  // this device's fixed scratch array (device address), or NULL
     Pool pool;
     uint32_t* pinned = nullptr;  // small host readback area
     int last_tw = 16, last_th = 16, last_batch = 0;
@@ -562,6 +564,61 @@ rtg_status ctx_ok(rtg_ctx* ctx) {
 
 }  // namespace
 
+// ======================================================== fixed scratch
+// Device scratch for the entry points that allocate nothing: one array per
+// GPU, resident from the code object's load until the process ends.  Host
+// code must never pass the array's own name to a kernel or a copy (it names
+// a host-side stand-in); it uses the device address that hipGetSymbolAddress
+// returns for the current device, taken once per device at context creation.
+constexpr size_t SCRATCH_BYTES = (size_t)96 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// With `device` current: its scratch address, looked up on first use.
+rtg_status scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+        return set_err(RTG_ERR_UNSUPPORTED, "fixed scratch: device %d beyond %d", device, SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_err(RTG_ERR_HIP, "hipGetSymbolAddress of the fixed scratch failed: %s (%d)",
+                           hipGetErrorString(e), (int)e);
+        }
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return RTG_OK;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+rtg_status collision_args(const rtg_gaussians* g, const float* points, int64_t n_points, float r_robot,
+                          float lambda_g, int32_t* collide) {
+    if (!g) return set_err(RTG_ERR_INVALID, "gaussians is NULL");
+    if (g->n < 0 || n_points < 0) return set_err(RTG_ERR_INVALID, "n = %lld, n_points = %lld", (long long)g->n,
+                                                 (long long)n_points);
+    if (g->n >= (int64_t)1 << 31 || n_points >= (int64_t)1 << 31)
+        return set_err(RTG_ERR_UNSUPPORTED, "n = %lld, n_points = %lld: 2^31 or more", (long long)g->n,
+                       (long long)n_points);
+    if (g->n > 0 && (!g->means || !g->log_scales)) return set_err(RTG_ERR_INVALID, "means and log_scales are required");
+    if (n_points > 0 && (!points || !collide)) return set_err(RTG_ERR_INVALID, "points and collide must be non-NULL");
+    if (!std::isfinite(r_robot) || !(r_robot >= 0.0f)) return set_err(RTG_ERR_INVALID, "r_robot must be finite and >= 0");
+    if (!std::isfinite(lambda_g) || !(lambda_g >= 0.0f))
+        return set_err(RTG_ERR_INVALID, "lambda_g must be finite and >= 0");
+    return RTG_OK;
+}
+
+}  // namespace
+
 // =================================================================== ABI
 
 extern "C" {
@@ -603,6 +660,9 @@ rtg_status rtg_create(int32_t device, rtg_ctx** out) {
     if (!c) return set_err(RTG_ERR_OOM, "host allocation failed");
     c->device = device;
     c->cu = device_cu_count();
+    // the fixed scratch of the allocation-free entry points; a failure here
+    // is reported by those entry points, the rest of the library works
+    if (scratch_address(device, &c->scratch) != RTG_OK) c->scratch = nullptr;
     HIP_TRY(hipHostMalloc((void**)&c->pinned, sizeof(uint32_t) * 64, hipHostMallocDefault));
     *out = c.release();
     return RTG_OK;
@@ -1506,17 +1566,7 @@ rtg_status rtg_region_utility(rtg_ctx* ctx, int64_t n, const float* means, const
 rtg_status rtg_collision_check(rtg_ctx* ctx, const rtg_gaussians* g, const float* points, int64_t n_points,
                                float r_robot, float lambda_g, int32_t* collide, float* clearance, void* stream) {
     RTG_TRY(ctx_ok(ctx));
-    if (!g) return set_err(RTG_ERR_INVALID, "gaussians is NULL");
-    if (g->n < 0 || n_points < 0) return set_err(RTG_ERR_INVALID, "n = %lld, n_points = %lld", (long long)g->n,
-                                                 (long long)n_points);
-    if (g->n >= (int64_t)1 << 31 || n_points >= (int64_t)1 << 31)
-        return set_err(RTG_ERR_UNSUPPORTED, "n = %lld, n_points = %lld: 2^31 or more", (long long)g->n,
-                       (long long)n_points);
-    if (g->n > 0 && (!g->means || !g->log_scales)) return set_err(RTG_ERR_INVALID, "means and log_scales are required");
-    if (n_points > 0 && (!points || !collide)) return set_err(RTG_ERR_INVALID, "points and collide must be non-NULL");
-    if (!std::isfinite(r_robot) || !(r_robot >= 0.0f)) return set_err(RTG_ERR_INVALID, "r_robot must be finite and >= 0");
-    if (!std::isfinite(lambda_g) || !(lambda_g >= 0.0f))
-        return set_err(RTG_ERR_INVALID, "lambda_g must be finite and >= 0");
+    RTG_TRY(collision_args(g, points, n_points, r_robot, lambda_g, collide));
     if (n_points == 0) return RTG_OK;
     hipStream_t s = (hipStream_t)stream;
     Buf packed, bound, key;
@@ -1526,6 +1576,35 @@ rtg_status rtg_collision_check(rtg_ctx* ctx, const rtg_gaussians* g, const float
     collision_check(to_dev(*g), points, n_points, r_robot, lambda_g, packed.as<float4>(), bound.as<float2>(), collide,
                     key.as<uint32_t>(), clearance, s);
     return check_launch("collision check");
+}
+
+rtg_status rtg_collision_check_noalloc(rtg_ctx* ctx, const rtg_gaussians* g, const float* points, int64_t n_points,
+                                       float r_robot, float lambda_g, int32_t* collide, float* clearance,
+                                       void* stream) {
+    RTG_TRY(ctx_ok(ctx));
+    RTG_TRY(collision_args(g, points, n_points, r_robot, lambda_g, collide));
+    // the same three scratch arrays as rtg_collision_check, carved from the
+    // fixed array: packed (16 B per Gaussian), bound (8 B), clear_key (4 B
+    // per point); the kernels write all of them before reading them
+    const size_t n = (size_t)g->n, np = (size_t)n_points;
+    const size_t off_bound = align256(16 * n), off_key = off_bound + align256(8 * n);
+    const size_t need = off_key + align256(4 * np);
+    if (need > SCRATCH_BYTES)
+        return set_err(RTG_ERR_UNSUPPORTED,
+                       "%lld Gaussians and %lld points need %zu bytes of scratch, above the fixed %zu "
+                       "(24 bytes per Gaussian + 4 per point); use rtg_collision_check",
+                       (long long)g->n, (long long)n_points, need, SCRATCH_BYTES);
+    if (n_points == 0) return RTG_OK;
+    if (!ctx->scratch) {
+        void* p = nullptr;
+        RTG_TRY(scratch_address(ctx->device, &p));
+        ctx->scratch = p;
+    }
+    unsigned char* base = static_cast<unsigned char*>(ctx->scratch);
+    collision_check(to_dev(*g), points, n_points, r_robot, lambda_g, reinterpret_cast<float4*>(base),
+                    reinterpret_cast<float2*>(base + off_bound), collide, reinterpret_cast<uint32_t*>(base + off_key),
+                    clearance, (hipStream_t)stream);
+    return check_launch("collision check (fixed scratch)");
 }
 
 rtg_status rtg_trajectory_select(rtg_ctx* ctx, const double* xi, const int32_t* offsets, int32_t n_traj,

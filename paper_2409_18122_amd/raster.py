@@ -550,9 +550,11 @@ def region_utility(ctx, means, u, box, size=2.5):
     return count, sm, mean
 
 
-def collision_check(ctx, g, points, r_robot, lambda_g=3.0, clearance=True):
+def collision_check(ctx, g, points, r_robot, lambda_g=3.0, clearance=True, no_alloc=False):
     """(collide int32[P], clearance float32[P] or None) of the points
-    (planar 3 x P) against the Gaussians' principal-axis spheres."""
+    (planar 3 x P) against the Gaussians' principal-axis spheres.
+    no_alloc=True calls rtg_collision_check_noalloc (the library's fixed
+    scratch, no device allocation; up to 96 MiB of scratch)."""
     for k in ("means", "log_scales"):
         t = g[k]
         if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda or t.dim() != 2 or t.shape[0] != 3:
@@ -566,8 +568,9 @@ def collision_check(ctx, g, points, r_robot, lambda_g=3.0, clearance=True):
     dev = g["means"].device
     hit = torch.empty(P, device=dev, dtype=torch.int32)
     clr = torch.empty(P, device=dev, dtype=torch.float32) if clearance else None
-    check(lib().rtg_collision_check(ctx.handle, ctypes.byref(gs), _ptr(pts), P, float(r_robot), float(lambda_g),
-                                    _ptr(hit), _ptr(clr), _stream()))
+    fn = lib().rtg_collision_check_noalloc if no_alloc else lib().rtg_collision_check
+    check(fn(ctx.handle, ctypes.byref(gs), _ptr(pts), P, float(r_robot), float(lambda_g), _ptr(hit), _ptr(clr),
+             _stream()))
     return hit, clr
 
 

@@ -88,6 +88,7 @@ def test_null_arguments_rejected_on_host(L):
     box = (ctypes.c_double * 6)(0, 0, 0, 10, 5, 2.5)
     assert L.rtg_region_utility(None, 4, None, None, box, 2.5, None, None, None, None) == -1
     assert L.rtg_collision_check(None, None, None, 4, 0.25, 3.0, None, None, None) == -1
+    assert L.rtg_collision_check_noalloc(None, None, None, 4, 0.25, 3.0, None, None, None) == -1
     stats = (ctypes.c_int64 * 4)()
     assert L.rtg_frame_stats(None, None, stats, None) == -1
     from paper_2409_18122_amd._lib import ALLOC_FN, FREE_FN
