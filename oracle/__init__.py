@@ -45,24 +45,45 @@ EV_ALPHA = 1e-5
 EV_T = 1e-4
 
 
+# binary64 throughout, no contraction and no reassociation: the optimisation
+# level and target only change speed, never a result
+_CFLAGS = ["-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
 def build(force: bool = False) -> str:
     """Compile rtg_oracle.c with gcc (binary64, no FP contraction, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
-               "-ffp-contract=off", "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", "-O2", *_CFLAGS, "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
 
 
+def use_native_build(directory: str) -> str:
+    """Compile rtg_oracle.c at -O3 -march=native for the host it runs on, into
+    `directory`, and make it the library this module calls (for timing the
+    oracle as a CPU baseline; results are the same as the in-tree build's).
+    Returns the gcc flags used."""
+    global _lib, _lib_path
+    path = os.path.join(directory, "librtgo_native.so")
+    flags = ["-O3", "-march=native"]
+    subprocess.run(["gcc", *flags, *_CFLAGS, "-o", path, _SRC, "-lm"], check=True)
+    _lib = None
+    _lib_path = path
+    lib()
+    return " ".join(flags)
+
+
 _lib = None
+_lib_path = None  # None: the in-tree build
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        if _lib_path is None:
+            build()
+        L = ctypes.CDLL(_lib_path or _LIB)
         p = ctypes.c_void_p
         i64 = ctypes.c_int64
         L.rtgo_project.argtypes = [i64] + [p] * 6 + [p] * 8

@@ -213,6 +213,31 @@ def config5(n=2_000_000, seed=5, n_views=256):
     return g, cams
 
 
+def trajectory_states(n_traj=64, L=8, seed=7, width=320, height=240, step=0.5, z=1.0, curvature=0.6):
+    """Candidate trajectories of the trajectory planner (Sec. IV-B): n_traj
+    motion primitives of L steps of `step` metres (the candidate spacing of
+    Sec. V-A) in the C3-C5 room, each a level camera at height z that looks
+    along its heading; start uniform in the room, heading U(0, 2 pi),
+    curvature U(-c, c) per metre.  Returns (cameras, offsets): the n_traj
+    (L + 1) states trajectory after trajectory, and offsets[t] = t (L + 1)."""
+    rng = np.random.default_rng(seed)
+    fx, fy, cx, cy = default_intrinsics(width, height)
+    xy0 = rng.uniform(-8.0, 8.0, (n_traj, 2))
+    th0 = rng.uniform(0.0, 2.0 * np.pi, n_traj)
+    kap = rng.uniform(-curvature, curvature, n_traj)
+    cams = []
+    for t in range(n_traj):
+        x, y, th = xy0[t, 0], xy0[t, 1], th0[t]
+        for l in range(L + 1):
+            R, T = yaw_pose(x, y, z, th)
+            cams.append(make_camera(width, height, fx, fy, cx, cy, R, T))
+            x += step * np.cos(th)
+            y += step * np.sin(th)
+            th += kap[t] * step
+    offsets = np.arange(n_traj + 1, dtype=np.int32) * (L + 1)
+    return cams, offsets
+
+
 LOT_HALF = 20.0  # a 40 m x 40 m lot
 
 
