@@ -121,6 +121,7 @@ def main():
     ap.add_argument("--only", type=str, default=",".join(SECTIONS),
                     help="comma-separated sections: " + ",".join(SECTIONS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-view (plain) scoring loops")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -289,6 +290,8 @@ def main():
         g3_np, cams3 = scenes.config3()
         g3 = raster.to_device(g3_np)
         for persistent, name in ((True, "batched"), (False, "plain")):
+            if not persistent and args.no_plain:
+                continue
             t = med(event_times(lambda: raster.score_views(ctx, g3, cams3, S, persistent=persistent), R, W))
             views[f"64x320x240_{name}"] = round(len(cams3) / (t * 1e-3), 1)
         gr3 = raster.ScoreGraph(ctx, g3, 64, 320, 240, S, probe=cams3)
@@ -313,8 +316,9 @@ def main():
             views[name] = round(len(cams5) / (t * 1e-3), 1)
         t = med(event_times(lambda: raster.score_views(ctx, g5, cams5, S, persistent=True), R, W))
         views["256_uneven_batched_eager"] = round(len(cams5) / (t * 1e-3), 1)
-        t = med(event_times(lambda: raster.score_views(ctx, g5, cams5, S, persistent=False), max(R // 5, 10), 2))
-        views["256_uneven_plain"] = round(len(cams5) / (t * 1e-3), 1)
+        if not args.no_plain:
+            t = med(event_times(lambda: raster.score_views(ctx, g5, cams5, S, persistent=False), max(R // 5, 10), 2))
+            views["256_uneven_plain"] = round(len(cams5) / (t * 1e-3), 1)
         f5 = raster.Frame(ctx, g5, cams5, S)
         f5.bin_sort()
         f5.render(("alpha",))

@@ -929,6 +929,61 @@ typedef struct {
     double dx, dy;
 } ocontrib;
 
+/* Marks, at a pixel holding near-threshold decisions, every Gaussian that
+ * contributes under one of the decision sets the forward pass considers (the
+ * primary one and each alternative of up to two flipped decisions) or whose
+ * own decision is near its threshold: only their per-pixel gradient terms
+ * depend on the decisions.  With more than two decisions, every candidate
+ * whose alpha reaches the lower edge of the alpha_min band is marked. */
+static void mark_touched(const oview *V, const int64_t *list, int64_t len, int u, int v, int32_t *touched)
+{
+    opix r;
+    composite(V, list, len, u, v, NULL, 0, &r);
+    int ne = r.nevents;
+    if (ne > 2) {
+        for (int64_t k = 0; k < len; k++) {
+            double a, G, dx, dy;
+            int cl;
+            alpha_at(V, list[k], (double)u, (double)v, &a, &G, &cl, &dx, &dy);
+            if (a >= V->s.alpha_min * (1.0 - V->ev_a)) {
+#pragma omp atomic write
+                touched[list[k]] = 1;
+            }
+        }
+        return;
+    }
+    oevent ev[2];
+    for (int e = 0; e < ne; e++) {
+        ev[e] = r.ev[e];
+#pragma omp atomic write
+        touched[list[ev[e].pos]] = 1;
+    }
+    /* decision sets: bit e of `set` flips event e */
+    for (int set = 0; set < (1 << ne); set++) {
+        oevent f[2];
+        int nf = 0;
+        for (int e = 0; e < ne; e++)
+            if (set & (1 << e)) f[nf++] = ev[e];
+        double T = 1.0;
+        for (int64_t k = 0; k < len; k++) {
+            int64_t i = list[k];
+            double a, G, dx, dy;
+            int cl;
+            alpha_at(V, i, (double)u, (double)v, &a, &G, &cl, &dx, &dy);
+            int skip = a < V->s.alpha_min;
+            if (nf && forced(f, nf, (int)k, 0)) skip = !skip;
+            if (skip) continue;
+            double Tn = T * (1.0 - a);
+            int stop = Tn < V->s.T_min;
+            if (nf && forced(f, nf, (int)k, 1)) stop = !stop;
+            if (stop) break;
+#pragma omp atomic write
+            touched[i] = 1;
+            T = Tn;
+        }
+    }
+}
+
 /* Reverse mode of one pixel given upstream gradients g[6] for r, g, b,
  * depth, alpha, uncertainty.  acc2d is indexed by Gaussian.  When touched is
  * not NULL and the pixel holds a near-threshold decision (the event bands of
@@ -963,18 +1018,7 @@ static void pixel_adjoint(const oview *V, const int64_t *list, int64_t len, int 
         m++;
         T = Tn;
     }
-    if (event && touched) {
-        for (int64_t k = 0; k < len; k++) {
-            int64_t i = list[k];
-            double a, G, dx, dy;
-            int cl;
-            alpha_at(V, i, (double)u, (double)v, &a, &G, &cl, &dx, &dy);
-            if (a >= V->s.alpha_min * (1.0 - V->ev_a)) {
-#pragma omp atomic write
-                touched[i] = 1;
-            }
-        }
-    }
+    if (event && touched) mark_touched(V, list, len, u, v, touched);
     /* suffix sums S_ch = sum_{j > i} v_j w_j */
     double S[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t k = m - 1; k >= 0; k--) {

@@ -504,11 +504,14 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
     }
     {
         Timer tm(f->ctx, 1, s);
+        // the last pass also lays the records' pair counts out in depth order
+        // (into inst_off), so that the scan below reads them in sequence
         f->order_in_alt = radix_sort(f->skey.as<uint32_t>(), f->order.as<uint32_t>(), f->skey2.as<uint32_t>(),
-                                     f->order2.as<uint32_t>(), f->ctr(C_REC), rc, 32, DEPTH_SORT_DIGIT, ws, s);
+                                     f->order2.as<uint32_t>(), f->ctr(C_REC), rc, 32, DEPTH_SORT_DIGIT, ws, s,
+                                     f->ntiles.as<uint32_t>(), f->inst_off.as<uint32_t>());
     }
-    scan_u32(f->ntiles.as<uint32_t>(), f->sorted_order(), f->inst_off.as<uint32_t>(), f->ctr(C_REC), rc,
-             f->ctr(C_INST), f->ctr(C_FLAGS), ScanWs{f->scan_ws.as<uint32_t>()}, s);
+    scan_u32(f->inst_off.as<uint32_t>(), nullptr, f->inst_off.as<uint32_t>(), f->ctr(C_REC), rc, f->ctr(C_INST),
+             f->ctr(C_FLAGS), ScanWs{f->scan_ws.as<uint32_t>()}, s);
     RTG_TRY(check_launch("depth sort"));
     if (eager) {
         uint32_t c[C_COUNT];

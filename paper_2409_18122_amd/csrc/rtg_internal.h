@@ -129,9 +129,11 @@ struct SortWs {
 int sort_blocks(uint64_t cap, int db);
 size_t sort_hist_words(uint64_t cap);
 // Stable sort of (key, value) pairs on the low nbits of the keys, in passes of
-// at most max_db (<= 11) bits; returns 1 if the result is in (k1, v1).
+// at most max_db (<= 11) bits; returns 1 if the result is in (k1, v1).  With
+// gsrc, the last pass also writes gout[i] = gsrc[value at sorted position i].
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
-               uint32_t cap, int nbits, int max_db, SortWs ws, hipStream_t s);
+               uint32_t cap, int nbits, int max_db, SortWs ws, hipStream_t s, const uint32_t* gsrc = nullptr,
+               uint32_t* gout = nullptr);
 
 // Instances of the depth-ordered records: tile keys and record ids, one per
 // tile a record's support meets (tiles tw x th).  Also empties ranges[0,

@@ -598,7 +598,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ vout,
                                                            const uint32_t* __restrict__ n_dev, uint32_t cap,
                                                            int shift, int bits, const uint32_t* __restrict__ hist,
-                                                           int block_major) {
+                                                           int block_major, const uint32_t* __restrict__ gsrc,
+                                                           uint32_t* __restrict__ gout) {
     constexpr int NB = 1 << DB;
     constexpr int DPT = NB / RS_THREADS > 0 ? NB / RS_THREADS : 1;  // digits per thread
     __shared__ uint32_t wh[RS_WAVES][NB];
@@ -710,6 +711,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                     uint32_t dst = wh[wv][d] + pos[j];
                     kout[dst] = k[j];
                     vout[dst] = v[j];
+                    if (gsrc) gout[dst] = gsrc[v[j]];
                 }
             }
         } else {
@@ -767,8 +769,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                 const uint32_t kk = s_k[i];
                 const uint32_t d = (kk >> shift) & mask;
                 const uint32_t dst = bbase[d] + (i - lst[d]);
+                const uint32_t vv = s_v[i];
                 kout[dst] = kk;
-                vout[dst] = s_v[i];
+                vout[dst] = vv;
+                if (gsrc) gout[dst] = gsrc[vv];
             }
             __syncthreads();
             for (int d = tid; d < NB; d += RS_THREADS) bbase[d] += tcnt[d];
@@ -781,14 +785,20 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
 
 // A block covers EM_ITEMS consecutive pairs and each thread EM_RUN
 // consecutive ones.  The depth-ordered records spanning the block are found
-// by one binary search over the pair offsets and their offsets staged in LDS;
-// a thread locates its first record there, positions a cursor on its first
-// pair (rows are walked once) and advances it pair by pair.  A record whose
-// support meets every tile of its box is enumerated in row-major order
-// directly.  Output is written in depth order, EM_RUN pairs per 16-byte store.
+// by one binary search over the pair offsets and their offsets staged in LDS.
+// A record whose support meets every tile of its box is enumerated in
+// row-major order directly.  For the others the block evaluates every tile
+// row of their rectangles once, in parallel (one support_row call per row),
+// into an LDS table of (first column, count) and its prefix; a thread then
+// finds the row of each of its pairs by binary search.  A block whose records
+// have more than EM_ROWS such rows falls back to a per-thread cursor that
+// walks the rows up to its first pair.  Output is written in depth order,
+// EM_RUN pairs per 16-byte store.
 constexpr int EM_THREADS = 256;
 constexpr int EM_RUN = 4;
 constexpr int EM_ITEMS = EM_THREADS * EM_RUN;
+constexpr int EM_ROWS = 2048;
+constexpr int EM_ROWS_PT = EM_ROWS / EM_THREADS;
 
 __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint32_t x) {
     // largest i < n with a[i] <= x (a[0] == 0 <= x)
@@ -1007,54 +1017,174 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
                                                                uint2* __restrict__ ranges, uint32_t tiles_cap,
                                                                uint32_t* __restrict__ flags) {
     __shared__ uint32_t s_off[EM_ITEMS + 1];
-    __shared__ uint32_t s_lo, s_n;
+    __shared__ uint32_t s_roff[EM_ITEMS + 1];  // first table row of each record (prefix of row counts)
+    __shared__ uint32_t s_row[EM_ROWS];        // first tile column | pairs of the row << 16
+    __shared__ uint32_t s_rpre[EM_ROWS + 1];   // pairs of all table rows before this one
+    __shared__ uint32_t ws[SC_THREADS / 64];
+    __shared__ uint32_t s_lo;
     // every tile starts empty; k_tile_ranges later fills the occupied ones
     // (nothing reads the ranges in between), and an overflow leaves them empty
     for (uint32_t t = blockIdx.x * EM_THREADS + threadIdx.x; t < tiles_cap; t += gridDim.x * EM_THREADS)
         ranges[t] = make_uint2(0u, 0u);
-    if (*flags & FLAG_REC_OVERFLOW) return;
+    if (*flags & (FLAG_REC_OVERFLOW | FLAG_COUNT_OVERFLOW)) return;
     const uint32_t R = min(*R_dev, rec_cap);
     const uint32_t Kall = *K_dev;
     if (threadIdx.x == 0 && blockIdx.x == 0 && Kall > inst_cap) atomicOr(flags, FLAG_INST_OVERFLOW);
     const uint32_t K = min(Kall, inst_cap);
     if (R == 0) return;
-    for (uint32_t k0 = blockIdx.x * EM_ITEMS; k0 < K; k0 += gridDim.x * EM_ITEMS) {
-        const uint32_t k1 = min(k0 + EM_ITEMS, K);  // exclusive
+    // each block takes one contiguous run of whole EM_ITEMS chunks, so that
+    // the records of a chunk follow those of the previous one: one search in
+    // global memory per block, then one coalesced load of the next EM_ITEMS + 1
+    // record offsets per chunk
+    const uint32_t per = (uint32_t)(((uint64_t)K + (uint64_t)gridDim.x * EM_ITEMS - 1) /
+                                    ((uint64_t)gridDim.x * EM_ITEMS)) * EM_ITEMS;
+    const uint32_t kbeg = (uint32_t)min<uint64_t>((uint64_t)blockIdx.x * per, K);
+    const uint32_t kend = (uint32_t)min<uint64_t>((uint64_t)kbeg + per, K);
+    if (kbeg >= kend) return;
+    if (threadIdx.x < 64) {
+        const uint32_t lo0 = wave_last_le(inst_off, R, kbeg);
+        if (threadIdx.x == 0) s_lo = lo0;
+    }
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += EM_ITEMS) {
+        const uint32_t k1 = min(k0 + EM_ITEMS, kend);  // exclusive
         __syncthreads();
-        // the first and last record spanning the block's pairs, one wave each
+        // the offsets of the records from the first one spanning the chunk
         // (every record owns at least one pair, so at most EM_ITEMS records
-        // span them)
-        if (threadIdx.x < 64) {
-            const uint32_t lo = wave_last_le(inst_off, R, k0);
-            if (threadIdx.x == 0) s_lo = lo;
-        } else if (threadIdx.x < 128) {
-            const uint32_t hi = wave_last_le(inst_off, R, k1 - 1);
-            if (threadIdx.x == 64) s_n = hi;
-        }
+        // span it); entries past the last record read as "after every pair"
+        const uint32_t lo = s_lo;
+        const uint32_t navail = min<uint32_t>(EM_ITEMS + 1, R - lo);
+        for (uint32_t q = threadIdx.x; q < EM_ITEMS + 1; q += EM_THREADS)
+            s_off[q] = q < navail ? inst_off[lo + q] : 0xffffffffu;
         __syncthreads();
-        const uint32_t lo = s_lo, nrec = s_n - s_lo + 1;
-        for (uint32_t i = threadIdx.x; i < nrec; i += EM_THREADS) s_off[i] = inst_off[lo + i];
+        const uint32_t nrec = last_le(s_off, navail, k1 - 1) + 1;
+        __syncthreads();
+        if (threadIdx.x == 0) s_lo = lo + last_le(s_off, navail, k1);  // the next chunk's first record
+        // table rows of the records (EM_RUN records per thread): every tile
+        // row of a record that is not enumerated directly
+        uint32_t nr[EM_RUN];
+        uint32_t nsum = 0;
+#pragma unroll
+        for (int q = 0; q < EM_RUN; q++) {
+            const uint32_t jr = threadIdx.x * EM_RUN + q;
+            nr[q] = 0;
+            if (jr < nrec) {
+                const EmitRec e = rec.emit[order[lo + jr]];
+                const uint32_t nx = (e.rect.x >> 16) - (e.rect.x & 0xffffu) + 1;
+                const uint32_t ny = (e.rect.y >> 16) - (e.rect.y & 0xffffu) + 1;
+                nr[q] = e.ntiles == nx * ny ? 0u : ny;
+            }
+            nsum += nr[q];
+        }
+        uint32_t total_rows;
+        uint32_t rbase = block_excl_scan(nsum, ws, total_rows);
+#pragma unroll
+        for (int q = 0; q < EM_RUN; q++) {
+            const uint32_t jr = threadIdx.x * EM_RUN + q;
+            if (jr < nrec) s_roff[jr] = rbase;
+            rbase += nr[q];
+        }
+        if (threadIdx.x == 0) s_roff[nrec] = total_rows;
+        const bool staged = total_rows <= (uint32_t)EM_ROWS;
+        if (staged) {
+            __syncthreads();
+            for (uint32_t t = threadIdx.x; t < total_rows; t += EM_THREADS) {
+                const uint32_t jr = last_le(s_roff, nrec, t);
+                const EmitRec e = rec.emit[order[lo + jr]];
+                const SupportRows S = support_setup(e.g0, e.g1, e.pbox, log2_amin);
+                const uint2 fc = support_row(S, (e.rect.y & 0xffffu) + (t - s_roff[jr]), tws, ths);
+                s_row[t] = fc.x | (fc.y << 16);
+            }
+            __syncthreads();
+            // exclusive prefix of the row counts over the whole table
+            uint32_t c[EM_ROWS_PT];
+            uint32_t csum = 0;
+#pragma unroll
+            for (int q = 0; q < EM_ROWS_PT; q++) {
+                const uint32_t t = threadIdx.x * EM_ROWS_PT + q;
+                c[q] = t < total_rows ? s_row[t] >> 16 : 0u;
+                csum += c[q];
+            }
+            uint32_t all;
+            uint32_t pre = block_excl_scan(csum, ws, all);
+#pragma unroll
+            for (int q = 0; q < EM_ROWS_PT; q++) {
+                const uint32_t t = threadIdx.x * EM_ROWS_PT + q;
+                if (t < total_rows) s_rpre[t] = pre;
+                pre += c[q];
+            }
+            if (threadIdx.x == 0) s_rpre[total_rows] = all;
+        }
         __syncthreads();
         const uint32_t kb = k0 + threadIdx.x * EM_RUN;
         if (kb >= k1) continue;
-        uint32_t j = last_le(s_off, nrec, kb);
-        PairCursor c;
-        cursor_open(c, rec, views, order[lo + j], kb - s_off[j], tws, ths, log2_amin, flags);
         uint32_t tk[EM_RUN], tr[EM_RUN];
         const int n = (int)min<uint32_t>(EM_RUN, k1 - kb);
+        if (staged) {
+            uint32_t j = last_le(s_off, nrec, kb);
+            uint32_t r = 0xffffffffu, base = 0, t0 = 0, t1 = 0, tx0 = 0, ty0 = 0, nx = 1, toff = 0, tiles_x = 0;
 #pragma unroll
-        for (int q = 0; q < EM_RUN; q++) {
-            if (q >= n) break;
-            if (q > 0) {
-                if (j + 1 < nrec && kb + q >= s_off[j + 1]) {
-                    j++;
-                    cursor_open(c, rec, views, order[lo + j], 0, tws, ths, log2_amin, flags);
-                } else {
-                    cursor_next(c, tws, ths);
+            for (int q = 0; q < EM_RUN; q++) {
+                if (q >= n) break;
+                const uint32_t kq = kb + q;
+                while (j + 1 < nrec && kq >= s_off[j + 1]) j++;
+                const uint32_t rj = order[lo + j];
+                if (rj != r) {
+                    r = rj;
+                    const EmitRec e = rec.emit[r];
+                    tx0 = e.rect.x & 0xffffu;
+                    nx = (e.rect.x >> 16) - tx0 + 1;
+                    ty0 = e.rect.y & 0xffffu;
+                    const ViewDev& V = views[e.view];
+                    toff = V.tile_off;
+                    tiles_x = (uint32_t)V.tiles_x;
+                    t0 = s_roff[j];
+                    t1 = s_roff[j + 1];
+                    base = s_rpre[t0];
                 }
+                const uint32_t li = kq - s_off[j];
+                uint32_t tile;
+                if (t0 == t1) {  // every tile of the rectangle
+                    tile = toff + (ty0 + li / nx) * tiles_x + tx0 + li % nx;
+                } else if (s_rpre[t1] == base) {
+                    // a support that meets no tile still owns one pair, its
+                    // box's first tile; anything else is a counting mismatch
+                    if (li != 0) atomicOr(flags, FLAG_BIN_MISMATCH);
+                    tile = toff + ty0 * tiles_x + tx0;
+                } else {
+                    // the last row whose pairs start at or before li (empty
+                    // rows share the next row's start, so it is not empty)
+                    uint32_t a = t0, b = t1 - 1;
+                    while (a < b) {
+                        const uint32_t m = a + (b - a + 1) / 2;
+                        if (s_rpre[m] - base <= li) a = m;
+                        else b = m - 1;
+                    }
+                    const uint32_t row = s_row[a];
+                    const uint32_t col = (row & 0xffffu) + (li - (s_rpre[a] - base));
+                    if (li - (s_rpre[a] - base) >= (row >> 16)) atomicOr(flags, FLAG_BIN_MISMATCH);
+                    tile = toff + (ty0 + (a - t0)) * tiles_x + col;
+                }
+                tk[q] = tile;
+                tr[q] = r;
             }
-            tk[q] = cursor_tile(c);
-            tr[q] = c.r;
+        } else {
+            uint32_t j = last_le(s_off, nrec, kb);
+            PairCursor c;
+            cursor_open(c, rec, views, order[lo + j], kb - s_off[j], tws, ths, log2_amin, flags);
+#pragma unroll
+            for (int q = 0; q < EM_RUN; q++) {
+                if (q >= n) break;
+                if (q > 0) {
+                    if (j + 1 < nrec && kb + q >= s_off[j + 1]) {
+                        j++;
+                        cursor_open(c, rec, views, order[lo + j], 0, tws, ths, log2_amin, flags);
+                    } else {
+                        cursor_next(c, tws, ths);
+                    }
+                }
+                tk[q] = cursor_tile(c);
+                tr[q] = c.r;
+            }
         }
         if (n == EM_RUN) {
 #pragma unroll
@@ -1071,18 +1201,48 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
     }
 }
 
+// A tile's range starts where the sorted key changes from the previous one
+// and ends where it changes to the next.  Each thread reads four consecutive
+// keys with one 16-byte load; the neighbours across thread boundaries come
+// from the adjacent lanes (lane 0 and lane 63 load theirs).  Keys are stored
+// 16-byte aligned.
+__device__ __forceinline__ void range_edges(uint32_t i, uint32_t t, uint32_t prev, uint32_t next, uint32_t K,
+                                            uint2* __restrict__ ranges, uint32_t tiles_cap) {
+    if (t >= tiles_cap) return;
+    if (i == 0 || prev != t) ranges[t].x = i;
+    if (i + 1 == K || next != t) ranges[t].y = i + 1;
+}
+
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ K_dev, uint32_t cap,
                                                      uint2* __restrict__ ranges, uint32_t tiles_cap,
                                                      const uint32_t* __restrict__ flags) {
     if (*flags) return;  // an overflowed binning leaves the ranges empty
-    uint32_t K = min(*K_dev, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
-        uint32_t t = key[i];
-        if (t >= tiles_cap) continue;
-        if (i == 0 || key[i - 1] != t) ranges[t].x = i;
-        if (i + 1 == K || key[i + 1] != t) ranges[t].y = i + 1;
+    const uint32_t K = min(*K_dev, cap);
+    const uint32_t n4 = K / 4;  // whole groups of four keys
+    const uint32_t lane = lane_id();
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // the loop bound is rounded up to whole waves so that every lane of a
+    // wave takes part in the shuffles of every round
+    const uint32_t nwave = (n4 + 63) / 64 * 64;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nwave; g += stride) {
+        const bool live = g < n4;
+        const uint32_t i = 4 * g;
+        const uint4 k = live ? *reinterpret_cast<const uint4*>(key + i) : make_uint4(0u, 0u, 0u, 0u);
+        uint32_t prev = (uint32_t)__shfl_up((int)k.w, 1, 64);
+        uint32_t next = (uint32_t)__shfl_down((int)k.x, 1, 64);
+        if (live && lane == 0 && i > 0) prev = key[i - 1];
+        if (live && (lane == 63 || g + 1 == n4)) next = i + 4 < K ? key[i + 4] : 0u;
+        if (live) {
+            range_edges(i, k.x, prev, k.y, K, ranges, tiles_cap);
+            range_edges(i + 1, k.y, k.x, k.z, K, ranges, tiles_cap);
+            range_edges(i + 2, k.z, k.y, k.w, K, ranges, tiles_cap);
+            range_edges(i + 3, k.w, k.z, next, K, ranges, tiles_cap);
+        }
     }
+    // the last K % 4 keys
+    const uint32_t i = 4 * n4 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < K) range_edges(i, key[i], i > 0 ? key[i - 1] : 0u, i + 1 < K ? key[i + 1] : 0u, K, ranges, tiles_cap);
 }
 
 // ------------------------------------------------------------ compositing
@@ -1483,6 +1643,9 @@ __device__ __forceinline__ void add_g2d(double* g2d, uint32_t r, const float* t)
 // < 1, 1 - a_i is a normal number well away from zero and the hardware
 // reciprocal (within 1 ulp) stands in for the correctly rounded division; T
 // only scales gradient terms here and decides nothing.
+// AU: the alpha and uncertainty images carry gradients too (otherwise their
+// terms and running sums are left out altogether).
+template <bool AU>
 __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float w1, float w2, float4 g1,
                                           float4 at, float ui, float amax, float kq, float gr, float gg, float gb,
                                           float gd, float ga, float gu, float& T, float& S0, float& S1, float& S2,
@@ -1494,8 +1657,10 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
     da = fmaf(gg, at.y * Ti - S1 * inv, da);
     da = fmaf(gb, at.z * Ti - S2 * inv, da);
     da = fmaf(gd, at.w * Ti - S3 * inv, da);
-    da = fmaf(ga, Ti - S4 * inv, da);
-    da = fmaf(gu, ui * Ti - S5 * inv, da);
+    if constexpr (AU) {
+        da = fmaf(ga, Ti - S4 * inv, da);
+        da = fmaf(gu, ui * Ti - S5 * inv, da);
+    }
     acc[6] = fmaf(gr, w, acc[6]);
     acc[7] = fmaf(gg, w, acc[7]);
     acc[8] = fmaf(gb, w, acc[8]);
@@ -1504,8 +1669,10 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
     S1 = fmaf(at.y, w, S1);
     S2 = fmaf(at.z, w, S2);
     S3 = fmaf(at.w, w, S3);
-    S4 += w;
-    S5 = fmaf(ui, w, S5);
+    if constexpr (AU) {
+        S4 += w;
+        S5 = fmaf(ui, w, S5);
+    }
     T = Ti;
     if (g1.w * G <= amax) {
         acc[5] = fmaf(da, G, acc[5]);
@@ -1527,8 +1694,8 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
 // the splats whose support can reach its blocks (ballot masks per batch).  Per
 // splat, the lane sums its pixels' contributions, the wave reduces them once
 // with DPP and one lane adds the 10 totals to the record's binary64 gradient.
-template <int TW, int TH, int NW>
-__global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
+template <int TW, int TH, int NW, bool AU>
+__global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec, Records rec,
                                                         SetDev st, const float* __restrict__ T_final,
@@ -1556,9 +1723,14 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const uint2 rg = ranges[tile];
     const uint64_t P = (uint64_t)W * H;
-    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63), wave = NW == 1 ? 0 : (int)(threadIdx.x >> 6);
 
-    float px[PPT], py[PPT], T[PPT];
+    // pixel j of this lane: (px0 + bx(j), py0 + by(j)), block offsets that
+    // are constants when the tile has one wave
+    const float px0 = (float)(tx * TW + (lane & 7)), py0 = (float)(ty * TH + (lane >> 3));
+    auto bx = [&](int j) { return (float)(((wave * PPT + j) % (TW / 8)) * 8); };
+    auto by = [&](int j) { return (float)(((wave * PPT + j) / (TW / 8)) * 8); };
+    float T[PPT];
     uint32_t last[PPT];
     float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
     float S0[PPT], S1[PPT], S2[PPT], S3[PPT], S4[PPT], S5[PPT];
@@ -1573,8 +1745,6 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
         wr0 = min(wr0, by0);
         wr1 = max(wr1, by0 + 7);
         const int u = bx0 + (lane & 7), v = by0 + (lane >> 3);
-        px[j] = (float)u;
-        py[j] = (float)v;
         T[j] = 1.0f;
         last[j] = 0;
         gr[j] = gg[j] = gb[j] = gd[j] = ga[j] = gu[j] = 0.0f;
@@ -1590,8 +1760,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
                 gb[j] = cb[2 * P];
             }
             if (d_depth) gd[j] = d_depth[pix];
-            if (d_alpha) ga[j] = d_alpha[pix];
-            if (d_unc) gu[j] = d_unc[pix];
+            if (AU && d_alpha) ga[j] = d_alpha[pix];
+            if (AU && d_unc) gu[j] = d_unc[pix];
         }
         mylast = max(mylast, last[j]);
     }
@@ -1619,7 +1789,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
                 s_g0[threadIdx.x] = e.g0;
                 s_g1[threadIdx.x] = e.g1;
                 s_at[threadIdx.x] = rec.attr[r];
-                s_u[threadIdx.x] = __uint_as_float(e.unc);
+                if (AU) s_u[threadIdx.x] = __uint_as_float(e.unc);
             }
         }
         __syncthreads();
@@ -1645,7 +1815,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
                 sg0[q] = s_g0[k];
                 sg1[q] = s_g1[k];
                 sat[q] = s_at[k];
-                su[q] = s_u[k];
+                su[q] = AU ? s_u[k] : 0.0f;
                 sr[q] = s_r[k];
                 spos[q] = ks[q] < 0 ? 0xffffffffu : (uint32_t)(bstart + ks[q]);
             }
@@ -1664,7 +1834,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
                 bool need = false;
 #pragma unroll
                 for (int q = 0; q < BWD_STEP; q++) {
-                    a[q] = splat_alpha(sg0[q], sg1[q], px[j], py[j], amax, G[q], dx[q], dy[q], w1[q], w2[q]);
+                    a[q] = splat_alpha(sg0[q], sg1[q], px0 + bx(j), py0 + by(j), amax, G[q], dx[q], dy[q], w1[q],
+                                       w2[q]);
                     ok[q] = spos[q] < last[j] && a[q] >= st.alpha_min;
                     need = need || (spos[q] < last[j] && near_amin(a[q], st.alpha_min));
                 }
@@ -1672,13 +1843,13 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const ViewDev* __restric
 #pragma unroll
                     for (int q = 0; q < BWD_STEP; q++)
                         if (spos[q] < last[j] && near_amin(a[q], st.alpha_min))
-                            ok[q] = kept64(sg0[q], sg1[q], rec.q64, sr[q], px[j], py[j], st);
+                            ok[q] = kept64(sg0[q], sg1[q], rec.q64, sr[q], px0 + bx(j), py0 + by(j), st);
                 }
 #pragma unroll
                 for (int q = 0; q < BWD_STEP; q++) {
                     if (ok[q]) {
                         any[q] = true;
-                        bwd_pixel(a[q], G[q], dx[q], dy[q], w1[q], w2[q], sg1[q], sat[q], su[q], amax, kq, gr[j],
+                        bwd_pixel<AU>(a[q], G[q], dx[q], dy[q], w1[q], w2[q], sg1[q], sat[q], su[q], amax, kq, gr[j],
                                   gg[j], gb[j], gd[j], ga[j], gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j],
                                   acc[q]);
                     }
@@ -2498,7 +2669,7 @@ size_t sort_hist_words(uint64_t cap) {
 
 template <int DB>
 static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, const uint32_t* n_dev, uint32_t cap,
-                    int nb, int shift, int bits, SortWs ws, hipStream_t s) {
+                    int nb, int shift, int bits, SortWs ws, const uint32_t* gsrc, uint32_t* gout, hipStream_t s) {
     const int fused = nb <= RS_FUSED_BLOCKS;
     k_rs_upsweep<DB><<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, bits, ws.hist, fused);
     if (!fused) {
@@ -2512,23 +2683,27 @@ static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, cons
     }
     // 8-bit passes stage their scatter in LDS; the 11-bit one writes directly (its
     // per-wave tables already take 32 KB of LDS)
-    k_rs_scatter<DB, DB == 8><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused);
+    k_rs_scatter<DB, DB == 8><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused,
+                                                         gsrc, gout);
 }
 
 // The nbits are split into the fewest passes of at most max_db bits, as
 // evenly as possible; passes of up to 8 bits use 256 bins.
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev, uint32_t cap,
-               int nbits, int max_db, SortWs ws, hipStream_t s) {
+               int nbits, int max_db, SortWs ws, hipStream_t s, const uint32_t* gsrc, uint32_t* gout) {
     max_db = std::max(1, std::min(max_db, RS_MAX_DB));
     const int passes = std::max(1, (nbits + max_db - 1) / max_db);
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     int shift = 0;
     for (int p = 0; p < passes; p++) {
         const int bits = nbits / passes + (p < nbits % passes ? 1 : 0);
+        const bool last = p + 1 == passes;
+        const uint32_t* gs = last ? gsrc : nullptr;
+        uint32_t* go = last ? gout : nullptr;
         if (bits <= 8)
-            rs_pass<8>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, 8), shift, std::max(bits, 1), ws, s);
+            rs_pass<8>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, 8), shift, std::max(bits, 1), ws, gs, go, s);
         else
-            rs_pass<RS_MAX_DB>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, RS_MAX_DB), shift, bits, ws, s);
+            rs_pass<RS_MAX_DB>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, RS_MAX_DB), shift, bits, ws, gs, go, s);
         shift += bits;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -2548,8 +2723,8 @@ void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_c
 
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap, uint2* ranges,
                  uint32_t tiles_cap, const uint32_t* flags, hipStream_t s) {
-    k_tile_ranges<<<grid_for(inst_cap, 256, 8192), 256, 0, s>>>(tile_key, K_dev, inst_cap, ranges, tiles_cap,
-                                                                flags);
+    k_tile_ranges<<<grid_for((inst_cap + 3) / 4, 256, 16384), 256, 0, s>>>(tile_key, K_dev, inst_cap, ranges,
+                                                                           tiles_cap, flags);
 }
 
 void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
@@ -2597,10 +2772,18 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
     (void)batch;  // the backward stages 64 splats per wave of the tile
     if (tiles_total == 0) return;
     const int nw = backward_waves(tw, th, tiles_total);
+    const bool au = d_alpha != nullptr || d_unc != nullptr;
 #define RTG_BWD_LAUNCH(TW_, TH_, NW_)                                                                          \
-    k_render_bwd<TW_, TH_, NW_><<<tiles_total, 64 * NW_, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,      \
-                                                                  T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, \
-                                                                  g2d, flags)
+    do {                                                                                                       \
+        if (au)                                                                                                \
+            k_render_bwd<TW_, TH_, NW_, true><<<tiles_total, 64 * NW_, 0, s>>>(                                \
+                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
+                flags);                                                                                        \
+        else                                                                                                   \
+            k_render_bwd<TW_, TH_, NW_, false><<<tiles_total, 64 * NW_, 0, s>>>(                               \
+                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
+                flags);                                                                                        \
+    } while (0)
     if (tw == 8 && th == 8) {
         RTG_BWD_LAUNCH(8, 8, 1);
     } else if (tw == 32 && th == 8) {

@@ -192,6 +192,43 @@ def test_keys_bit_exact(raster, rctx, tile):
         f.close()
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_keys_tall_records(raster, rctx, tile):
+    # five needle-thin, slightly tilted Gaussians spanning the whole height of
+    # a 1024 x 16384 view: each record meets ~2 tiles on each of up to 2048
+    # tile rows, so the pair-emission blocks that hold parts of two records
+    # have more support rows than they tabulate and walk them per thread
+    n = 5
+    rng = np.random.default_rng(17)
+    g = {"means": np.zeros((3, n), np.float32),
+         "log_scales": np.tile(np.array([[-3.5], [2.0], [-3.5]], np.float32), (1, n)),
+         "quats": np.zeros((4, n), np.float32), "opacity": np.full(n, 0.9, np.float32),
+         "colors": rng.random((3, n)).astype(np.float32), "uncert": rng.random(n).astype(np.float32)}
+    ang = np.array([0.004, -0.006, 0.01, 0.0025, -0.012])
+    g["quats"][0] = np.cos(ang / 2)
+    g["quats"][3] = np.sin(ang / 2)  # about the optical axis
+    g["means"][0] = np.array([-0.8, -0.3, 0.1, 0.4, 0.9], np.float32)
+    g["means"][2] = np.array([3.0, 3.2, 2.9, 3.1, 3.05], np.float32)
+    cams = [scenes.make_camera(1024, 16384, 1000.0, 1000.0, 512.0, 8192.0)]
+    say(f"tall records, tile {tile}")
+    dev = raster.to_device(g)
+    f = raster.Frame(rctx, dev, cams, S(tile))
+    f.bin_sort()
+    keys, vals, _ = f.export()
+    f.close()
+    keys = keys.cpu().numpy().view(np.uint64)
+    vals = vals.cpu().numpy().view(np.uint32)
+    k_box, v_box = oracle.keys(g, cams, S(tile), tile)
+    k_sup, v_sup = oracle.keys(g, cams, S(tile), tile, support=True)
+    got = pair_ids(keys, vals)
+    keep = np.isin(pair_ids(k_box, v_box), got)
+    assert keep.sum() == len(got) and len(np.unique(got)) == len(got)
+    assert np.array_equal(keys, k_box[keep]) and np.array_equal(vals, v_box[keep])
+    assert np.isin(pair_ids(k_sup, v_sup), got).all()
+    say(f"tall records {tile}: box {len(k_box)} support {len(k_sup)} gpu {len(keys)}")
+    assert len(keys) <= len(k_sup) + max(8, len(k_sup) // 20)
+
+
 # ---------------------------------------------------------- loss, backward
 
 def test_c2_loss_parity(raster, rctx):
