@@ -1301,6 +1301,28 @@ __device__ __forceinline__ void wave_masks(const uint2* s_pb, const float4* s_g0
         m[c] = __ballot(hit);
     }
 }
+// The same selection as a list: the indices of the staged splats that can
+// reach the wave's pixel rectangle, in ascending order, written to list[0, n)
+// (n returned, wave-uniform).  A loop over the list needs no scalar
+// bit-scanning per splat.
+template <int NT, bool ELL>
+__device__ __forceinline__ int wave_list(const uint2* s_pb, const float4* s_g0, const float4* s_g1,
+                                         float log2_amin, int cnt, int c0, int c1, int r0, int r1,
+                                         uint16_t* list) {
+    const int lane = (int)lane_id();
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < (NT + 63) / 64; c++) {
+        const int e = c * 64 + lane;
+        bool hit = e < cnt && box_meets(s_pb[e], c0, c1, r0, r1);
+        if (ELL && hit) hit = support_meets_rect(s_g0[e], s_g1[e], log2_amin, c0, c1, r0, r1);
+        const uint64_t m = __ballot(hit);
+        if (hit) list[n + (int)__popcll(m & lanemask_lt())] = (uint16_t)e;
+        n += (int)__popcll(m);
+    }
+    return n;
+}
+
 // Next P set bits of a wave-uniform mask (entries past the last are -1).
 template <int P>
 __device__ __forceinline__ void pop_n(uint64_t& mm, int base, int (&ks)[P]) {
@@ -1351,20 +1373,21 @@ __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __re
 // B splats are staged per batch (B <= TW * TH; threads below B load them).
 // Register budget: at most 80 VGPRs, six waves per SIMD (a 640x480 frame of
 // 16x16 tiles brings 4.7 waves per SIMD, larger frames many more).
-template <int TW, int TH, int B>
+// UNC: the uncertainty image is requested (otherwise it is not composited).
+template <int TW, int TH, int B, bool UNC>
 __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ inst_rec,
                                                         Records rec, SetDev st, RenderOut out,
                                                         const uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
-    constexpr int NC = (B + 63) / 64;
     static_assert(B <= NT, "batch larger than the tile");
     if (flags && *flags) return;
     __shared__ float4 s_g0[B], s_g1[B], s_at[B];
     __shared__ float s_u[B];
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
+    __shared__ uint16_t s_list[NT / 64 * B];
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -1392,59 +1415,58 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
             s_g0[threadIdx.x] = e.g0;
             s_g1[threadIdx.x] = e.g1;
             s_at[threadIdx.x] = rec.attr[r];
-            s_u[threadIdx.x] = __uint_as_float(e.unc);
+            if (UNC) s_u[threadIdx.x] = __uint_as_float(e.unc);
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);
-        uint64_t m[NC] = {};
-        if (__ballot(!done)) wave_masks<B, FWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
+        uint16_t* my = s_list + (threadIdx.x >> 6) * B;
+        int nl = 0;
+        if (__ballot(!done)) nl = wave_list<B, FWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, my);
+        __syncthreads();  // the wave's list is in LDS
+        for (int i = 0; i < nl; i += FWD_STEP) {
+            if (!__ballot(!done)) break;
+            int ks[FWD_STEP];
 #pragma unroll
-        for (int c = 0; c < NC; c++) {
-            uint64_t mm = m[c];
-            while (mm && !done) {
-                int ks[FWD_STEP];
-                pop_n<FWD_STEP>(mm, c * 64, ks);
-                float as[FWD_STEP];
-                bool ok[FWD_STEP];
-                bool need = false;
+            for (int q = 0; q < FWD_STEP; q++) ks[q] = i + q < nl ? (int)my[i + q] : -1;
+            float as[FWD_STEP];
+            bool ok[FWD_STEP];
+            bool need = false;
 #pragma unroll
-                for (int q = 0; q < FWD_STEP; q++) {
-                    const int k = ks[q] < 0 ? ks[0] : ks[q];
-                    float G, dx, dy, w1, w2;
-                    as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
-                    ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
-                    need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
-                }
-                if (__ballot(need)) {
-#pragma unroll
-                    for (int q = 0; q < FWD_STEP; q++) {
-                        const int k = ks[q] < 0 ? ks[0] : ks[q];
-                        if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
-                            ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
-                    }
-                }
-                // predicated, not branched: the update is a few FMAs
+            for (int q = 0; q < FWD_STEP; q++) {
+                const int k = ks[q] < 0 ? ks[0] : ks[q];
+                float G, dx, dy, w1, w2;
+                as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
+                ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
+                need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
+            }
+            if (__ballot(need)) {
 #pragma unroll
                 for (int q = 0; q < FWD_STEP; q++) {
                     const int k = ks[q] < 0 ? ks[0] : ks[q];
-                    const float a = as[q];
-                    const float Tn = T * (1.0f - a);
-                    const bool take = ok[q] && !done;
-                    const bool stop = take && Tn < st.T_min;
-                    const bool use = take && !stop;
-                    done = done || stop;
-                    const float w = a * T;
-                    const float4 at = s_at[k];
-                    const float uk = s_u[k];
-                    c0 = use ? fmaf(at.x, w, c0) : c0;
-                    c1 = use ? fmaf(at.y, w, c1) : c1;
-                    c2 = use ? fmaf(at.z, w, c2) : c2;
-                    dd = use ? fmaf(at.w, w, dd) : dd;
-                    uu = use ? fmaf(uk, w, uu) : uu;
-                    T = use ? Tn : T;
-                    last = use ? b - rg.x + (uint32_t)k + 1 : last;
-                    ncontrib += use ? 1u : 0u;
+                    if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
+                        ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
                 }
+            }
+            // predicated, not branched: the update is a few FMAs
+#pragma unroll
+            for (int q = 0; q < FWD_STEP; q++) {
+                const int k = ks[q] < 0 ? ks[0] : ks[q];
+                const float a = as[q];
+                const float Tn = T * (1.0f - a);
+                const bool take = ok[q] && !done;
+                const bool stop = take && Tn < st.T_min;
+                const bool use = take && !stop;
+                done = done || stop;
+                const float w = a * T;
+                const float4 at = s_at[k];
+                c0 = use ? fmaf(at.x, w, c0) : c0;
+                c1 = use ? fmaf(at.y, w, c1) : c1;
+                c2 = use ? fmaf(at.z, w, c2) : c2;
+                dd = use ? fmaf(at.w, w, dd) : dd;
+                if (UNC) uu = use ? fmaf(s_u[k], w, uu) : uu;
+                T = use ? Tn : T;
+                last = use ? b - rg.x + (uint32_t)k + 1 : last;
+                ncontrib += use ? 1u : 0u;
             }
         }
     }
@@ -2043,7 +2065,7 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
                                                const uint32_t* __restrict__ inst_rec, const Records& rec,
                                                const SetDev& st, int mode, double* __restrict__ partial,
                                                float4* s_g0, float4* s_g1, float* s_u, uint32_t* s_r,
-                                               uint2* s_pb, double* ws) {
+                                               uint2* s_pb, double* ws, uint16_t* s_list) {
     constexpr int NT = TW * TH;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -2058,7 +2080,6 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
     const uint2 rg = ranges[tile];
     float T = 1.0f, uu = 0.0f;
     bool done = !inside;
-    constexpr int NC = (B + 63) / 64;
     for (uint32_t b = rg.x; b < rg.y; b += B) {
         if (__syncthreads_count(done) == NT) break;
         uint32_t idx = b + threadIdx.x;
@@ -2073,48 +2094,48 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);
-        uint64_t m[NC] = {};
-        if (__ballot(!done)) wave_masks<B, SCORE_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, m);
+        uint16_t* my = s_list + (threadIdx.x >> 6) * B;
+        int nl = 0;
+        if (__ballot(!done)) nl = wave_list<B, SCORE_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, my);
+        __syncthreads();  // the wave's list is in LDS
+        for (int i = 0; i < nl; i += SCORE_STEP) {
+            if (!__ballot(!done)) break;
+            int ks[SCORE_STEP];
 #pragma unroll
-        for (int c = 0; c < NC; c++) {
-            uint64_t mm = m[c];
-            while (mm && !done) {
-                int ks[SCORE_STEP];
-                pop_n<SCORE_STEP>(mm, c * 64, ks);
-                float as[SCORE_STEP];
-                bool ok[SCORE_STEP];
-                bool need = false;
+            for (int q = 0; q < SCORE_STEP; q++) ks[q] = i + q < nl ? (int)my[i + q] : -1;
+            float as[SCORE_STEP];
+            bool ok[SCORE_STEP];
+            bool need = false;
 #pragma unroll
-                for (int q = 0; q < SCORE_STEP; q++) {
-                    const int k = ks[q] < 0 ? ks[0] : ks[q];
-                    float G, dx, dy, w1, w2;
-                    as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
-                    ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
-                    need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
-                }
-                if (__ballot(need)) {
-#pragma unroll
-                    for (int q = 0; q < SCORE_STEP; q++) {
-                        const int k = ks[q] < 0 ? ks[0] : ks[q];
-                        if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
-                            ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
-                    }
-                }
-                // predicated, not branched
+            for (int q = 0; q < SCORE_STEP; q++) {
+                const int k = ks[q] < 0 ? ks[0] : ks[q];
+                float G, dx, dy, w1, w2;
+                as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
+                ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
+                need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
+            }
+            if (__ballot(need)) {
 #pragma unroll
                 for (int q = 0; q < SCORE_STEP; q++) {
                     const int k = ks[q] < 0 ? ks[0] : ks[q];
-                    const float a = as[q];
-                    const float Tn = T * (1.0f - a);
-                    const bool take = ok[q] && !done;
-                    const bool stop = take && Tn < st.T_min;
-                    const bool use = take && !stop;
-                    done = done || stop;
-                    const float uk = s_u[k];
-                    const float wk = mode ? 1.0f : a * T;
-                    uu = use ? fmaf(uk, wk, uu) : uu;
-                    T = use ? Tn : T;
+                    if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
+                        ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
                 }
+            }
+            // predicated, not branched
+#pragma unroll
+            for (int q = 0; q < SCORE_STEP; q++) {
+                const int k = ks[q] < 0 ? ks[0] : ks[q];
+                const float a = as[q];
+                const float Tn = T * (1.0f - a);
+                const bool take = ok[q] && !done;
+                const bool stop = take && Tn < st.T_min;
+                const bool use = take && !stop;
+                done = done || stop;
+                const float uk = s_u[k];
+                const float wk = mode ? 1.0f : a * T;
+                uu = use ? fmaf(uk, wk, uu) : uu;
+                T = use ? Tn : T;
             }
         }
     }
@@ -2141,8 +2162,9 @@ __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restri
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
+    __shared__ uint16_t s_list[NT / 64 * B];
     score_one_tile<TW, TH, B>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, mode, partial,
-                              s_g0, s_g1, s_u, s_r, s_pb, ws);
+                              s_g0, s_g1, s_u, s_r, s_pb, ws, s_list);
 }
 
 template <int TW, int TH, int B>
@@ -2161,6 +2183,7 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
+    __shared__ uint16_t s_list[NT / 64 * B];
     __shared__ uint32_t s_item;
     const uint32_t total = hdr->tiles_total;
     const int nv = (int)hdr->n_views;
@@ -2171,7 +2194,7 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
         __syncthreads();
         if (item >= total) break;
         score_one_tile<TW, TH, B>(views, nv, item, ranges, inst_rec, rec, st, mode, partial, s_g0, s_g1, s_u, s_r,
-                                  s_pb, ws);
+                                  s_pb, ws, s_list);
     }
 }
 
@@ -2731,9 +2754,13 @@ void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views
                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
                     RenderOut out, const uint32_t* flags, hipStream_t s) {
     if (tiles_total == 0) return;
-    RTG_BATCH_DISPATCH(TW, TH, B, (k_render_fwd<TW, TH, B><<<tiles_total, TW * TH, 0, s>>>(views, n_views, ranges,
-                                                                                          inst_rec, rec, st, out,
-                                                                                          flags)));
+    if (out.unc) {
+        RTG_BATCH_DISPATCH(TW, TH, B, (k_render_fwd<TW, TH, B, true><<<tiles_total, TW * TH, 0, s>>>(
+                                          views, n_views, ranges, inst_rec, rec, st, out, flags)));
+    } else {
+        RTG_BATCH_DISPATCH(TW, TH, B, (k_render_fwd<TW, TH, B, false><<<tiles_total, TW * TH, 0, s>>>(
+                                          views, n_views, ranges, inst_rec, rec, st, out, flags)));
+    }
 }
 
 void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
