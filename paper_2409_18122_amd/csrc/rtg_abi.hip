@@ -360,16 +360,16 @@ struct rtg_frame {
     int64_t K = -1;     // instances (-1 before binning)
     uint32_t rec_cap = 0, inst_cap = 0, tiles_cap = 0;
     bool rendered = false;
+    bool scoring = false;  // only scored: records carry no colour / depth attributes
     int order_in_alt = 0, inst_in_alt = 0;
 
     Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist;
-    Buf emit, q64, attr, gid, view, dkey, ntiles, skey, skey2, order, order2;
+    Buf emit, q64, attr, ntiles, skey, skey2, order, order2;
     Buf inst_off, tkey, tkey2, irec, irec2, ranges;
     Buf T_final, n_last, g2d, loss_part, score_part, ssim_maps;
 
     Records records() const {
-        return Records{emit.as<EmitRec>(), q64.as<double4>(), attr.as<float4>(), gid.as<uint32_t>(),
-                       view.as<uint32_t>(), dkey.as<uint32_t>(), ntiles.as<uint32_t>()};
+        return Records{emit.as<EmitRec>(), q64.as<double4>(), attr.as<float4>(), ntiles.as<uint32_t>()};
     }
     uint32_t* sorted_order() const { return order_in_alt ? order2.as<uint32_t>() : order.as<uint32_t>(); }
     uint32_t* sorted_tkey() const { return inst_in_alt ? tkey2.as<uint32_t>() : tkey.as<uint32_t>(); }
@@ -427,10 +427,7 @@ rtg_status alloc_records(rtg_frame* f, uint32_t rc) {
     size_t r = std::max<uint32_t>(rc, 1);
     RTG_TRY(f->emit.ensure(ctx, sizeof(EmitRec) * r));
     RTG_TRY(f->q64.ensure(ctx, 32 * r));
-    RTG_TRY(f->attr.ensure(ctx, 16 * r));
-    RTG_TRY(f->gid.ensure(ctx, 4 * r));
-    RTG_TRY(f->view.ensure(ctx, 4 * r));
-    RTG_TRY(f->dkey.ensure(ctx, 4 * r));
+    if (!f->scoring) RTG_TRY(f->attr.ensure(ctx, 16 * r));
     RTG_TRY(f->ntiles.ensure(ctx, 4 * r));
     RTG_TRY(f->skey.ensure(ctx, 4 * r));
     RTG_TRY(f->skey2.ensure(ctx, 4 * r));
@@ -482,7 +479,7 @@ rtg_status enqueue_project(rtg_frame* f, bool eager, hipStream_t s) {
     }
     project_emit(gd, views, hdr, f->views_cap, sd, f->st.tile_w, f->st.tile_h, f->mask.as<uint32_t>(),
                  f->rec_off.as<uint32_t>(), f->ctr(C_REC), f->rec_cap, f->records(), f->skey.as<uint32_t>(),
-                 f->order.as<uint32_t>(), f->ctr(C_FLAGS), s);
+                 f->order.as<uint32_t>(), !f->scoring, f->ctr(C_FLAGS), s);
     return check_launch("projection emit");
 }
 
@@ -807,7 +804,7 @@ rtg_status rtg_render_backward(rtg_ctx* ctx, rtg_frame* f, const float* d_rgb, c
     RTG_TRY(check_launch("render backward"));
     Timer tm(ctx, 6, s);
     project_backward(to_dev(f->g), f->views.as<ViewDev>(), to_dev(f->st), f->rec_off.as<uint32_t>(),
-                     f->cnt.as<uint32_t>(), f->view.as<uint32_t>(), f->g2d.as<double>(), out->d_means,
+                     f->cnt.as<uint32_t>(), f->emit.as<EmitRec>(), f->g2d.as<double>(), out->d_means,
                      out->d_log_scales, out->d_quats, out->d_opacity, out->d_colors, f->ctr(C_FLAGS), s);
     return check_launch("projection backward");
 }
@@ -910,6 +907,7 @@ rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera*
     rtg_frame* fp = nullptr;
     RTG_TRY(new_frame(ctx, g, cams, n_views, settings, &fp, s));
     std::unique_ptr<rtg_frame> f(fp);
+    f->scoring = true;
     RTG_TRY(enqueue_project(f.get(), true, s));
     RTG_TRY(enqueue_bin(f.get(), true, s));
     RTG_TRY(f->score_part.ensure(ctx, sizeof(double) * std::max<uint32_t>(f->L.hdr.tiles_total, 1)));
@@ -929,6 +927,7 @@ rtg_status score_plain(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* c
         rtg_frame* fp = nullptr;
         RTG_TRY(new_frame(ctx, g, cams + v, 1, settings, &fp, s));
         std::unique_ptr<rtg_frame> f(fp);
+        f->scoring = true;
         RTG_TRY(enqueue_project(f.get(), true, s));
         RTG_TRY(enqueue_bin(f.get(), true, s));
         RTG_TRY(f->score_part.ensure(ctx, sizeof(double) * std::max<uint32_t>(f->L.hdr.tiles_total, 1)));
@@ -1093,6 +1092,7 @@ rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t 
         rtg_frame* fp = nullptr;
         RTG_TRY(new_frame(ctx, g, probe, n_probe, &st, &fp, s));
         std::unique_ptr<rtg_frame> pf(fp);
+        pf->scoring = true;
         RTG_TRY(enqueue_project(pf.get(), true, s));
         RTG_TRY(enqueue_bin(pf.get(), true, s));
         double scale = 2.0 * (double)max_views / (double)n_probe;
@@ -1121,6 +1121,7 @@ rtg_status rtg_score_graph_create(rtg_ctx* ctx, const rtg_gaussians* g, int32_t 
     f->ctx = ctx;
     f->g = *g;
     f->st = st;
+    f->scoring = true;
     uint32_t tiles_per = (uint32_t)(((max_width + st.tile_w - 1) / st.tile_w) * ((max_height + st.tile_h - 1) / st.tile_h));
     uint32_t tiles_cap = tiles_per * (uint32_t)max_views;
     rtg_status rs = RTG_OK;
@@ -1317,7 +1318,7 @@ static rtg_status map_graph_build(rtg_ctx* ctx, const rtg_gaussians* g, const rt
                         f->n_last.as<uint32_t>(), d_rgb, d_dep, nullptr, nullptr, f->g2d.as<double>(), f->ctr(C_FLAGS),
                         cs);
         project_backward(to_dev(f->g), f->views.as<ViewDev>(), to_dev(st), f->rec_off.as<uint32_t>(),
-                         f->cnt.as<uint32_t>(), f->view.as<uint32_t>(), f->g2d.as<double>(), grads->d_means,
+                         f->cnt.as<uint32_t>(), f->emit.as<EmitRec>(), f->g2d.as<double>(), grads->d_means,
                          grads->d_log_scales, grads->d_quats, grads->d_opacity, grads->d_colors, f->ctr(C_FLAGS), cs);
         e = hipMemcpyAsync(gr->flag_host, f->ctr(C_FLAGS), sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
         if (e != hipSuccess) rs = set_err(RTG_ERR_HIP, "flag copy failed: %s", hipGetErrorString(e));

@@ -48,12 +48,12 @@ struct alignas(16) EmitRec {
     uint2 rect;  // tile rectangle: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
     uint32_t ntiles, view;
     uint32_t unc;  // binary32 bits of the uncertainty
-    uint32_t pad;
+    uint32_t gid;  // Gaussian index
 };
 
 // Projected (view, Gaussian) records, structure of arrays.
 //   emit = EmitRec: geo0, geo1, pixel box, tile rectangle, pair count, view,
-//          uncertainty, where
+//          uncertainty, Gaussian index, where
 //          geo0 = (mean_x hi, mean_y hi, mean_x lo, mean_y lo): the binary64
 //          mean as a sum of two binary32 values, so per-pixel offsets are exact;
 //          geo1 = (m00, m10, m11, opacity): the lower-triangular whitening M
@@ -63,15 +63,16 @@ struct alignas(16) EmitRec {
 //          pixel box of alpha >= alpha_min: x = u0 | u1 << 16, y = v0 | v1 << 16;
 //   q64  = binary64 Sigma_2D^-1 (xx, xy, yy, 0), read only to re-take the
 //          alpha_min decision in binary64 when binary32 alpha is near it;
-//   attr = (r, g, b, camera depth).
+//   attr = (r, g, b, binary32 camera depth, whose bits are the sort key);
+//          written only for frames that composite colour and depth (not
+//          for scoring);
+//   ntiles = pairs (support tiles) of the record, also in emit, here dense
+//          for the pair scan.
 struct Records {
     EmitRec* emit;
     double4* q64;
     float4* attr;
-    uint32_t* gid;
-    uint32_t* view;
-    uint32_t* dkey;    // binary32 bits of the camera depth (sort key)
-    uint32_t* ntiles;  // pairs (support tiles) of the record
+    uint32_t* ntiles;
 };
 
 // Screen-space gradient per record, binary64, 16 entries (one 128-byte line):
@@ -103,11 +104,12 @@ void fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 // cnt[i] = visible views of Gaussian i; mask[w * n + i] bit b = view 32w+b.
 void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap,
                    SetDev st, uint32_t* cnt, uint32_t* mask, hipStream_t s);
-// Writes records at rec_off[i] .. for the visible views of Gaussian i.
+// Writes records at rec_off[i] .. for the visible views of Gaussian i (attr
+// only when write_attr).
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap,
                   SetDev st, int tw, int th, const uint32_t* mask, const uint32_t* rec_off,
                   const uint32_t* R_dev, uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order,
-                  uint32_t* flags, hipStream_t s);
+                  bool write_attr, uint32_t* flags, hipStream_t s);
 
 // Exclusive prefix sum of in[0..n) (n = min(*n_dev, cap)) into out; *total =
 // the full sum.  If gather != NULL the input is in[gather[i]].  A sum of 2^31
@@ -171,7 +173,7 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
                      const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s);
 
 void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
-                      const uint32_t* cnt, const uint32_t* rec_view, const double* g2d,
+                      const uint32_t* cnt, const EmitRec* emit, const double* g2d,
                       float* d_means, float* d_log_scales, float* d_quats, float* d_opacity,
                       float* d_colors, const uint32_t* flags, hipStream_t s);
 

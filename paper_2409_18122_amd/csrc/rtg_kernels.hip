@@ -571,9 +571,21 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
     rs_chunk(n, begin, end);
-    for (uint32_t base = begin + wv * 64; base < end; base += RS_THREADS) {
-        uint32_t idx = base + lane_id();
-        if (idx < end) atomicAdd(&h[wv][(keys[idx] >> shift) & mask], 1u);
+    // the scatter's tiling: RS_IPT coalesced loads per lane in flight, then
+    // their RS_IPT additions to the wave's table
+    for (uint32_t t0 = begin; t0 < end; t0 += RS_TILE) {
+        const uint32_t seg = t0 + wv * RS_SEG;
+        uint32_t k[RS_IPT];
+#pragma unroll
+        for (int j = 0; j < RS_IPT; j++) {
+            const uint32_t idx = seg + j * 64 + lane_id();
+            k[j] = idx < end ? keys[idx] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < RS_IPT; j++) {
+            const uint32_t idx = seg + j * 64 + lane_id();
+            if (idx < end) atomicAdd(&h[wv][(k[j] >> shift) & mask], 1u);
+        }
     }
     __syncthreads();
     for (int d = tid; d < NB; d += RS_THREADS) {
@@ -908,6 +920,7 @@ __device__ __forceinline__ void cursor_next(PairCursor& c, int tws, int ths) {
 // Gaussians, is searched in global memory instead).
 constexpr int PE_THREADS = 256;
 constexpr uint32_t PE_LDS = 2048;
+constexpr uint32_t PE_PRE = 64;
 
 __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
                                                              int words, SetDev st, int tws, int ths,
@@ -915,9 +928,10 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
                                                              const uint32_t* __restrict__ rec_off,
                                                              const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
                                                              Records rec, uint32_t* __restrict__ sortkey,
-                                                             uint32_t* __restrict__ order,
+                                                             uint32_t* __restrict__ order, int write_attr,
                                                              uint32_t* __restrict__ flags) {
     __shared__ uint32_t s_off[PE_LDS];
+    __shared__ GPre s_pre[PE_PRE];
     __shared__ uint32_t s_lo, s_hi;
     const uint32_t Rall = *R_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0 && Rall > rec_cap) atomicOr(flags, FLAG_REC_OVERFLOW);
@@ -938,6 +952,10 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         const bool staged = ng <= PE_LDS;
         if (staged)
             for (uint32_t j = threadIdx.x; j < ng; j += PE_THREADS) s_off[j] = rec_off[lo + j];
+        // the per-Gaussian part of the projection, once per Gaussian when few
+        // Gaussians own the block's records (many views see each)
+        const bool shared_pre = ng <= PE_PRE;
+        if (shared_pre && threadIdx.x < ng) pre_gauss(g, lo + threadIdx.x, st, s_pre[threadIdx.x]);
         __syncthreads();
         const uint32_t pos = k0 + threadIdx.x;
         if (pos >= k1) continue;
@@ -957,7 +975,8 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
             kk -= c;
         }
         GPre P;
-        pre_gauss(g, i, st, P);
+        if (shared_pre) P = s_pre[i - lo];
+        else pre_gauss(g, i, st, P);
         const ViewDev& V = views[v];
         GProj q;
         project_exact(P, V, st, q);
@@ -974,17 +993,16 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
         float depth = (float)q.t[2];
         const int64_t gi = i;
-        if (g.colors)
-            rec.attr[pos] = make_float4(g.colors[gi], g.colors[g.n + gi], g.colors[2 * g.n + gi], depth);
-        else
-            rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
-        rec.gid[pos] = i;
-        rec.view[pos] = (uint32_t)v;
+        if (write_attr) {
+            if (g.colors)
+                rec.attr[pos] = make_float4(g.colors[gi], g.colors[g.n + gi], g.colors[2 * g.n + gi], depth);
+            else
+                rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
+        }
         uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
         uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
         const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
                                     (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
-        rec.dkey[pos] = __float_as_uint(depth);
         sortkey[pos] = __float_as_uint(depth);
         // pairs: the tiles the support meets (a subset of the box's
         // tiles); at least one, so that every record owns a pair
@@ -1000,7 +1018,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         e.ntiles = max(nt, 1u);
         e.view = (uint32_t)v;
         e.unc = __float_as_uint(g.uncert ? g.uncert[gi] : 0.0f);
-        e.pad = 0;
+        e.gid = i;
         rec.emit[pos] = e;
         order[pos] = pos;
     }
@@ -1904,7 +1922,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* __restrict__ views, SetDev st,
                                                      const uint32_t* __restrict__ rec_off,
                                                      const uint32_t* __restrict__ cnt,
-                                                     const uint32_t* __restrict__ rec_view,
+                                                     const EmitRec* __restrict__ emit,
                                                      const double* __restrict__ g2d,
                                                      float* __restrict__ d_means, float* __restrict__ d_ls,
                                                      float* __restrict__ d_quats, float* __restrict__ d_op,
@@ -1921,7 +1939,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
     double go = 0.0, gc[3] = {0, 0, 0};
     uint32_t r0 = rec_off[i];
     for (uint32_t r = r0; r < r0 + c; r++) {
-        const ViewDev& V = views[rec_view[r]];
+        const ViewDev& V = views[emit[r].view];
         GProj q;
         project_exact(P, V, st, q);
         const double* G2 = g2d + (uint64_t)r * G2D_STRIDE;
@@ -2227,8 +2245,8 @@ __global__ __launch_bounds__(256) void k_export(const uint32_t* __restrict__ til
     uint32_t K = min(*K_dev, cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
         uint32_t r = inst_rec[i];
-        if (keys) keys[i] = ((uint64_t)tile_key[i] << 32) | rec.dkey[r];
-        if (vals) vals[i] = rec.gid[r];
+        if (keys) keys[i] = ((uint64_t)tile_key[i] << 32) | __float_as_uint(rec.attr[r].w);
+        if (vals) vals[i] = rec.emit[r].gid;
     }
 }
 
@@ -2257,8 +2275,8 @@ __global__ __launch_bounds__(256) void k_export_records(const uint32_t* __restri
             pbox[2 * (uint64_t)R + r] = (int32_t)(e.pbox.y & 0xffffu);
             pbox[3 * (uint64_t)R + r] = (int32_t)(e.pbox.y >> 16);
         }
-        if (depth_bits) depth_bits[r] = rec.dkey[r];
-        if (gid) gid[r] = rec.gid[r];
+        if (depth_bits) depth_bits[r] = __float_as_uint(rec.attr[r].w);
+        if (gid) gid[r] = e.gid;
         if (view) view[r] = e.view;
         if (ntiles) ntiles[r] = e.ntiles;
     }
@@ -2652,12 +2670,14 @@ static int ilog2(int x) {
 
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap, SetDev st,
                   int tw, int th, const uint32_t* mask, const uint32_t* rec_off, const uint32_t* R_dev,
-                  uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order, uint32_t* flags, hipStream_t s) {
+                  uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order, bool write_attr, uint32_t* flags,
+                  hipStream_t s) {
     (void)hdr;
     if (g.n == 0 || rec_cap == 0) return;
     int words = (n_views_cap + 31) / 32;
     k_project_emit<<<grid_for(rec_cap, PE_THREADS, 32768), PE_THREADS, 0, s>>>(
-        g, views, words, st, ilog2(tw), ilog2(th), mask, rec_off, R_dev, rec_cap, rec, sortkey, order, flags);
+        g, views, words, st, ilog2(tw), ilog2(th), mask, rec_off, R_dev, rec_cap, rec, sortkey, order,
+        write_attr ? 1 : 0, flags);
 }
 
 int scan_blocks(uint64_t cap) {
@@ -2826,11 +2846,11 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
 }
 
 void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
-                      const uint32_t* cnt, const uint32_t* rec_view, const double* g2d, float* d_means,
+                      const uint32_t* cnt, const EmitRec* emit, const double* g2d, float* d_means,
                       float* d_log_scales, float* d_quats, float* d_opacity, float* d_colors, const uint32_t* flags,
                       hipStream_t s) {
     if (g.n == 0) return;
-    k_project_bwd<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, st, rec_off, cnt, rec_view, g2d, d_means,
+    k_project_bwd<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, st, rec_off, cnt, emit, g2d, d_means,
                                                      d_log_scales, d_quats, d_opacity, d_colors, flags);
 }
 
