@@ -477,12 +477,19 @@ def trajectory_select(ctx, xi, offsets):
     return util, best
 
 
-def tune_key(g, cams, mode):
-    """Cache key of a tuning result: mode, resolution(s), view count and the
-    power-of-two bucket of the Gaussian count."""
+def tune_key(g, cams, mode, settings=None):
+    """Cache key of a tuning result: the device, mode, resolution(s), view
+    count, the power-of-two bucket of the Gaussian count, and the settings
+    that change the work (alpha_min, T_min, alpha_max, eps2d, isotropic)."""
     n = int(g["opacity"].shape[0])
     res = sorted({(int(c["width"]), int(c["height"])) for c in cams})
-    return f"mode{int(mode)}:" + ",".join(f"{w}x{h}" for w, h in res) + f":v{len(cams)}:n2^{max(n, 1).bit_length() - 1}"
+    st = make_settings(settings)
+    t = g["opacity"]
+    name = torch.cuda.get_device_name(t.device) if isinstance(t, torch.Tensor) and t.is_cuda else "host"
+    work = (f"amin{st.alpha_min:.9g}:tmin{st.T_min:.9g}:amax{st.alpha_max:.9g}:eps{st.eps2d:.9g}"
+            f":iso{int(st.isotropic)}")
+    return (f"{name}:mode{int(mode)}:" + ",".join(f"{w}x{h}" for w, h in res) +
+            f":v{len(cams)}:n2^{max(n, 1).bit_length() - 1}:{work}")
 
 
 def autotune(ctx, g, cams, mode, settings=None, cache=None):
@@ -491,7 +498,7 @@ def autotune(ctx, g, cams, mode, settings=None, cache=None):
     under the same tune_key is returned without timing, and a new result is
     stored there."""
     out = dict(settings or DEFAULTS)
-    key = tune_key(g, cams, mode)
+    key = tune_key(g, cams, mode, settings)
     table = {}
     if cache is not None and os.path.exists(cache):
         with open(cache) as fh:

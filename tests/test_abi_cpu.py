@@ -128,3 +128,17 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_librtg.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_tune_key_separates_what_changes_the_work():
+    import scenes
+    from paper_2409_18122_amd import raster
+    g, cams = scenes.config1()
+    base = raster.tune_key(g, cams, 1, dict(scenes.DEFAULT_SETTINGS))
+    assert base.startswith("host:mode1:")
+    assert raster.tune_key(g, cams, 1, dict(scenes.DEFAULT_SETTINGS)) == base
+    for k, v in (("alpha_min", 0.01), ("T_min", 1e-3), ("alpha_max", 0.9), ("eps2d", 0.1), ("isotropic", 1)):
+        assert raster.tune_key(g, cams, 1, dict(scenes.DEFAULT_SETTINGS, **{k: v})) != base, k
+    assert raster.tune_key(g, cams, 0, dict(scenes.DEFAULT_SETTINGS)) != base
+    # tile, batch and capacity are what the tuner picks or bounds: not in the key
+    assert raster.tune_key(g, cams, 1, dict(scenes.DEFAULT_SETTINGS, tile_w=32, tile_h=8, batch=64)) == base

@@ -267,7 +267,10 @@ def test_autotuner_choice_does_not_change_results(raster, rctx, tmp_path):
     import json
     with open(cache) as fh:
         table = json.load(fh)
-    key = raster.tune_key(g, cams, 1)
+    key = raster.tune_key(dev, cams, 1, S())
+    # the key separates settings that change the work
+    assert raster.tune_key(dev, cams, 1, S(alpha_min=0.01)) != key
+    assert raster.tune_key(dev, cams, 1, S(isotropic=1)) != key
     assert table[key] == {"tile_w": first["tile_w"], "tile_h": first["tile_h"], "batch": first["batch"]}
     table[key] = {"tile_w": 32, "tile_h": 8, "batch": 64}  # a stored entry wins without timing
     with open(cache, "w") as fh:
