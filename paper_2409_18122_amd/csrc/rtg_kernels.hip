@@ -273,14 +273,19 @@ __device__ __forceinline__ bool support_span(float4 g0, float4 g1, float log2_am
 }
 
 // Whether a splat's support can reach a pixel of the rectangle [c0, c1] x
-// [r0, r1] (a prefilter; the per-pixel tests decide).
-__device__ __forceinline__ bool support_meets_rect(float4 g0, float4 g1, float log2_amin, int c0, int c1, int r0,
-                                                   int r1) {
-    const float mx = g0.x + g0.z;
+// [r0, r1] (a prefilter; the per-pixel tests decide).  The mean (mx, my) and
+// the rectangle are in any common pixel frame.
+__device__ __forceinline__ bool support_meets_rect_xy(float mx, float my, float4 g1, float log2_amin, int c0,
+                                                      int c1, int r0, int r1) {
     const float X = fmaxf(fabsf((float)c0 - mx), fabsf((float)c1 - mx));
     float xl, xr;
-    if (!support_span(g0, g1, log2_amin, X, r0, r1, xl, xr)) return false;
+    if (!support_span(make_float4(mx, my, 0.0f, 0.0f), g1, log2_amin, X, r0, r1, xl, xr)) return false;
     return xl <= (float)c1 && xr >= (float)c0;
+}
+
+__device__ __forceinline__ bool support_meets_rect(float4 g0, float4 g1, float log2_amin, int c0, int c1, int r0,
+                                                   int r1) {
+    return support_meets_rect_xy(g0.x + g0.z, g0.y + g0.w, g1, log2_amin, c0, c1, r0, r1);
 }
 
 // Per-record constants of the support rows: on a slice at offset dy the
@@ -2077,83 +2082,145 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
 
 // mode 0: sum_i u_i a_i T_i (the rendered proxy); mode 1: sum of u_i over
 // the contributing splats (the binary-J trace).
-template <int TW, int TH, int B>
+//
+// The pair loop is cut to the arithmetic the proxy needs.  Staged per splat:
+// the mean relative to an origin fixed per 32 x 16 pixel block (a multiple
+// of every tile shape, so no pixel's arithmetic depends on the tile), the
+// whitening M, log2(opacity) and u; a pixel's offset is then one subtraction
+// from a small exact integer, and alpha = min(alpha_max, exp2(log2 o - |Md|^2)).
+// Termination is carried by T itself: a pixel whose next transmittance
+// would fall below T_min stops with T = 0, after which every splat leaves it
+// unchanged, so the loop needs no per-pixel flags; a splat below alpha_min
+// enters the update with alpha 0 (T unchanged, exactly).
+template <int MODE>
+__device__ __forceinline__ float score_weight(float a0, float T) {
+    return MODE ? 1.0f : a0 * T;
+}
+
+// The staged splats (relative mean, whitening, log2 o, u) whose box and
+// support ellipse reach the wave's pixel rectangle, as a list of LDS byte
+// offsets of their s_p entries (see wave_list; 32-bit entries, so a step
+// reads its two offsets with one load and no unpacking); the rectangle is given
+// relative to the block origin.  Two entries past the end name the null
+// splat (slot B), so the pair loop runs in whole steps without checks.
+template <int NB>
+__device__ __forceinline__ int score_list(const uint2* s_pb, const float4* s_p, const float4* s_q,
+                                          float log2_amin, int cnt, int c0, int c1, int r0, int r1, int ox,
+                                          int oy, uint32_t* list) {
+    const int lane = (int)lane_id();
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < (NB + 63) / 64; c++) {
+        const int e = c * 64 + lane;
+        bool hit = e < cnt && box_meets(s_pb[e], c0 + ox, c1 + ox, r0 + oy, r1 + oy);
+        if (hit) {
+            const float4 p = s_p[e], q = s_q[e];
+            hit = support_meets_rect_xy(p.x, p.y, make_float4(p.z, p.w, q.x, q.w), log2_amin, c0, c1, r0, r1);
+        }
+        const uint64_t m = __ballot(hit);
+        if (hit) list[n + (int)__popcll(m & lanemask_lt())] = (uint32_t)(e * sizeof(float4));
+        n += (int)__popcll(m);
+    }
+    if (lane < 2) list[n + lane] = (uint32_t)(NB * sizeof(float4));
+    return n;
+}
+
+// Slot B of the staged arrays: a splat whose alpha is 0 at every pixel
+// (log2 o = -3e38), far from alpha_min's band, so it never contributes.
+template <int B>
+__device__ __forceinline__ void score_null_splat(float4* s_p, float4* s_q) {
+    if (threadIdx.x == 0) {
+        s_p[B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        s_q[B] = make_float4(0.0f, -3e38f, 0.0f, 0.0f);
+    }
+}
+
+template <int TW, int TH, int B, int MODE>
 __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views, int n_views, uint32_t tile,
                                                const uint2* __restrict__ ranges,
                                                const uint32_t* __restrict__ inst_rec, const Records& rec,
-                                               const SetDev& st, int mode, double* __restrict__ partial,
-                                               float4* s_g0, float4* s_g1, float* s_u, uint32_t* s_r,
-                                               uint2* s_pb, double* ws, uint16_t* s_list) {
+                                               const SetDev& st, double* __restrict__ partial,
+                                               float4* s_p, float4* s_q, uint32_t* s_r, uint2* s_pb,
+                                               double* ws, uint32_t* s_list) {
     constexpr int NT = TW * TH;
+    static_assert(32 % TW == 0 && 16 % TH == 0, "tiles must divide the 32 x 16 origin block");
+    static_assert(SCORE_STEP == 2, "the list is padded for steps of two");
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
     const uint32_t lt = tile - V.tile_off;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
-    // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of the tile)
-    const int wc0 = tx * TW, wc1 = wc0 + TW - 1;
-    const int wr0 = ty * TH + (int)(threadIdx.x >> 6) * (64 / TW), wr1 = wr0 + 64 / TW - 1;
+    const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~15;
+    // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of
+    // the tile), relative to the origin
+    const int wc0 = tx * TW - ox, wc1 = wc0 + TW - 1;
+    const int wr0 = ty * TH + (int)(threadIdx.x >> 6) * (64 / TW) - oy, wr1 = wr0 + 64 / TW - 1;
     const bool inside = u < V.W && v < V.H;
-    const float px = (float)u, py = (float)v;
+    const float lx = (float)(u - ox), ly = (float)(v - oy);
+    const float amin = st.alpha_min, amax = st.alpha_max, tmin = st.T_min;
+    const float nlo = amin - REFINE * amin, nhi = amin + REFINE * amin;
     const uint2 rg = ranges[tile];
-    float T = 1.0f, uu = 0.0f;
-    bool done = !inside;
+    const char* sp = reinterpret_cast<const char*>(s_p);
+    const char* sq = reinterpret_cast<const char*>(s_q);
+    float T = inside ? 1.0f : 0.0f, uu = 0.0f;
     for (uint32_t b = rg.x; b < rg.y; b += B) {
-        if (__syncthreads_count(done) == NT) break;
+        if (__syncthreads_count(T > 0.0f) == 0) break;
         uint32_t idx = b + threadIdx.x;
         if (threadIdx.x < (uint32_t)B && idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
             const EmitRec e = rec.emit[r];
             s_pb[threadIdx.x] = e.pbox;
-            s_g0[threadIdx.x] = e.g0;
-            s_g1[threadIdx.x] = e.g1;
-            s_u[threadIdx.x] = __uint_as_float(e.unc);
+            s_p[threadIdx.x] = make_float4((e.g0.x - (float)ox) + e.g0.z, (e.g0.y - (float)oy) + e.g0.w, e.g1.x,
+                                           e.g1.y);
+            s_q[threadIdx.x] = make_float4(e.g1.z, __builtin_amdgcn_logf(e.g1.w), __uint_as_float(e.unc), e.g1.w);
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);
-        uint16_t* my = s_list + (threadIdx.x >> 6) * B;
+        uint32_t* my = s_list + (threadIdx.x >> 6) * (B + 2);
         int nl = 0;
-        if (__ballot(!done)) nl = wave_list<B, SCORE_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, my);
+        if (__ballot(T > 0.0f)) nl = score_list<B>(s_pb, s_p, s_q, st.log2_amin, cnt, wc0, wc1, wr0, wr1, ox, oy, my);
         __syncthreads();  // the wave's list is in LDS
         for (int i = 0; i < nl; i += SCORE_STEP) {
-            if (!__ballot(!done)) break;
-            int ks[SCORE_STEP];
-#pragma unroll
-            for (int q = 0; q < SCORE_STEP; q++) ks[q] = i + q < nl ? (int)my[i + q] : -1;
-            float as[SCORE_STEP];
-            bool ok[SCORE_STEP];
+            if (!__ballot(T > 0.0f)) break;
+            uint32_t ko[SCORE_STEP];
+            float as[SCORE_STEP], us[SCORE_STEP];
             bool need = false;
 #pragma unroll
             for (int q = 0; q < SCORE_STEP; q++) {
-                const int k = ks[q] < 0 ? ks[0] : ks[q];
-                float G, dx, dy, w1, w2;
-                as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
-                ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
-                need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
+                ko[q] = my[i + q];
+                const float4 p = *reinterpret_cast<const float4*>(sp + ko[q]);
+                const float4 g = *reinterpret_cast<const float4*>(sq + ko[q]);
+                const float dx = lx - p.x, dy = ly - p.y;
+                const float w1 = p.z * dx, w2 = fmaf(p.w, dx, g.x * dy);
+                const float ex = fmaf(w1, w1, fmaf(w2, w2, -g.y));
+                const float a = __builtin_amdgcn_fmed3f(fast_exp2(-ex), 0.0f, amax);
+                as[q] = a;
+                us[q] = g.z;
+                need = need | ((a >= nlo) & (a <= nhi));
             }
             if (__ballot(need)) {
+                // the binary64 decision: a splat it keeps enters with alpha
+                // at least alpha_min (its binary32 alpha is within the band),
+                // one it drops with alpha 0
 #pragma unroll
                 for (int q = 0; q < SCORE_STEP; q++) {
-                    const int k = ks[q] < 0 ? ks[0] : ks[q];
-                    if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
-                        ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
+                    if ((as[q] >= nlo) & (as[q] <= nhi) & (ko[q] < B * sizeof(float4))) {
+                        const uint32_t r = s_r[ko[q] / sizeof(float4)];
+                        const EmitRec& e = rec.emit[r];
+                        as[q] = kept64(e.g0, e.g1, rec.q64, r, (float)u, (float)v, st) ? fmaxf(as[q], amin) : 0.0f;
+                    }
                 }
             }
-            // predicated, not branched
 #pragma unroll
             for (int q = 0; q < SCORE_STEP; q++) {
-                const int k = ks[q] < 0 ? ks[0] : ks[q];
-                const float a = as[q];
-                const float Tn = T * (1.0f - a);
-                const bool take = ok[q] && !done;
-                const bool stop = take && Tn < st.T_min;
-                const bool use = take && !stop;
-                done = done || stop;
-                const float uk = s_u[k];
-                const float wk = mode ? 1.0f : a * T;
-                uu = use ? fmaf(uk, wk, uu) : uu;
-                T = use ? Tn : T;
+                const bool ok = as[q] >= amin;
+                const float a0 = ok ? as[q] : 0.0f;
+                const float Tn = fmaf(-a0, T, T);
+                const bool live = Tn >= tmin;
+                const float w = score_weight<MODE>(a0, T);
+                uu = (ok & live) ? fmaf(us[q], w, uu) : uu;
+                T = live ? Tn : 0.0f;
             }
         }
     }
@@ -2175,14 +2242,18 @@ __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restri
                                                          SetDev st, int mode, double* __restrict__ partial) {
     constexpr int NT = TW * TH;
     static_assert(B <= NT, "batch larger than the tile");
-    __shared__ float4 s_g0[B], s_g1[B];
-    __shared__ float s_u[B];
+    __shared__ float4 s_p[B + 1], s_q[B + 1];
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
-    __shared__ uint16_t s_list[NT / 64 * B];
-    score_one_tile<TW, TH, B>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, mode, partial,
-                              s_g0, s_g1, s_u, s_r, s_pb, ws, s_list);
+    __shared__ __align__(8) uint32_t s_list[NT / 64 * (B + 2)];
+    score_null_splat<B>(s_p, s_q);
+    if (mode)
+        score_one_tile<TW, TH, B, 1>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial,
+                                     s_p, s_q, s_r, s_pb, ws, s_list);
+    else
+        score_one_tile<TW, TH, B, 0>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial,
+                                     s_p, s_q, s_r, s_pb, ws, s_list);
 }
 
 template <int TW, int TH, int B>
@@ -2196,12 +2267,12 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
     constexpr int NT = TW * TH;
     static_assert(B <= NT, "batch larger than the tile");
     if (*flags) return;  // overflowed binning: results are reported invalid
-    __shared__ float4 s_g0[B], s_g1[B];
-    __shared__ float s_u[B];
+    __shared__ float4 s_p[B + 1], s_q[B + 1];
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
-    __shared__ uint16_t s_list[NT / 64 * B];
+    __shared__ __align__(8) uint32_t s_list[NT / 64 * (B + 2)];
+    score_null_splat<B>(s_p, s_q);
     __shared__ uint32_t s_item;
     const uint32_t total = hdr->tiles_total;
     const int nv = (int)hdr->n_views;
@@ -2211,8 +2282,12 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= total) break;
-        score_one_tile<TW, TH, B>(views, nv, item, ranges, inst_rec, rec, st, mode, partial, s_g0, s_g1, s_u, s_r,
-                                  s_pb, ws, s_list);
+        if (mode)
+            score_one_tile<TW, TH, B, 1>(views, nv, item, ranges, inst_rec, rec, st, partial, s_p, s_q, s_r, s_pb,
+                                         ws, s_list);
+        else
+            score_one_tile<TW, TH, B, 0>(views, nv, item, ranges, inst_rec, rec, st, partial, s_p, s_q, s_r, s_pb,
+                                         ws, s_list);
     }
 }
 
