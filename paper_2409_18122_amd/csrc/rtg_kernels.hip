@@ -1282,19 +1282,30 @@ __device__ __forceinline__ uint32_t view_of_tile(const ViewDev* views, int nv, u
     return (uint32_t)lo;
 }
 
-// alpha of one splat at pixel centre (px, py): G = exp2(-|M d|^2) with
-// d = p - mean (the mean as hi + lo binary32 parts, so d is exact to binary32).
-__device__ __forceinline__ float splat_alpha(float4 g0, float4 g1, float px, float py, float amax, float& G,
+// Pixel arithmetic of the compositing loops is done relative to an origin
+// fixed per 32 x 16 pixel block (a multiple of every tile shape, so no
+// pixel's arithmetic depends on the tile): a pixel's coordinates are then
+// small exact integers and a splat's mean, staged once per tile as
+// (mean hi - origin) + mean lo, is rounded at the magnitude of its distance
+// from the block, far below what the alpha test needs.
+__device__ __forceinline__ int origin_x(int x) { return x & ~31; }
+__device__ __forceinline__ int origin_y(int y) { return y & ~15; }
+__device__ __forceinline__ float4 rel_mean(float4 g0, int ox, int oy) {
+    return make_float4((g0.x - (float)ox) + g0.z, (g0.y - (float)oy) + g0.w, 0.0f, 0.0f);
+}
+
+// alpha of one splat at the pixel (lx, ly) of the block whose origin the
+// staged mean (mx, my) is relative to: G = exp2(-|M d|^2), d = p - mean.
+__device__ __forceinline__ float splat_alpha(float mx, float my, float4 g1, float lx, float ly, float amax, float& G,
                                              float& dx, float& dy, float& w1, float& w2) {
-    dx = (px - g0.x) - g0.z;
-    dy = (py - g0.y) - g0.w;
+    dx = lx - mx;
+    dy = ly - my;
     w1 = g1.x * dx;
     w2 = fmaf(g1.y, dx, g1.z * dy);
     float pw = fmaf(w1, w1, w2 * w2);
     G = fast_exp2(-pw);
     return fminf(amax, g1.w * G);
 }
-
 
 // Splat box meets the pixel rectangle [c0, c1] x [r0, r1].
 __device__ __forceinline__ bool box_meets(uint2 b, int c0, int c1, int r0, int r1) {
@@ -1362,10 +1373,8 @@ __device__ __forceinline__ void pop_n(uint64_t& mm, int base, int (&ks)[P]) {
 
 // Splats evaluated per step of the front-to-back loops: their alphas are
 // independent of the pixel state, so they overlap; the updates follow in order.
-// At six waves per SIMD two per step measured 1% faster than four.
 constexpr int FWD_STEP = 2;
-// The scoring loop's (it keeps only T and one sum per pixel): 2 measured 3%
-// faster than 1, 4 or 8 on 64 and 256 views.
+// The scoring loop's (it keeps only T and one sum per pixel).
 constexpr int SCORE_STEP = 2;
 // Splats per step of the back-to-front backward loop (four measured slower:
 // the registers cut occupancy); the reduction below is written for two.
@@ -1375,12 +1384,12 @@ constexpr int BWD_STEP = 2;
 constexpr float REFINE = 2e-3f;
 
 // The alpha_min test: a splat with alpha < alpha_min at a pixel is skipped
-// there.  Near the threshold (near_amin) the decision is re-taken in binary64
-// from the binary64 conic (kept64), as the definition states it.  No pixel
-// box test is needed: the box is the exact bounding box of the support, so
-// outside it alpha < alpha_min already.  The loops take the rare binary64
-// branch once per step, for all the splats of the step.
-__device__ __forceinline__ bool near_amin(float a, float amin) { return fabsf(a - amin) <= REFINE * amin; }
+// there.  Where binary32 alpha lies in [alpha_min (1 - REFINE), alpha_min
+// (1 + REFINE)] the decision is re-taken in binary64 from the binary64 conic
+// (kept64), as the definition states it.  No pixel box test is needed: the
+// box is the exact bounding box of the support, so outside it alpha <
+// alpha_min already.  The loops take the rare binary64 branch once per
+// step, for all the splats of the step.
 
 __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __restrict__ q64, uint32_t r, float px,
                                        float py, const SetDev& st) {
@@ -1393,10 +1402,74 @@ __device__ __forceinline__ bool kept64(float4 g0, float4 g1, const double4* __re
     return ad >= (double)amin;
 }
 
+// Staged form of a splat for the pair loops of the forward and scoring
+// kernels: p = (mean x, mean y relative to the block origin, M00, M10),
+// q = (M11, opacity, u, log2 opacity).  Slot NB of the staged arrays holds
+// the null splat (opacity 0, log2 opacity -3e38): alpha 0 at every pixel, far
+// from alpha_min's band, so it never contributes.
+__device__ __forceinline__ void stage_splat(const EmitRec& e, int ox, int oy, float4& p, float4& q) {
+    const float4 m = rel_mean(e.g0, ox, oy);
+    p = make_float4(m.x, m.y, e.g1.x, e.g1.y);
+    q = make_float4(e.g1.z, e.g1.w, __uint_as_float(e.unc), __builtin_amdgcn_logf(e.g1.w));
+}
+
+template <int NB>
+__device__ __forceinline__ void stage_null_splat(float4* s_p, float4* s_q) {
+    if (threadIdx.x == 0) {
+        s_p[NB] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        s_q[NB] = make_float4(0.0f, 0.0f, 0.0f, -3e38f);
+    }
+}
+
+// The staged splats that can reach the calling wave's pixel rectangle
+// [c0, c1] x [r0, r1] (relative to the block origin (ox, oy)): their box
+// meets it and, with ELL, so does their support ellipse.  Written to list as
+// LDS byte offsets of their staged entries, in ascending order (so a step
+// reads its offsets with one load and no unpacking); two entries past the
+// end name the null splat, so the loops run in whole steps of two without
+// checks.  Returns the count (wave-uniform).
+template <int NB, bool ELL>
+__device__ __forceinline__ int splat_list(const uint2* s_pb, const float4* s_p, const float4* s_q, float log2_amin,
+                                          int cnt, int c0, int c1, int r0, int r1, int ox, int oy,
+                                          uint32_t* list) {
+    const int lane = (int)lane_id();
+    int n = 0;
+#pragma unroll
+    for (int c = 0; c < (NB + 63) / 64; c++) {
+        const int e = c * 64 + lane;
+        bool hit = e < cnt && box_meets(s_pb[e], c0 + ox, c1 + ox, r0 + oy, r1 + oy);
+        if (ELL && hit) {
+            const float4 p = s_p[e], q = s_q[e];
+            hit = support_meets_rect_xy(p.x, p.y, make_float4(p.z, p.w, q.x, q.y), log2_amin, c0, c1, r0, r1);
+        }
+        const uint64_t m = __ballot(hit);
+        if (hit) list[n + (int)__popcll(m & lanemask_lt())] = (uint32_t)(e * sizeof(float4));
+        n += (int)__popcll(m);
+    }
+    if (lane < 2) list[n + lane] = (uint32_t)(NB * sizeof(float4));
+    return n;
+}
+
+// The binary64 re-decision of a splat whose binary32 alpha fell within the
+// band around alpha_min: a splat it keeps enters with alpha at least
+// alpha_min (its binary32 alpha lies within the band, below the binary64
+// value), one it drops with alpha 0.
+__device__ __forceinline__ float redecide(float a, const Records& rec, uint32_t r, int u, int v, const SetDev& st) {
+    const EmitRec& e = rec.emit[r];
+    return kept64(e.g0, e.g1, rec.q64, r, (float)u, (float)v, st) ? fmaxf(a, st.alpha_min) : 0.0f;
+}
+
 // B splats are staged per batch (B <= TW * TH; threads below B load them).
 // Register budget: at most 80 VGPRs, six waves per SIMD (a 640x480 frame of
 // 16x16 tiles brings 4.7 waves per SIMD, larger frames many more).
 // UNC: the uncertainty image is requested (otherwise it is not composited).
+//
+// Front to back over the wave's list, FWD_STEP splats per step: their alphas
+// are independent of the pixel state, the updates follow in order.  A pixel
+// whose next transmittance would fall below T_min stops there; its T is then
+// kept negated (|T| is the final transmittance), which no later update
+// passes, so the loop carries no per-pixel flags.  A splat below alpha_min
+// enters with alpha 0 (T unchanged, exactly) and is not counted.
 template <int TW, int TH, int B, bool UNC>
 __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
@@ -1405,12 +1478,15 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
                                                         const uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
     static_assert(B <= NT, "batch larger than the tile");
+    static_assert(32 % TW == 0 && 16 % TH == 0, "tiles must divide the 32 x 16 origin block");
+    static_assert(FWD_STEP == 2, "the list is padded for steps of two");
     if (flags && *flags) return;
-    __shared__ float4 s_g0[B], s_g1[B], s_at[B];
-    __shared__ float s_u[B];
+    __shared__ float4 s_p[B + 1], s_q[B + 1], s_at[B + 1];
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
-    __shared__ uint16_t s_list[NT / 64 * B];
+    __shared__ __align__(8) uint32_t s_list[NT / 64 * (B + 2)];
+    stage_null_splat<B>(s_p, s_q);
+    if (threadIdx.x == 0) s_at[B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const uint32_t tile = blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
@@ -1418,82 +1494,88 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
     const uint32_t lt = tile - V.tile_off;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
-    // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of the tile)
-    const int wc0 = tx * TW, wc1 = wc0 + TW - 1;
-    const int wr0 = ty * TH + (int)(threadIdx.x >> 6) * (64 / TW), wr1 = wr0 + 64 / TW - 1;
+    const int ox = origin_x(tx * TW), oy = origin_y(ty * TH);
+    // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of
+    // the tile), relative to the origin
+    const int wc0 = tx * TW - ox, wc1 = wc0 + TW - 1;
+    const int wr0 = ty * TH + (int)(threadIdx.x >> 6) * (64 / TW) - oy, wr1 = wr0 + 64 / TW - 1;
     const bool inside = u < W && v < H;
-    const float px = (float)u, py = (float)v;
+    const float lx = (float)(u - ox), ly = (float)(v - oy);
+    const float amin = st.alpha_min, amax = st.alpha_max, tmin = st.T_min;
+    const float nlo = amin - REFINE * amin, nhi = amin + REFINE * amin;
+    const char* sp = reinterpret_cast<const char*>(s_p);
+    const char* sq = reinterpret_cast<const char*>(s_q);
+    const char* sa = reinterpret_cast<const char*>(s_at);
     const uint2 rg = ranges[tile];
-    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dd = 0.0f, uu = 0.0f;
+    float T = inside ? 1.0f : -1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dd = 0.0f, uu = 0.0f;
     uint32_t last = 0, ncontrib = 0;
-    bool done = !inside;
     for (uint32_t b = rg.x; b < rg.y; b += B) {
-        if (__syncthreads_count(done) == NT) break;
+        if (__syncthreads_count(T > 0.0f) == 0) break;
         uint32_t idx = b + threadIdx.x;
         if (threadIdx.x < (uint32_t)B && idx < rg.y) {
             uint32_t r = inst_rec[idx];
             s_r[threadIdx.x] = r;
             const EmitRec e = rec.emit[r];
             s_pb[threadIdx.x] = e.pbox;
-            s_g0[threadIdx.x] = e.g0;
-            s_g1[threadIdx.x] = e.g1;
+            stage_splat(e, ox, oy, s_p[threadIdx.x], s_q[threadIdx.x]);
             s_at[threadIdx.x] = rec.attr[r];
-            if (UNC) s_u[threadIdx.x] = __uint_as_float(e.unc);
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);
-        uint16_t* my = s_list + (threadIdx.x >> 6) * B;
+        uint32_t* my = s_list + (threadIdx.x >> 6) * (B + 2);
         int nl = 0;
-        if (__ballot(!done)) nl = wave_list<B, FWD_ELL>(s_pb, s_g0, s_g1, st.log2_amin, cnt, wc0, wc1, wr0, wr1, my);
+        if (__ballot(T > 0.0f))
+            nl = splat_list<B, FWD_ELL>(s_pb, s_p, s_q, st.log2_amin, cnt, wc0, wc1, wr0, wr1, ox, oy, my);
         __syncthreads();  // the wave's list is in LDS
+        // LDS offset of the last splat this lane took in this batch
+        uint32_t lastoff = 0xffffffffu;
         for (int i = 0; i < nl; i += FWD_STEP) {
-            if (!__ballot(!done)) break;
-            int ks[FWD_STEP];
-#pragma unroll
-            for (int q = 0; q < FWD_STEP; q++) ks[q] = i + q < nl ? (int)my[i + q] : -1;
+            if (!__ballot(T > 0.0f)) break;
+            uint32_t ko[FWD_STEP];
             float as[FWD_STEP];
-            bool ok[FWD_STEP];
             bool need = false;
 #pragma unroll
             for (int q = 0; q < FWD_STEP; q++) {
-                const int k = ks[q] < 0 ? ks[0] : ks[q];
+                ko[q] = my[i + q];
+                const float4 pp = *reinterpret_cast<const float4*>(sp + ko[q]);
+                const float4 qq = *reinterpret_cast<const float4*>(sq + ko[q]);
                 float G, dx, dy, w1, w2;
-                as[q] = splat_alpha(s_g0[k], s_g1[k], px, py, st.alpha_max, G, dx, dy, w1, w2);
-                ok[q] = ks[q] >= 0 && as[q] >= st.alpha_min;
-                need = need || (ks[q] >= 0 && near_amin(as[q], st.alpha_min));
+                as[q] = splat_alpha(pp.x, pp.y, make_float4(pp.z, pp.w, qq.x, qq.y), lx, ly, amax, G, dx, dy, w1,
+                                    w2);
+                need = need | ((as[q] >= nlo) & (as[q] <= nhi));
             }
             if (__ballot(need)) {
 #pragma unroll
-                for (int q = 0; q < FWD_STEP; q++) {
-                    const int k = ks[q] < 0 ? ks[0] : ks[q];
-                    if (ks[q] >= 0 && near_amin(as[q], st.alpha_min))
-                        ok[q] = kept64(s_g0[k], s_g1[k], rec.q64, s_r[k], px, py, st);
-                }
+                for (int q = 0; q < FWD_STEP; q++)
+                    if ((as[q] >= nlo) & (as[q] <= nhi) & (ko[q] < B * sizeof(float4)))
+                        as[q] = redecide(as[q], rec, s_r[ko[q] / sizeof(float4)], u, v, st);
             }
-            // predicated, not branched: the update is a few FMAs
 #pragma unroll
             for (int q = 0; q < FWD_STEP; q++) {
-                const int k = ks[q] < 0 ? ks[0] : ks[q];
-                const float a = as[q];
-                const float Tn = T * (1.0f - a);
-                const bool take = ok[q] && !done;
-                const bool stop = take && Tn < st.T_min;
-                const bool use = take && !stop;
-                done = done || stop;
-                const float w = a * T;
-                const float4 at = s_at[k];
+                const bool ok = as[q] >= amin;
+                const float a0 = ok ? as[q] : 0.0f;
+                const float Tn = fmaf(-a0, T, T);
+                const bool live = Tn >= tmin;
+                const bool use = ok & live;
+                const float w = a0 * T;
+                const float4 at = *reinterpret_cast<const float4*>(sa + ko[q]);
                 c0 = use ? fmaf(at.x, w, c0) : c0;
                 c1 = use ? fmaf(at.y, w, c1) : c1;
                 c2 = use ? fmaf(at.z, w, c2) : c2;
                 dd = use ? fmaf(at.w, w, dd) : dd;
-                if (UNC) uu = use ? fmaf(s_u[k], w, uu) : uu;
-                T = use ? Tn : T;
-                last = use ? b - rg.x + (uint32_t)k + 1 : last;
+                if (UNC) {
+                    const float uk = *reinterpret_cast<const float*>(sq + ko[q] + 8);
+                    uu = use ? fmaf(uk, w, uu) : uu;
+                }
+                lastoff = use ? ko[q] : lastoff;
                 ncontrib += use ? 1u : 0u;
+                T = live ? Tn : -fabsf(T);
             }
         }
+        if (lastoff != 0xffffffffu) last = b - rg.x + 1 + lastoff / (uint32_t)sizeof(float4);
     }
     if (!inside) return;
+    T = fabsf(T);
     const uint64_t P = (uint64_t)W * H;
     const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
     if (out.rgb) {
@@ -1770,11 +1852,14 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
     const uint64_t P = (uint64_t)W * H;
     const int lane = (int)(threadIdx.x & 63), wave = NW == 1 ? 0 : (int)(threadIdx.x >> 6);
 
-    // pixel j of this lane: (px0 + bx(j), py0 + by(j)), block offsets that
-    // are constants when the tile has one wave
-    const float px0 = (float)(tx * TW + (lane & 7)), py0 = (float)(ty * TH + (lane >> 3));
+    // pixel j of this lane: (px0 + bx(j), py0 + by(j)) relative to the block
+    // origin, block offsets that are constants when the tile has one wave
+    const int ox = origin_x(tx * TW), oy = origin_y(ty * TH);
+    const float px0 = (float)(tx * TW - ox + (lane & 7)), py0 = (float)(ty * TH - oy + (lane >> 3));
     auto bx = [&](int j) { return (float)(((wave * PPT + j) % (TW / 8)) * 8); };
     auto by = [&](int j) { return (float)(((wave * PPT + j) / (TW / 8)) * 8); };
+    auto ux = [&](int j) { return tx * TW + ((wave * PPT + j) % (TW / 8)) * 8 + (lane & 7); };
+    auto vy = [&](int j) { return ty * TH + ((wave * PPT + j) / (TW / 8)) * 8 + (lane >> 3); };
     float T[PPT];
     uint32_t last[PPT];
     float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
@@ -1819,6 +1904,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     const float amax = st.alpha_max;
+    const float nlo = st.alpha_min - REFINE * st.alpha_min, nhi = st.alpha_min + REFINE * st.alpha_min;
     const float kq = (float)(4.0 / LOG2E);
 
     for (int64_t bend = maxlast; bend > 0; bend -= B) {
@@ -1831,7 +1917,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 s_r[threadIdx.x] = r;
                 const EmitRec e = rec.emit[r];
                 s_pb[threadIdx.x] = e.pbox;
-                s_g0[threadIdx.x] = e.g0;
+                s_g0[threadIdx.x] = rel_mean(e.g0, ox, oy);
                 s_g1[threadIdx.x] = e.g1;
                 s_at[threadIdx.x] = rec.attr[r];
                 if (AU) s_u[threadIdx.x] = __uint_as_float(e.unc);
@@ -1875,24 +1961,23 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 #pragma unroll
             for (int j = 0; j < PPT; j++) {
                 float a[BWD_STEP], G[BWD_STEP], dx[BWD_STEP], dy[BWD_STEP], w1[BWD_STEP], w2[BWD_STEP];
-                bool ok[BWD_STEP];
                 bool need = false;
 #pragma unroll
                 for (int q = 0; q < BWD_STEP; q++) {
-                    a[q] = splat_alpha(sg0[q], sg1[q], px0 + bx(j), py0 + by(j), amax, G[q], dx[q], dy[q], w1[q],
-                                       w2[q]);
-                    ok[q] = spos[q] < last[j] && a[q] >= st.alpha_min;
-                    need = need || (spos[q] < last[j] && near_amin(a[q], st.alpha_min));
+                    a[q] = splat_alpha(sg0[q].x, sg0[q].y, sg1[q], px0 + bx(j), py0 + by(j), amax, G[q], dx[q],
+                                       dy[q], w1[q], w2[q]);
+                    need = need | ((spos[q] < last[j]) & (a[q] >= nlo) & (a[q] <= nhi));
                 }
+                // the forward's binary64 re-decision, taken the same way
                 if (__ballot(need)) {
 #pragma unroll
                     for (int q = 0; q < BWD_STEP; q++)
-                        if (spos[q] < last[j] && near_amin(a[q], st.alpha_min))
-                            ok[q] = kept64(sg0[q], sg1[q], rec.q64, sr[q], px0 + bx(j), py0 + by(j), st);
+                        if ((spos[q] < last[j]) & (a[q] >= nlo) & (a[q] <= nhi))
+                            a[q] = redecide(a[q], rec, sr[q], ux(j), vy(j), st);
                 }
 #pragma unroll
                 for (int q = 0; q < BWD_STEP; q++) {
-                    if (ok[q]) {
+                    if ((spos[q] < last[j]) & (a[q] >= st.alpha_min)) {
                         any[q] = true;
                         bwd_pixel<AU>(a[q], G[q], dx[q], dy[q], w1[q], w2[q], sg1[q], sat[q], su[q], amax, kq, gr[j],
                                   gg[j], gb[j], gd[j], ga[j], gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j],
@@ -2097,44 +2182,6 @@ __device__ __forceinline__ float score_weight(float a0, float T) {
     return MODE ? 1.0f : a0 * T;
 }
 
-// The staged splats (relative mean, whitening, log2 o, u) whose box and
-// support ellipse reach the wave's pixel rectangle, as a list of LDS byte
-// offsets of their s_p entries (see wave_list; 32-bit entries, so a step
-// reads its two offsets with one load and no unpacking); the rectangle is given
-// relative to the block origin.  Two entries past the end name the null
-// splat (slot B), so the pair loop runs in whole steps without checks.
-template <int NB>
-__device__ __forceinline__ int score_list(const uint2* s_pb, const float4* s_p, const float4* s_q,
-                                          float log2_amin, int cnt, int c0, int c1, int r0, int r1, int ox,
-                                          int oy, uint32_t* list) {
-    const int lane = (int)lane_id();
-    int n = 0;
-#pragma unroll
-    for (int c = 0; c < (NB + 63) / 64; c++) {
-        const int e = c * 64 + lane;
-        bool hit = e < cnt && box_meets(s_pb[e], c0 + ox, c1 + ox, r0 + oy, r1 + oy);
-        if (hit) {
-            const float4 p = s_p[e], q = s_q[e];
-            hit = support_meets_rect_xy(p.x, p.y, make_float4(p.z, p.w, q.x, q.w), log2_amin, c0, c1, r0, r1);
-        }
-        const uint64_t m = __ballot(hit);
-        if (hit) list[n + (int)__popcll(m & lanemask_lt())] = (uint32_t)(e * sizeof(float4));
-        n += (int)__popcll(m);
-    }
-    if (lane < 2) list[n + lane] = (uint32_t)(NB * sizeof(float4));
-    return n;
-}
-
-// Slot B of the staged arrays: a splat whose alpha is 0 at every pixel
-// (log2 o = -3e38), far from alpha_min's band, so it never contributes.
-template <int B>
-__device__ __forceinline__ void score_null_splat(float4* s_p, float4* s_q) {
-    if (threadIdx.x == 0) {
-        s_p[B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        s_q[B] = make_float4(0.0f, -3e38f, 0.0f, 0.0f);
-    }
-}
-
 template <int TW, int TH, int B, int MODE>
 __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views, int n_views, uint32_t tile,
                                                const uint2* __restrict__ ranges,
@@ -2150,7 +2197,7 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
     const uint32_t lt = tile - V.tile_off;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const int u = tx * TW + (int)(threadIdx.x % TW), v = ty * TH + (int)(threadIdx.x / TW);
-    const int ox = (tx * TW) & ~31, oy = (ty * TH) & ~15;
+    const int ox = origin_x(tx * TW), oy = origin_y(ty * TH);
     // this wave's pixel rectangle (64 consecutive threads = 64 / TW rows of
     // the tile), relative to the origin
     const int wc0 = tx * TW - ox, wc1 = wc0 + TW - 1;
@@ -2171,15 +2218,14 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
             s_r[threadIdx.x] = r;
             const EmitRec e = rec.emit[r];
             s_pb[threadIdx.x] = e.pbox;
-            s_p[threadIdx.x] = make_float4((e.g0.x - (float)ox) + e.g0.z, (e.g0.y - (float)oy) + e.g0.w, e.g1.x,
-                                           e.g1.y);
-            s_q[threadIdx.x] = make_float4(e.g1.z, __builtin_amdgcn_logf(e.g1.w), __uint_as_float(e.unc), e.g1.w);
+            stage_splat(e, ox, oy, s_p[threadIdx.x], s_q[threadIdx.x]);
         }
         __syncthreads();
         const int cnt = (int)min<uint32_t>(B, rg.y - b);
         uint32_t* my = s_list + (threadIdx.x >> 6) * (B + 2);
         int nl = 0;
-        if (__ballot(T > 0.0f)) nl = score_list<B>(s_pb, s_p, s_q, st.log2_amin, cnt, wc0, wc1, wr0, wr1, ox, oy, my);
+        if (__ballot(T > 0.0f))
+            nl = splat_list<B, SCORE_ELL>(s_pb, s_p, s_q, st.log2_amin, cnt, wc0, wc1, wr0, wr1, ox, oy, my);
         __syncthreads();  // the wave's list is in LDS
         for (int i = 0; i < nl; i += SCORE_STEP) {
             if (!__ballot(T > 0.0f)) break;
@@ -2193,24 +2239,17 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
                 const float4 g = *reinterpret_cast<const float4*>(sq + ko[q]);
                 const float dx = lx - p.x, dy = ly - p.y;
                 const float w1 = p.z * dx, w2 = fmaf(p.w, dx, g.x * dy);
-                const float ex = fmaf(w1, w1, fmaf(w2, w2, -g.y));
+                const float ex = fmaf(w1, w1, fmaf(w2, w2, -g.w));
                 const float a = __builtin_amdgcn_fmed3f(fast_exp2(-ex), 0.0f, amax);
                 as[q] = a;
                 us[q] = g.z;
                 need = need | ((a >= nlo) & (a <= nhi));
             }
             if (__ballot(need)) {
-                // the binary64 decision: a splat it keeps enters with alpha
-                // at least alpha_min (its binary32 alpha is within the band),
-                // one it drops with alpha 0
 #pragma unroll
-                for (int q = 0; q < SCORE_STEP; q++) {
-                    if ((as[q] >= nlo) & (as[q] <= nhi) & (ko[q] < B * sizeof(float4))) {
-                        const uint32_t r = s_r[ko[q] / sizeof(float4)];
-                        const EmitRec& e = rec.emit[r];
-                        as[q] = kept64(e.g0, e.g1, rec.q64, r, (float)u, (float)v, st) ? fmaxf(as[q], amin) : 0.0f;
-                    }
-                }
+                for (int q = 0; q < SCORE_STEP; q++)
+                    if ((as[q] >= nlo) & (as[q] <= nhi) & (ko[q] < B * sizeof(float4)))
+                        as[q] = redecide(as[q], rec, s_r[ko[q] / sizeof(float4)], u, v, st);
             }
 #pragma unroll
             for (int q = 0; q < SCORE_STEP; q++) {
@@ -2247,7 +2286,7 @@ __global__ __launch_bounds__(TW * TH) void k_score_plain(const ViewDev* __restri
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
     __shared__ __align__(8) uint32_t s_list[NT / 64 * (B + 2)];
-    score_null_splat<B>(s_p, s_q);
+    stage_null_splat<B>(s_p, s_q);
     if (mode)
         score_one_tile<TW, TH, B, 1>(views, n_views, tile_begin + blockIdx.x, ranges, inst_rec, rec, st, partial,
                                      s_p, s_q, s_r, s_pb, ws, s_list);
@@ -2272,7 +2311,7 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
     __shared__ uint2 s_pb[B];
     __shared__ double ws[NT / 64];
     __shared__ __align__(8) uint32_t s_list[NT / 64 * (B + 2)];
-    score_null_splat<B>(s_p, s_q);
+    stage_null_splat<B>(s_p, s_q);
     __shared__ uint32_t s_item;
     const uint32_t total = hdr->tiles_total;
     const int nv = (int)hdr->n_views;
