@@ -1755,63 +1755,58 @@ __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
     return k;
 }
 
-// Adds a splat's 10 wave totals to its record's binary64 gradient slots:
-// mean (2), conic (3), opacity, colour (3), depth.
-__device__ __forceinline__ void add_g2d(double* g2d, uint32_t r, const float* t) {
-    double* dst = g2d + (uint64_t)r * G2D_STRIDE;
-#pragma unroll
-    for (int v = 0; v < 10; v++) unsafeAtomicAdd(dst + v, (double)t[v]);
-}
-
-// One pixel's step of the reverse compositing recursion for a kept splat:
-// restores T and the running sums S of the splats behind it, and adds the
-// pixel's contributions to the splat's per-lane sums acc (same order as
-// add_g2d).  T_i = T_{i+1} / (1 - a_i); w = a_i T_i.  Since a_i <= alpha_max
-// < 1, 1 - a_i is a normal number well away from zero and the hardware
-// reciprocal (within 1 ulp) stands in for the correctly rounded division; T
-// only scales gradient terms here and decides nothing.
-// AU: the alpha and uncertainty images carry gradients too (otherwise their
-// terms and running sums are left out altogether).
+// One pixel's step of the reverse compositing recursion for a kept splat i.
+// With T = T_{i+1} (transmittance behind it), T_i = T / (1 - a_i) and the
+// splat's weight w = a_i T_i; for an image channel with colour c_i and pixel
+// gradient g, dL/da_i = g (c_i T_i - S / (1 - a_i)), S = sum_{j > i} c_j w_j.
+// The channels enter only through GA = sum_ch g_ch c_i,ch, so the pixel
+// carries one running sum D = sum_ch g_ch S_ch (D += w GA) instead of one per
+// channel: dL/da_i = T_i GA - D / (1 - a_i).  Since a_i <= alpha_max < 1,
+// 1 - a_i is a normal number well away from zero and the hardware reciprocal
+// (within 1 ulp) stands in for the correctly rounded division; T only scales
+// gradient terms here and decides nothing.
+// Per-lane sums acc (the record's gradient slots, in this order):
+//   0, 1: sum dpow dx, sum dpow dy, with dpow = dL/dpower, power = d^T Q d
+//         (G = exp(-power / 2)), d = pixel - mean; the mean's gradient
+//         -2 Q (sum dpow d) is formed from them in binary64 per record;
+//   2, 3, 4: sum dpow dx^2, sum dpow dx dy, sum dpow dy^2 (dL/dQ);
+//   5: sum dL/da G (the opacity's gradient: a = o G below alpha_max);
+//   6..9: sum g_ch w (colour and depth).
+// AU: the alpha and uncertainty images carry gradients too (colour 1 and u
+// in GA; otherwise their terms are left out altogether).
 template <bool AU>
-__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float w1, float w2, float4 g1,
-                                          float4 at, float ui, float amax, float kq, float gr, float gg, float gb,
-                                          float gd, float ga, float gu, float& T, float& S0, float& S1, float& S2,
-                                          float& S3, float& S4, float& S5, float* acc) {
+__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 g1, float4 at, float ui,
+                                          float amax, float nho, float gr, float gg, float gb, float gd, float ga,
+                                          float gu, float& T, float& D, float* acc) {
     const float inv = __builtin_amdgcn_rcpf(1.0f - a);
     const float Ti = T * inv;
     const float w = a * Ti;
-    float da = gr * (at.x * Ti - S0 * inv);
-    da = fmaf(gg, at.y * Ti - S1 * inv, da);
-    da = fmaf(gb, at.z * Ti - S2 * inv, da);
-    da = fmaf(gd, at.w * Ti - S3 * inv, da);
+    float GA = gr * at.x;
+    GA = fmaf(gg, at.y, GA);
+    GA = fmaf(gb, at.z, GA);
+    GA = fmaf(gd, at.w, GA);
     if constexpr (AU) {
-        da = fmaf(ga, Ti - S4 * inv, da);
-        da = fmaf(gu, ui * Ti - S5 * inv, da);
+        GA += ga;
+        GA = fmaf(gu, ui, GA);
     }
+    const float da = fmaf(Ti, GA, -(D * inv));
+    D = fmaf(w, GA, D);
     acc[6] = fmaf(gr, w, acc[6]);
     acc[7] = fmaf(gg, w, acc[7]);
     acc[8] = fmaf(gb, w, acc[8]);
     acc[9] = fmaf(gd, w, acc[9]);
-    S0 = fmaf(at.x, w, S0);
-    S1 = fmaf(at.y, w, S1);
-    S2 = fmaf(at.z, w, S2);
-    S3 = fmaf(at.w, w, S3);
-    if constexpr (AU) {
-        S4 += w;
-        S5 = fmaf(ui, w, S5);
-    }
     T = Ti;
     if (g1.w * G <= amax) {
-        acc[5] = fmaf(da, G, acc[5]);
-        // dL/dpower with power = d^T Q d and G = exp(-power / 2)
-        const float dpow = -0.5f * G * (da * g1.w);
-        acc[2] = fmaf(dpow * dx, dx, acc[2]);
-        acc[3] = fmaf(dpow * 2.0f * dx, dy, acc[3]);
-        acc[4] = fmaf(dpow * dy, dy, acc[4]);
-        // d = p - mean: dL/dmean = -dpow * 2 Q d, with Q d = (2 / log2e) M^T w
-        const float mm = -dpow * kq;
-        acc[0] = fmaf(mm, fmaf(g1.x, w1, g1.y * w2), acc[0]);
-        acc[1] = fmaf(mm, g1.z * w2, acc[1]);
+        const float t0 = da * G;
+        acc[5] += t0;
+        // nho = -o / 2: dpow = dL/da * o * dG/dpower
+        const float dpow = t0 * nho;
+        const float t1 = dpow * dx, t2 = dpow * dy;
+        acc[0] += t1;
+        acc[1] += t2;
+        acc[2] = fmaf(t1, dx, acc[2]);
+        acc[3] = fmaf(t1, dy, acc[3]);
+        acc[4] = fmaf(t2, dy, acc[4]);
     }
 }
 
@@ -1863,7 +1858,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
     float T[PPT];
     uint32_t last[PPT];
     float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
-    float S0[PPT], S1[PPT], S2[PPT], S3[PPT], S4[PPT], S5[PPT];
+    float D[PPT];
     uint32_t mylast = 0;
     int wc0 = 1 << 30, wc1 = -1, wr0 = 1 << 30, wr1 = -1;  // the wave's pixel rectangle
 #pragma unroll
@@ -1878,7 +1873,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
         T[j] = 1.0f;
         last[j] = 0;
         gr[j] = gg[j] = gb[j] = gd[j] = ga[j] = gu[j] = 0.0f;
-        S0[j] = S1[j] = S2[j] = S3[j] = S4[j] = S5[j] = 0.0f;
+        D[j] = 0.0f;
         if (u < W && v < H) {
             const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
             T[j] = T_final[pix];
@@ -1905,7 +1900,6 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     const float amax = st.alpha_max;
     const float nlo = st.alpha_min - REFINE * st.alpha_min, nhi = st.alpha_min + REFINE * st.alpha_min;
-    const float kq = (float)(4.0 / LOG2E);
 
     for (int64_t bend = maxlast; bend > 0; bend -= B) {
         const int64_t bstart = bend - B > 0 ? bend - B : 0;
@@ -1979,9 +1973,8 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 for (int q = 0; q < BWD_STEP; q++) {
                     if ((spos[q] < last[j]) & (a[q] >= st.alpha_min)) {
                         any[q] = true;
-                        bwd_pixel<AU>(a[q], G[q], dx[q], dy[q], w1[q], w2[q], sg1[q], sat[q], su[q], amax, kq, gr[j],
-                                  gg[j], gb[j], gd[j], ga[j], gu[j], T[j], S0[j], S1[j], S2[j], S3[j], S4[j], S5[j],
-                                  acc[q]);
+                        bwd_pixel<AU>(a[q], G[q], dx[q], dy[q], sg1[q], sat[q], su[q], amax, -0.5f * sg1[q].w,
+                                      gr[j], gg[j], gb[j], gd[j], ga[j], gu[j], T[j], D[j], acc[q]);
                     }
                 }
             }
@@ -2033,16 +2026,20 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
         GProj q;
         project_exact(P, V, st, q);
         const double* G2 = g2d + (uint64_t)r * G2D_STRIDE;
-        double gmx = G2[0], gmy = G2[1], gqa = G2[2], gqb = G2[3], gqc = G2[4];
         go += G2[5];
         gc[0] += G2[6];
         gc[1] += G2[7];
         gc[2] += G2[8];
         double gdepth = G2[9];
-        // conic gradient (xy as one parameter) -> symmetric matrix gradient
         double det = q.cxx * q.cyy - q.cxy * q.cxy;
         double Qxx = q.cyy / det, Qxy = -q.cxy / det, Qyy = q.cxx / det;
-        double Gq00 = gqa, Gq01 = 0.5 * gqb, Gq11 = gqc;
+        // the 2D mean: power = d^T Q d with d = pixel - mean, so
+        // dL/dmean = -2 Q sum_p dpow d (slots 0 and 1 hold the sum)
+        double gmx = -2.0 * (Qxx * G2[0] + Qxy * G2[1]);
+        double gmy = -2.0 * (Qxy * G2[0] + Qyy * G2[1]);
+        // conic gradient (slots 2..4: dL/dQxx, dL/dQxy of the xy term taken
+        // once, dL/dQyy) -> symmetric matrix gradient
+        double Gq00 = G2[2], Gq01 = G2[3], Gq11 = G2[4];
         // G_cov = -Q G_Q Q
         double m00 = Gq00 * Qxx + Gq01 * Qxy, m01 = Gq00 * Qxy + Gq01 * Qyy;
         double m10 = Gq01 * Qxx + Gq11 * Qxy, m11 = Gq01 * Qxy + Gq11 * Qyy;
