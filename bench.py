@@ -35,11 +35,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "render+backward Mpix/s and candidate views scored/s, batched vs plain, 1 GPU"
 
-# Algorithmic work per unit:
-#  forward compositing: 20 FP32 VALU operations per contributing pixel-splat pair;
-#  backward compositing: 55 FP32 VALU operations per contributing pair;
-#  scoring compositing (alpha and uncertainty only): 15 per contributing pair.
-OPS_PER_PAIR = {"render": 20.0, "render_backward": 55.0, "score": 15.0}
+# Algorithmic work per unit, FP32 VALU operations per contributing
+# pixel-splat pair, counted on the method's arithmetic:
+#  alpha: offset (2), whitened offset (3), squared norm (2), exp2, times
+#   opacity, clamp to alpha_max = 10; the alpha_min test = 1;
+#  forward: alpha and test (11), next transmittance, its T_min test, weight
+#   (3), colour and depth accumulation (4) = 18;
+#  backward: alpha and test (11), 1 - a and its reciprocal, T_i, weight (4),
+#   gradient-weighted colour (4), dL/da (2), its running sum (1), colour and
+#   depth gradients (4), opacity term and dL/dpower (3), the offset products
+#   (2) and the five geometric sums (5) = 36;
+#  scoring: alpha with the opacity inside the exponent (9), test (1), next
+#   transmittance, its test, weight, uncertainty accumulation (4) = 14.
+OPS_PER_PAIR = {"render": 18.0, "render_backward": 36.0, "score": 14.0}
 # FP32 vector peak in lane-operations per second: 256 CUs x 4 SIMDs x 32 lanes
 # per cycle (a wave64 instruction every 2 cycles) x 2.4 GHz = 78.6e12, i.e. the
 # 157.3 TFLOP/s FP32 vector figure counting a fused multiply-add as one operation

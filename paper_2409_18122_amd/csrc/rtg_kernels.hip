@@ -1772,12 +1772,16 @@ __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
 //   2, 3, 4: sum dpow dx^2, sum dpow dx dy, sum dpow dy^2 (dL/dQ);
 //   5: sum dL/da G (the opacity's gradient: a = o G below alpha_max);
 //   6..9: sum g_ch w (colour and depth).
+// G is 0 where alpha is clamped at alpha_max (no gradient flows through
+// the clamp).  A splat with a = 0 and G = 0 leaves T (1 / (1 - 0) = 1
+// exactly), D and every sum unchanged, for finite pixel gradients and
+// colours.
 // AU: the alpha and uncertainty images carry gradients too (colour 1 and u
 // in GA; otherwise their terms are left out altogether).
 template <bool AU>
-__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 g1, float4 at, float ui,
-                                          float amax, float nho, float gr, float gg, float gb, float gd, float ga,
-                                          float gu, float& T, float& D, float* acc) {
+__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 at, float ui, float nho,
+                                          float gr, float gg, float gb, float gd, float ga, float gu, float& T,
+                                          float& D, float* acc) {
     const float inv = __builtin_amdgcn_rcpf(1.0f - a);
     const float Ti = T * inv;
     const float w = a * Ti;
@@ -1796,18 +1800,16 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
     acc[8] = fmaf(gb, w, acc[8]);
     acc[9] = fmaf(gd, w, acc[9]);
     T = Ti;
-    if (g1.w * G <= amax) {
-        const float t0 = da * G;
-        acc[5] += t0;
-        // nho = -o / 2: dpow = dL/da * o * dG/dpower
-        const float dpow = t0 * nho;
-        const float t1 = dpow * dx, t2 = dpow * dy;
-        acc[0] += t1;
-        acc[1] += t2;
-        acc[2] = fmaf(t1, dx, acc[2]);
-        acc[3] = fmaf(t1, dy, acc[3]);
-        acc[4] = fmaf(t2, dy, acc[4]);
-    }
+    const float t0 = da * G;
+    acc[5] += t0;
+    // nho = -o / 2: dpow = dL/da * o * dG/dpower
+    const float dpow = t0 * nho;
+    const float t1 = dpow * dx, t2 = dpow * dy;
+    acc[0] += t1;
+    acc[1] += t2;
+    acc[2] = fmaf(t1, dx, acc[2]);
+    acc[3] = fmaf(t1, dy, acc[3]);
+    acc[4] = fmaf(t2, dy, acc[4]);
 }
 
 // NW waves per tile; the tile's 8x8 pixel blocks are dealt to the waves in
@@ -1932,7 +1934,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 #pragma unroll
             for (int q = 1; q < BWD_STEP; q++) ks[q] = pop_high<NW>(m);
             float4 sg0[BWD_STEP], sg1[BWD_STEP], sat[BWD_STEP];
-            float su[BWD_STEP];
+            float su[BWD_STEP], nho[BWD_STEP];
             uint32_t sr[BWD_STEP], spos[BWD_STEP];
 #pragma unroll
             for (int q = 0; q < BWD_STEP; q++) {
@@ -1942,6 +1944,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 sat[q] = s_at[k];
                 su[q] = AU ? s_u[k] : 0.0f;
                 sr[q] = s_r[k];
+                nho[q] = -0.5f * sg1[q].w;
                 spos[q] = ks[q] < 0 ? 0xffffffffu : (uint32_t)(bstart + ks[q]);
             }
             float acc[BWD_STEP][10];
@@ -1969,13 +1972,17 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                         if ((spos[q] < last[j]) & (a[q] >= nlo) & (a[q] <= nhi))
                             a[q] = redecide(a[q], rec, sr[q], ux(j), vy(j), st);
                 }
+                // predicated, not branched: a splat the pixel does not take
+                // enters with alpha 0 and G 0, which leaves T, D and the sums
+                // unchanged
 #pragma unroll
                 for (int q = 0; q < BWD_STEP; q++) {
-                    if ((spos[q] < last[j]) & (a[q] >= st.alpha_min)) {
-                        any[q] = true;
-                        bwd_pixel<AU>(a[q], G[q], dx[q], dy[q], sg1[q], sat[q], su[q], amax, -0.5f * sg1[q].w,
-                                      gr[j], gg[j], gb[j], gd[j], ga[j], gu[j], T[j], D[j], acc[q]);
-                    }
+                    const bool ok = (spos[q] < last[j]) & (a[q] >= st.alpha_min);
+                    any[q] = any[q] | ok;
+                    const float a0 = ok ? a[q] : 0.0f;
+                    const float G0 = (ok & (sg1[q].w * G[q] <= amax)) ? G[q] : 0.0f;
+                    bwd_pixel<AU>(a0, G0, dx[q], dy[q], sat[q], su[q], nho[q], gr[j], gg[j], gb[j], gd[j], ga[j],
+                                  gu[j], T[j], D[j], acc[q]);
                 }
             }
             bool t[BWD_STEP];
