@@ -330,11 +330,16 @@ rtg_status rtg_score_graph_status(rtg_graph *gr);
 void rtg_score_graph_destroy(rtg_graph *gr);
 
 /* Autotuner: times `mode` (0 forward, 1 forward+backward, 2 scoring) on the
- * given map and cameras for each tile in {8x8, 16x16, 32x8} with one splat
- * staged per thread, then for the fastest tile each smaller staging batch in
- * {32, 64, 128}; writes the fastest into settings->tile_w/tile_h/batch and
- * makes it the context's choice for settings with tile 0x0.  Images, scores
- * and gradients do not depend on the choice.  Synchronises `stream`. */
+ * given map and cameras for every tile in {8x8, 16x16, 32x8} with every
+ * staging batch in {0 (one splat per thread of the tile), 32, 64, 128} below
+ * the tile's pixel count (10 candidates); a candidate's cost is the median
+ * over three calls (after one warm-up) of its kernels' device time, taken
+ * with the library's per-group events (the eager calls' host reads are left
+ * out, as in a captured graph).  Writes the fastest into
+ * settings->tile_w/tile_h/batch and makes it the context's choice for
+ * settings with tile 0x0.  The caller's rtg_timing totals are left as they
+ * were.  Images, scores and gradients do not depend on the choice.
+ * Synchronises `stream`. */
 rtg_status rtg_autotune(rtg_ctx *ctx, const rtg_gaussians *g, const rtg_camera *cams,
                         int32_t n_views, int32_t mode, rtg_settings *settings, void *stream);
 

@@ -1408,71 +1408,79 @@ rtg_status rtg_autotune(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* 
     fill_u32(grads.as<uint32_t>(), 0u, 14 * (uint64_t)std::max<int64_t>(g->n, 1), s);
     float* gp = grads.as<float>();
     rtg_grads gr{gp, gp + 3 * g->n, gp + 6 * g->n, gp + 10 * g->n, gp + 11 * g->n};
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    // one timed call of `mode` with the given settings (the first of three
-    // warms up; the best of the other two counts)
-    auto time_it = [&](const rtg_settings& st, float& ms_best) -> rtg_status {
-        ms_best = 1e30f;
-        for (int rep = 0; rep < 3; rep++) {
-            (void)hipEventRecord(e0, s);
-            rtg_status r = RTG_OK;
-            if (mode == 2) {
-                r = rtg_score_views(ctx, g, cams, n_views, &st, scores.as<double>(), 1, 0, stream);
-            } else {
-                rtg_frame* f = nullptr;
-                r = rtg_project(ctx, g, cams, n_views, &st, &f, stream);
-                if (r == RTG_OK) r = rtg_bin_sort(ctx, f, nullptr, stream);
-                if (r == RTG_OK)
-                    r = rtg_render(ctx, f, im, im + 3 * pix, im + 4 * pix, g->uncert ? im + 5 * pix : nullptr, stream);
-                if (r == RTG_OK && mode == 1) {
-                    float* d = dimg.as<float>();
-                    r = rtg_render_backward(ctx, f, d, d + 3 * pix, nullptr, nullptr, &gr, stream);
-                }
-                rtg_frame_destroy(f);
-            }
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            if (r != RTG_OK) return r;
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) ms_best = std::min(ms_best, ms);
+    // The cost of a candidate is the device time of its kernels, read from
+    // the library's per-group event timers: the eager calls' host reads of
+    // the pair counts are left out, so this is the work a captured graph of
+    // the same call replays.  The caller's timer totals are kept aside.
+    drain_timers(ctx);
+    const bool was_timing = ctx->timing;
+    double saved_ms[N_TIMERS];
+    int64_t saved_n[N_TIMERS];
+    for (int i = 0; i < N_TIMERS; i++) {
+        saved_ms[i] = ctx->timer_ms[i];
+        saved_n[i] = ctx->timer_n[i];
+    }
+    ctx->timing = true;
+    auto device_ms = [&]() {
+        drain_timers(ctx);
+        double t = 0.0;
+        for (int i = 0; i < N_TIMERS; i++) t += ctx->timer_ms[i];
+        return t;
+    };
+    auto run_once = [&](const rtg_settings& st) -> rtg_status {
+        if (mode == 2) return rtg_score_views(ctx, g, cams, n_views, &st, scores.as<double>(), 1, 0, stream);
+        rtg_frame* f = nullptr;
+        rtg_status r = rtg_project(ctx, g, cams, n_views, &st, &f, stream);
+        if (r == RTG_OK) r = rtg_bin_sort(ctx, f, nullptr, stream);
+        if (r == RTG_OK) r = rtg_render(ctx, f, im, im + 3 * pix, im + 4 * pix, g->uncert ? im + 5 * pix : nullptr, stream);
+        if (r == RTG_OK && mode == 1) {
+            float* d = dimg.as<float>();
+            r = rtg_render_backward(ctx, f, d, d + 3 * pix, nullptr, nullptr, &gr, stream);
         }
+        rtg_frame_destroy(f);
+        return r;
+    };
+    // one warm-up call, then the median of three timed ones
+    auto time_it = [&](const rtg_settings& st, double& ms) -> rtg_status {
+        double t[3];
+        for (int rep = 0; rep < 4; rep++) {
+            const double before = device_ms();
+            RTG_TRY(run_once(st));
+            const double after = device_ms();
+            if (rep > 0) t[rep - 1] = after - before;
+        }
+        std::sort(t, t + 3);
+        ms = t[1];
         return RTG_OK;
     };
-    // the tile first (one splat staged per thread), then the staging batch
-    float best = 1e30f;
+    // every tile with every staging batch below its pixel count (0: one
+    // splat per thread of the tile)
+    static const int batches[4] = {0, 32, 64, 128};
+    double best = 1e300;
     int bi = 1, bb = 0;
     rtg_status rs = RTG_OK;
     for (int t = 0; t < 3 && rs == RTG_OK; t++) {
-        rtg_settings st = *settings;
-        st.tile_w = tiles[t][0];
-        st.tile_h = tiles[t][1];
-        st.batch = 0;
-        float ms;
-        rs = time_it(st, ms);
-        if (rs == RTG_OK && ms < best) {
-            best = ms;
-            bi = t;
+        for (int k = 0; k < 4 && rs == RTG_OK; k++) {
+            if (batches[k] >= tiles[t][0] * tiles[t][1]) continue;
+            rtg_settings st = *settings;
+            st.tile_w = tiles[t][0];
+            st.tile_h = tiles[t][1];
+            st.batch = batches[k];
+            double ms = 0.0;
+            rs = time_it(st, ms);
+            if (rs == RTG_OK && ms < best) {
+                best = ms;
+                bi = t;
+                bb = batches[k];
+            }
         }
     }
-    static const int batches[3] = {32, 64, 128};
-    for (int k = 0; k < 3 && rs == RTG_OK; k++) {
-        if (batches[k] >= tiles[bi][0] * tiles[bi][1]) break;
-        rtg_settings st = *settings;
-        st.tile_w = tiles[bi][0];
-        st.tile_h = tiles[bi][1];
-        st.batch = batches[k];
-        float ms;
-        rs = time_it(st, ms);
-        if (rs == RTG_OK && ms < best) {
-            best = ms;
-            bb = batches[k];
-        }
+    drain_timers(ctx);
+    ctx->timing = was_timing;
+    for (int i = 0; i < N_TIMERS; i++) {
+        ctx->timer_ms[i] = saved_ms[i];
+        ctx->timer_n[i] = saved_n[i];
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rs != RTG_OK) return rs;
     settings->tile_w = tiles[bi][0];
     settings->tile_h = tiles[bi][1];
