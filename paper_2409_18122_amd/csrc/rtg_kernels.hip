@@ -2451,24 +2451,63 @@ __device__ __forceinline__ bool fov_exact(double mx0, double my0, double mz0, co
     return mx >= 0.0 && mx <= (double)(V.W - 1) && my >= 0.0 && my <= (double)(V.H - 1);
 }
 
-// 1 visible, 0 not, -1 undecided in binary32
-__device__ __forceinline__ int fov_fast(float x, float y, float z, const ViewDev& V, float z_near, float range) {
-    float dx = x - (float)V.T[0], dy = y - (float)V.T[1], dz = z - (float)V.T[2];
-    float mag = fabsf(dx) + fabsf(dy) + fabsf(dz) + 1.0f;
-    float tx = dx * (float)V.R[0] + dy * (float)V.R[3] + dz * (float)V.R[6];
-    float ty = dx * (float)V.R[1] + dy * (float)V.R[4] + dz * (float)V.R[7];
-    float tz = dx * (float)V.R[2] + dy * (float)V.R[5] + dz * (float)V.R[8];
-    float ez = 1e-5f * mag;
-    if (tz <= z_near - ez || tz > range + ez) return 0;
-    if (tz <= z_near + ez || tz > range - ez) return -1;
-    float mx = (float)V.fx * tx / tz + (float)V.cx;
-    float my = (float)V.fy * ty / tz + (float)V.cy;
-    float m = 1e-3f * (1.0f + fabsf(mx) + fabsf(my)) + 1e-3f * mag * ((float)V.fx + (float)V.fy) / tz;
-    float W1 = (float)(V.W - 1), H1 = (float)(V.H - 1);
-    if (mx < -m || mx > W1 + m || my < -m || my > H1 + m) return 0;
-    if (mx > m && mx < W1 - m && my > m && my < H1 - m) return 1;
-    return -1;
+// A view's binary32 values for the field-of-view screen (the camera's own
+// binary32 values: its binary64 fields are these, widened).
+struct ViewF {
+    float T[3], R[9], fx, fy, cx, cy, W1, H1, kf, pad;
+};
+
+__device__ __forceinline__ ViewF view_f(const ViewDev& V) {
+    ViewF f;
+#pragma unroll
+    for (int k = 0; k < 3; k++) f.T[k] = V.Tf[k];
+#pragma unroll
+    for (int k = 0; k < 9; k++) f.R[k] = V.Rf[k];
+    f.fx = V.fxf;
+    f.fy = V.fyf;
+    f.cx = V.cxf;
+    f.cy = V.cyf;
+    f.W1 = (float)(V.W - 1);
+    f.H1 = (float)(V.H - 1);
+    f.kf = 1e-3f * (V.fxf + V.fyf);
+    f.pad = 0.0f;
+    return f;
 }
+
+// Binary32 screen of the field-of-view test: 1 certainly visible, 0
+// certainly not, -1 too close to a depth limit or an image border to tell
+// (the binary64 test then decides).  Branch-free: every Gaussian of a wave
+// takes the same instructions.
+__device__ __forceinline__ int fov_fast(float x, float y, float z, const ViewF& V, float z_near, float range) {
+    const float dx = x - V.T[0], dy = y - V.T[1], dz = z - V.T[2];
+    const float mag = fabsf(dx) + fabsf(dy) + fabsf(dz) + 1.0f;
+    const float tx = fmaf(dz, V.R[6], fmaf(dy, V.R[3], dx * V.R[0]));
+    const float ty = fmaf(dz, V.R[7], fmaf(dy, V.R[4], dx * V.R[1]));
+    const float tz = fmaf(dz, V.R[8], fmaf(dy, V.R[5], dx * V.R[2]));
+    const float ez = 1e-5f * mag;
+    // hardware reciprocal (within an ulp or two): far inside the margin m
+    const float iz = __builtin_amdgcn_rcpf(tz);
+    const float mx = fmaf(V.fx * tx, iz, V.cx);
+    const float my = fmaf(V.fy * ty, iz, V.cy);
+    const float m = fmaf(1e-3f, 1.0f + fabsf(mx) + fabsf(my), V.kf * mag * iz);
+    const bool out = (tz <= z_near - ez) | (tz > range + ez) | (mx < -m) | (mx > V.W1 + m) | (my < -m) |
+                     (my > V.H1 + m);
+    const bool in = (tz > z_near + ez) & (tz <= range - ez) & (mx > m) & (mx < V.W1 - m) & (my > m) &
+                    (my < V.H1 - m);
+    return out ? 0 : (in ? 1 : -1);
+}
+
+__device__ __noinline__ bool fov_exact_call(float x, float y, float z, const ViewDev& V, float z_near, float range) {
+    return fov_exact((double)x, (double)y, (double)z, V, (double)z_near, (double)range);
+}
+
+// Work split: a block takes UT_VB views (their screen values in LDS) and a
+// share of the Gaussians, streamed UT_G per thread per step with coalesced
+// loads; each thread keeps its counts and fixed-point sum per view in
+// registers and the wave reduces them once at the end.  Counts and sums are
+// integers: the result does not depend on the order.
+constexpr int UT_VB = 8;
+constexpr int UT_G = 4;
 
 __global__ __launch_bounds__(UT_THREADS) void k_view_utility(GaussDev g, const ViewDev* __restrict__ views, int nv,
                                                              float z_near, float range,
@@ -2476,47 +2515,86 @@ __global__ __launch_bounds__(UT_THREADS) void k_view_utility(GaussDev g, const V
                                                              unsigned long long* __restrict__ cnt_h,
                                                              unsigned long long* __restrict__ cnt_l,
                                                              unsigned long long* __restrict__ fix_u) {
-    extern __shared__ unsigned long long s_acc[];  // 3 * nv
-    for (int i = threadIdx.x; i < 3 * nv; i += UT_THREADS) s_acc[i] = 0ull;
+    __shared__ ViewF s_v[UT_VB];
+    const int v0 = (int)blockIdx.y * UT_VB;
+    const int nvb = min(UT_VB, nv - v0);
+    if ((int)threadIdx.x < nvb) s_v[threadIdx.x] = view_f(views[v0 + threadIdx.x]);
     __syncthreads();
     const double lo = lo_hi[0], hi = lo_hi[1];
     const int64_t n = g.n;
-    for (int64_t base = (int64_t)blockIdx.x * UT_THREADS; base < n; base += (int64_t)gridDim.x * UT_THREADS) {
-        const int64_t i = base + threadIdx.x;
-        const bool live = i < n;
-        float x = 0.0f, y = 0.0f, z = 0.0f, u = 0.0f;
-        if (live) {
-            x = g.means[i];
-            y = g.means[n + i];
-            z = g.means[2 * n + i];
-            u = g.uncert[i];
-        }
-        const bool ok = live && isfinite(x) && isfinite(y) && isfinite(z);
-        const bool isH = (double)u > hi, isL = (double)u < lo;
-        const unsigned long long fu = (isfinite(u) && u > 0.0f) ? (unsigned long long)((double)u * FIX_SCALE) : 0ull;
-        for (int v = 0; v < nv; v++) {
-            const ViewDev& V = views[v];
-            bool vis = false;
-            if (ok) {
-                int f = fov_fast(x, y, z, V, z_near, range);
-                vis = f < 0 ? fov_exact((double)x, (double)y, (double)z, V, (double)z_near, (double)range) : f == 1;
-            }
-            const uint64_t bh = __ballot(vis && isH), bl = __ballot(vis && isL);
-            unsigned long long su = vis ? fu : 0ull;
+    uint32_t ch[UT_VB], cl[UT_VB];
+    unsigned long long su[UT_VB];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) su += __shfl_xor(su, o, 64);
-            if (lane_id() == 0 && (bh | bl | su)) {
-                atomicAdd(&s_acc[3 * v + 0], (unsigned long long)__popcll(bh));
-                atomicAdd(&s_acc[3 * v + 1], (unsigned long long)__popcll(bl));
-                atomicAdd(&s_acc[3 * v + 2], su);
+    for (int b = 0; b < UT_VB; b++) {
+        ch[b] = cl[b] = 0u;
+        su[b] = 0ull;
+    }
+    constexpr int64_t CH = (int64_t)UT_THREADS * UT_G;
+    for (int64_t base = (int64_t)blockIdx.x * CH; base < n; base += (int64_t)gridDim.x * CH) {
+        float x[UT_G], y[UT_G], z[UT_G];
+        unsigned long long fu[UT_G];
+        uint32_t ok = 0, isH = 0, isL = 0;  // bit j: Gaussian j of this thread
+#pragma unroll
+        for (int j = 0; j < UT_G; j++) {
+            const int64_t i = base + (int64_t)j * UT_THREADS + threadIdx.x;
+            x[j] = y[j] = z[j] = 0.0f;
+            fu[j] = 0ull;
+            if (i < n) {
+                x[j] = g.means[i];
+                y[j] = g.means[n + i];
+                z[j] = g.means[2 * n + i];
+                const float u = g.uncert[i];
+                if (isfinite(x[j]) && isfinite(y[j]) && isfinite(z[j])) ok |= 1u << j;
+                if ((double)u > hi) isH |= 1u << j;
+                if ((double)u < lo) isL |= 1u << j;
+                fu[j] = (isfinite(u) && u > 0.0f) ? (unsigned long long)((double)u * FIX_SCALE) : 0ull;
             }
+        }
+        // the views' values are read from LDS in every step (a compiler
+        // barrier keeps them from being hoisted into registers, which would
+        // cost occupancy)
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int b = 0; b < UT_VB; b++) {
+            if (b >= nvb) break;
+            const ViewF V = s_v[b];
+            uint32_t vis = 0, unsure = 0;
+#pragma unroll
+            for (int j = 0; j < UT_G; j++) {
+                const int f = fov_fast(x[j], y[j], z[j], V, z_near, range);
+                vis |= (uint32_t)(f == 1) << j;
+                unsure |= (uint32_t)(f < 0) << j;
+            }
+            unsure &= ok;
+            // near a border or the depth limits the binary64 test decides
+            if (__ballot(unsure != 0)) {
+#pragma unroll
+                for (int j = 0; j < UT_G; j++)
+                    if (((unsure >> j) & 1u) && fov_exact_call(x[j], y[j], z[j], views[v0 + b], z_near, range))
+                        vis |= 1u << j;
+            }
+            vis &= ok;
+            ch[b] += __popc(vis & isH);
+            cl[b] += __popc(vis & isL);
+#pragma unroll
+            for (int j = 0; j < UT_G; j++) su[b] += ((vis >> j) & 1u) ? fu[j] : 0ull;
         }
     }
-    __syncthreads();
-    for (int v = threadIdx.x; v < nv; v += UT_THREADS) {
-        if (s_acc[3 * v + 0]) atomicAdd(cnt_h + v, s_acc[3 * v + 0]);
-        if (s_acc[3 * v + 1]) atomicAdd(cnt_l + v, s_acc[3 * v + 1]);
-        if (s_acc[3 * v + 2]) atomicAdd(fix_u + v, s_acc[3 * v + 2]);
+#pragma unroll
+    for (int b = 0; b < UT_VB; b++) {
+        if (b >= nvb) break;
+        unsigned long long h = ch[b], l = cl[b], t = su[b];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            h += __shfl_xor(h, o, 64);
+            l += __shfl_xor(l, o, 64);
+            t += __shfl_xor(t, o, 64);
+        }
+        if (lane_id() == 0) {
+            if (h) atomicAdd(cnt_h + v0 + b, h);
+            if (l) atomicAdd(cnt_l + v0 + b, l);
+            if (t) atomicAdd(fix_u + v0 + b, t);
+        }
     }
 }
 
@@ -2740,9 +2818,12 @@ void view_utility(const GaussDev& g, const ViewDev* views, int nv, float z_near,
                   hipStream_t s) {
     fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, (uint64_t)6 * nv, s);
     if (g.n > 0) {
-        unsigned grid = grid_for((uint64_t)g.n, UT_THREADS, 1024);
-        size_t lds = sizeof(unsigned long long) * 3 * (size_t)nv;
-        k_view_utility<<<grid, UT_THREADS, lds, s>>>(g, views, nv, z_near, range, lo_hi, acc, acc + nv, acc + 2 * nv);
+        // about 2048 blocks over (Gaussian shares) x (groups of UT_VB views)
+        const unsigned gy = (unsigned)((nv + UT_VB - 1) / UT_VB);
+        const unsigned gmax = grid_for(((uint64_t)g.n + UT_G - 1) / UT_G, UT_THREADS, 1u << 20);
+        const unsigned gx = std::max(1u, std::min(gmax, (2048u + gy - 1) / gy));
+        k_view_utility<<<dim3(gx, gy), UT_THREADS, 0, s>>>(g, views, nv, z_near, range, lo_hi, acc, acc + nv,
+                                                           acc + 2 * nv);
     }
     k_utility_finish<<<(nv + 255) / 256, 256, 0, s>>>(nv, acc, acc + nv, acc + 2 * nv, lambda, n_high, n_low, sum_u,
                                                       xi);

@@ -12,6 +12,7 @@ import json
 import os
 import weakref
 
+import numpy as np
 import torch
 
 from . import _lib as _lib_mod
@@ -50,11 +51,22 @@ def make_settings(settings=None) -> Settings:
                     float(s["eps2d"]), int(s["max_instances"]), int(s["isotropic"]), 0)
 
 
+def _host_f64(x):
+    if isinstance(x, torch.Tensor):
+        x = x.detach().cpu().numpy()
+    return np.asarray(x, dtype=np.float64)
+
+
 def make_cameras(cams):
+    """The C camera array of a list of camera dicts; an array made by this
+    function is passed through unchanged (build it once to call an entry
+    point many times on the same views)."""
+    if isinstance(cams, ctypes.Array):
+        return cams
     arr = (Camera * len(cams))()
     for i, c in enumerate(cams):
-        R = [float(x) for x in torch.as_tensor(c["R"], dtype=torch.float64).reshape(9)]
-        T = [float(x) for x in torch.as_tensor(c["T"], dtype=torch.float64).reshape(3)]
+        R = _host_f64(c["R"]).reshape(9).tolist()
+        T = _host_f64(c["T"]).reshape(3).tolist()
         arr[i] = Camera(int(c["width"]), int(c["height"]), float(c["fx"]), float(c["fy"]),
                         float(c["cx"]), float(c["cy"]), (ctypes.c_float * 9)(*R),
                         (ctypes.c_float * 3)(*T))
