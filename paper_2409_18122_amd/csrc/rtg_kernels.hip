@@ -1046,6 +1046,10 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
     __shared__ uint32_t s_roff[EM_ITEMS + 1];  // first table row of each record (prefix of row counts)
     __shared__ uint32_t s_row[EM_ROWS];        // first tile column | pairs of the row << 16
     __shared__ uint32_t s_rpre[EM_ROWS + 1];   // pairs of all table rows before this one
+    // per record of the chunk: its id, its first tile row's global tile id
+    // minus tx0, tx0 | nx << 16, and its view's tiles per row
+    __shared__ uint32_t s_rid[EM_ITEMS], s_tbase[EM_ITEMS], s_tx[EM_ITEMS];
+    __shared__ uint16_t s_tpr[EM_ITEMS];
     __shared__ uint32_t ws[SC_THREADS / 64];
     __shared__ uint32_t s_lo;
     // every tile starts empty; k_tile_ranges later fills the occupied ones
@@ -1094,10 +1098,17 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
             const uint32_t jr = threadIdx.x * EM_RUN + q;
             nr[q] = 0;
             if (jr < nrec) {
-                const EmitRec e = rec.emit[order[lo + jr]];
-                const uint32_t nx = (e.rect.x >> 16) - (e.rect.x & 0xffffu) + 1;
-                const uint32_t ny = (e.rect.y >> 16) - (e.rect.y & 0xffffu) + 1;
+                const uint32_t rid = order[lo + jr];
+                const EmitRec e = rec.emit[rid];
+                const uint32_t tx0 = e.rect.x & 0xffffu, ty0 = e.rect.y & 0xffffu;
+                const uint32_t nx = (e.rect.x >> 16) - tx0 + 1;
+                const uint32_t ny = (e.rect.y >> 16) - ty0 + 1;
                 nr[q] = e.ntiles == nx * ny ? 0u : ny;
+                const ViewDev& V = views[e.view];
+                s_rid[jr] = rid;
+                s_tbase[jr] = V.tile_off + ty0 * (uint32_t)V.tiles_x;
+                s_tx[jr] = tx0 | (nx << 16);
+                s_tpr[jr] = (uint16_t)V.tiles_x;
             }
             nsum += nr[q];
         }
@@ -1115,7 +1126,7 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
             __syncthreads();
             for (uint32_t t = threadIdx.x; t < total_rows; t += EM_THREADS) {
                 const uint32_t jr = last_le(s_roff, nrec, t);
-                const EmitRec e = rec.emit[order[lo + jr]];
+                const EmitRec e = rec.emit[s_rid[jr]];
                 const SupportRows S = support_setup(e.g0, e.g1, e.pbox, log2_amin);
                 const uint2 fc = support_row(S, (e.rect.y & 0xffffu) + (t - s_roff[jr]), tws, ths);
                 s_row[t] = fc.x | (fc.y << 16);
@@ -1147,22 +1158,19 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
         const int n = (int)min<uint32_t>(EM_RUN, k1 - kb);
         if (staged) {
             uint32_t j = last_le(s_off, nrec, kb);
-            uint32_t r = 0xffffffffu, base = 0, t0 = 0, t1 = 0, tx0 = 0, ty0 = 0, nx = 1, toff = 0, tiles_x = 0;
+            uint32_t jc = 0xffffffffu, r = 0, base = 0, t0 = 0, t1 = 0, tx0 = 0, nx = 1, tb = 0, tiles_x = 0;
 #pragma unroll
             for (int q = 0; q < EM_RUN; q++) {
                 if (q >= n) break;
                 const uint32_t kq = kb + q;
                 while (j + 1 < nrec && kq >= s_off[j + 1]) j++;
-                const uint32_t rj = order[lo + j];
-                if (rj != r) {
-                    r = rj;
-                    const EmitRec e = rec.emit[r];
-                    tx0 = e.rect.x & 0xffffu;
-                    nx = (e.rect.x >> 16) - tx0 + 1;
-                    ty0 = e.rect.y & 0xffffu;
-                    const ViewDev& V = views[e.view];
-                    toff = V.tile_off;
-                    tiles_x = (uint32_t)V.tiles_x;
+                if (j != jc) {
+                    jc = j;
+                    r = s_rid[j];
+                    tx0 = s_tx[j] & 0xffffu;
+                    nx = s_tx[j] >> 16;
+                    tb = s_tbase[j];
+                    tiles_x = s_tpr[j];
                     t0 = s_roff[j];
                     t1 = s_roff[j + 1];
                     base = s_rpre[t0];
@@ -1170,12 +1178,12 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
                 const uint32_t li = kq - s_off[j];
                 uint32_t tile;
                 if (t0 == t1) {  // every tile of the rectangle
-                    tile = toff + (ty0 + li / nx) * tiles_x + tx0 + li % nx;
+                    tile = tb + (li / nx) * tiles_x + tx0 + li % nx;
                 } else if (s_rpre[t1] == base) {
                     // a support that meets no tile still owns one pair, its
                     // box's first tile; anything else is a counting mismatch
                     if (li != 0) atomicOr(flags, FLAG_BIN_MISMATCH);
-                    tile = toff + ty0 * tiles_x + tx0;
+                    tile = tb + tx0;
                 } else {
                     // the last row whose pairs start at or before li (empty
                     // rows share the next row's start, so it is not empty)
@@ -1188,7 +1196,7 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
                     const uint32_t row = s_row[a];
                     const uint32_t col = (row & 0xffffu) + (li - (s_rpre[a] - base));
                     if (li - (s_rpre[a] - base) >= (row >> 16)) atomicOr(flags, FLAG_BIN_MISMATCH);
-                    tile = toff + (ty0 + (a - t0)) * tiles_x + col;
+                    tile = tb + (a - t0) * tiles_x + col;
                 }
                 tk[q] = tile;
                 tr[q] = r;
