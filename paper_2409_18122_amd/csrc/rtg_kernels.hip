@@ -1789,7 +1789,7 @@ __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
 // colours.
 // AU: the alpha and uncertainty images carry gradients too (colour 1 and u
 // in GA; otherwise their terms are left out altogether).
-template <bool AU>
+template <bool AU, bool FIRST = false>
 __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 at, float ui, float nho,
                                           float gr, float gg, float gb, float gd, float ga, float gu, float& T,
                                           float& D, float* acc) {
@@ -1806,21 +1806,34 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
     }
     const float da = fmaf(Ti, GA, -(D * inv));
     D = fmaf(w, GA, D);
-    acc[6] = fmaf(gr, w, acc[6]);
-    acc[7] = fmaf(gg, w, acc[7]);
-    acc[8] = fmaf(gb, w, acc[8]);
-    acc[9] = fmaf(gd, w, acc[9]);
     T = Ti;
     const float t0 = da * G;
-    acc[5] += t0;
     // nho = -o / 2: dpow = dL/da * o * dG/dpower
     const float dpow = t0 * nho;
     const float t1 = dpow * dx, t2 = dpow * dy;
-    acc[0] += t1;
-    acc[1] += t2;
-    acc[2] = fmaf(t1, dx, acc[2]);
-    acc[3] = fmaf(t1, dy, acc[3]);
-    acc[4] = fmaf(t2, dy, acc[4]);
+    if constexpr (FIRST) {
+        acc[6] = gr * w;
+        acc[7] = gg * w;
+        acc[8] = gb * w;
+        acc[9] = gd * w;
+        acc[5] = t0;
+        acc[0] = t1;
+        acc[1] = t2;
+        acc[2] = t1 * dx;
+        acc[3] = t1 * dy;
+        acc[4] = t2 * dy;
+    } else {
+        acc[6] = fmaf(gr, w, acc[6]);
+        acc[7] = fmaf(gg, w, acc[7]);
+        acc[8] = fmaf(gb, w, acc[8]);
+        acc[9] = fmaf(gd, w, acc[9]);
+        acc[5] += t0;
+        acc[0] += t1;
+        acc[1] += t2;
+        acc[2] = fmaf(t1, dx, acc[2]);
+        acc[3] = fmaf(t1, dy, acc[3]);
+        acc[4] = fmaf(t2, dy, acc[4]);
+    }
 }
 
 // NW waves per tile; the tile's 8x8 pixel blocks are dealt to the waves in
@@ -2013,6 +2026,197 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                     if (q ? t[1] : t[0])
                         unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + (v - 10 * q), (double)tot);
                 }
+            }
+        }
+    }
+}
+
+// The one-wave form of k_render_bwd (a tile per wave): the staging lanes
+// keep only the splats whose box meets the tile and write them compacted, in
+// ascending order, to LDS, so the walk back to front is a plain countdown
+// with no mask scanning; the wave loads the next step's two splats while it
+// computes the current one.  Every pixel sees the same splats in the same
+// order, with the same arithmetic, as in k_render_bwd, and every splat's
+// per-tile sums are reduced by the same lane tree, so the two kernels add
+// identical partial gradients.  Slot B holds the null splat: position
+// 0xffffffff (no pixel takes it), zero geometry and colour.
+template <int TW, int TH, bool AU>
+__global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* __restrict__ views, int n_views,
+                                                        const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ inst_rec, Records rec,
+                                                        SetDev st, const float* __restrict__ T_final,
+                                                        const uint32_t* __restrict__ n_last,
+                                                        const float* __restrict__ d_rgb,
+                                                        const float* __restrict__ d_depth,
+                                                        const float* __restrict__ d_alpha,
+                                                        const float* __restrict__ d_unc, double* __restrict__ g2d,
+                                                        const uint32_t* __restrict__ flags) {
+    constexpr int PPT = TW * TH / 64;
+    constexpr int B = 64;
+    static_assert(PPT >= 1 && PPT * 64 == TW * TH, "the tile must be whole 8x8 blocks");
+    if (flags && *flags) return;
+    // s_p = (mean x, mean y relative to the origin, record id bits, position bits)
+    __shared__ float4 s_p[B + 1], s_g1[B + 1], s_at[B + 1];
+    __shared__ float s_u[B + 1];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t vi = view_of_tile(views, n_views, tile);
+    const ViewDev& V = views[vi];
+    const int W = V.W, H = V.H;
+    const uint32_t lt = tile - V.tile_off;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const uint2 rg = ranges[tile];
+    const uint64_t P = (uint64_t)W * H;
+    const int lane = (int)threadIdx.x;
+    if (lane == 0) {
+        s_p[B] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(0xffffffffu));
+        s_g1[B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        s_at[B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        s_u[B] = 0.0f;
+    }
+
+    const int ox = origin_x(tx * TW), oy = origin_y(ty * TH);
+    const float px0 = (float)(tx * TW - ox + (lane & 7)), py0 = (float)(ty * TH - oy + (lane >> 3));
+    auto bx = [&](int j) { return (float)((j % (TW / 8)) * 8); };
+    auto by = [&](int j) { return (float)((j / (TW / 8)) * 8); };
+    auto ux = [&](int j) { return tx * TW + (j % (TW / 8)) * 8 + (lane & 7); };
+    auto vy = [&](int j) { return ty * TH + (j / (TW / 8)) * 8 + (lane >> 3); };
+    float T[PPT];
+    uint32_t last[PPT];
+    float gr[PPT], gg[PPT], gb[PPT], gd[PPT], ga[PPT], gu[PPT];
+    float D[PPT];
+    uint32_t mylast = 0;
+    const int c0 = tx * TW, c1 = c0 + TW - 1, r0 = ty * TH, r1 = r0 + TH - 1;  // the tile's pixels
+#pragma unroll
+    for (int j = 0; j < PPT; j++) {
+        const int u = ux(j), v = vy(j);
+        T[j] = 1.0f;
+        last[j] = 0;
+        gr[j] = gg[j] = gb[j] = gd[j] = ga[j] = gu[j] = 0.0f;
+        D[j] = 0.0f;
+        if (u < W && v < H) {
+            const uint64_t pix = V.pix_off + (uint64_t)v * W + u;
+            T[j] = T_final[pix];
+            last[j] = n_last[pix];
+            if (d_rgb) {
+                const float* cb = d_rgb + 3 * V.pix_off + (uint64_t)v * W + u;
+                gr[j] = cb[0];
+                gg[j] = cb[P];
+                gb[j] = cb[2 * P];
+            }
+            if (d_depth) gd[j] = d_depth[pix];
+            if (AU && d_alpha) ga[j] = d_alpha[pix];
+            if (AU && d_unc) gu[j] = d_unc[pix];
+        }
+        mylast = max(mylast, last[j]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, (uint32_t)__shfl_xor((int)mylast, o, 64));
+    const uint32_t maxlast = mylast;
+    const float amax = st.alpha_max;
+    const float nlo = st.alpha_min - REFINE * st.alpha_min, nhi = st.alpha_min + REFINE * st.alpha_min;
+
+    for (int64_t bend = maxlast; bend > 0; bend -= B) {
+        const int64_t bstart = bend - B > 0 ? bend - B : 0;
+        __syncthreads();
+        bool hit = false;
+        float4 p, q1, at;
+        float uv = 0.0f;
+        {
+            const int64_t e = bstart + lane;
+            if (e < bend) {
+                const uint32_t r = inst_rec[rg.x + (uint32_t)e];
+                const EmitRec er = rec.emit[r];
+                hit = box_meets(er.pbox, c0, c1, r0, r1);
+                const float4 m = rel_mean(er.g0, ox, oy);
+                p = make_float4(m.x, m.y, __uint_as_float(r), __uint_as_float((uint32_t)e));
+                q1 = er.g1;
+                at = rec.attr[r];
+                if (AU) uv = __uint_as_float(er.unc);
+            }
+        }
+        const uint64_t hm = __ballot(hit);
+        const int n = (int)__popcll(hm);
+        if (hit) {
+            const int slot = (int)__popcll(hm & lanemask_lt());
+            s_p[slot] = p;
+            s_g1[slot] = q1;
+            s_at[slot] = at;
+            if (AU) s_u[slot] = uv;
+        }
+        __syncthreads();
+        // back to front over slots n - 1, n - 2, ..., two per step
+        for (int i = n - 1; i >= 0; i -= 2) {
+            float4 cp[2], cg[2], ca[2];
+            float cu[2];
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const int k = i - q >= 0 ? i - q : B;
+                cp[q] = s_p[k];
+                cg[q] = s_g1[k];
+                ca[q] = s_at[k];
+                cu[q] = AU ? s_u[k] : 0.0f;
+            }
+            float nho[2];
+            uint32_t sr[2], spos[2];
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                sr[q] = __float_as_uint(cp[q].z);
+                spos[q] = __float_as_uint(cp[q].w);
+                nho[q] = -0.5f * cg[q].w;
+            }
+            float acc[2][10];
+            bool any[2];
+#pragma unroll
+            for (int q = 0; q < 2; q++) any[q] = false;
+            // every alpha of the step first (one block of independent work),
+            // then the rare binary64 re-decisions, then the ordered updates
+            float a[PPT][2], G[PPT][2], dx[PPT][2], dy[PPT][2];
+            bool need = false;
+#pragma unroll
+            for (int j = 0; j < PPT; j++)
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    float w1, w2;
+                    a[j][q] = splat_alpha(cp[q].x, cp[q].y, cg[q], px0 + bx(j), py0 + by(j), amax, G[j][q],
+                                          dx[j][q], dy[j][q], w1, w2);
+                    need = need | ((spos[q] < last[j]) & (a[j][q] >= nlo) & (a[j][q] <= nhi));
+                }
+            if (__ballot(need)) {
+#pragma unroll
+                for (int j = 0; j < PPT; j++)
+#pragma unroll
+                    for (int q = 0; q < 2; q++)
+                        if ((spos[q] < last[j]) & (a[j][q] >= nlo) & (a[j][q] <= nhi))
+                            a[j][q] = redecide(a[j][q], rec, sr[q], ux(j), vy(j), st);
+            }
+#pragma unroll
+            for (int j = 0; j < PPT; j++) {
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const bool ok = (spos[q] < last[j]) & (a[j][q] >= st.alpha_min);
+                    any[q] = any[q] | ok;
+                    const float a0 = ok ? a[j][q] : 0.0f;
+                    const float G0 = (ok & (cg[q].w * G[j][q] <= amax)) ? G[j][q] : 0.0f;
+                    if (j == 0)
+                        bwd_pixel<AU, true>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], nho[q], gr[j], gg[j], gb[j],
+                                            gd[j], ga[j], gu[j], T[j], D[j], acc[q]);
+                    else
+                        bwd_pixel<AU>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], nho[q], gr[j], gg[j], gb[j], gd[j],
+                                      ga[j], gu[j], T[j], D[j], acc[q]);
+                }
+            }
+            bool t[2];
+#pragma unroll
+            for (int q = 0; q < 2; q++) t[q] = __ballot(any[q]) != 0;
+            // reduced unconditionally (a step that no pixel takes is rare), so
+            // that the per-pixel sums are formed pixel by pixel instead of
+            // being held back behind a branch
+            int v;
+            const float tot = wave_sum_halving20(&acc[0][0], lane, v);
+            if (lane < 32 && v >= 0) {
+                const int q = v >= 10 ? 1 : 0;
+                if (q ? t[1] : t[0])
+                    unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + (v - 10 * q), (double)tot);
             }
         }
     }
@@ -3032,7 +3236,15 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
     const bool au = d_alpha != nullptr || d_unc != nullptr;
 #define RTG_BWD_LAUNCH(TW_, TH_, NW_)                                                                          \
     do {                                                                                                       \
-        if (au)                                                                                                \
+        if (NW_ == 1 && au)                                                                                    \
+            k_render_bwd1<TW_, TH_, true><<<tiles_total, 64, 0, s>>>(                                          \
+                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
+                flags);                                                                                        \
+        else if (NW_ == 1)                                                                                     \
+            k_render_bwd1<TW_, TH_, false><<<tiles_total, 64, 0, s>>>(                                         \
+                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
+                flags);                                                                                        \
+        else if (au)                                                                                           \
             k_render_bwd<TW_, TH_, NW_, true><<<tiles_total, 64 * NW_, 0, s>>>(                                \
                 views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
                 flags);                                                                                        \
