@@ -929,6 +929,27 @@ __device__ __forceinline__ void cursor_next(PairCursor& c, int tws, int ths) {
 constexpr int PE_THREADS = 256;
 constexpr uint32_t PE_LDS = 2048;
 constexpr uint32_t PE_PRE = 64;
+// Records with more tile rows than this have their rows counted by the
+// whole wave (a wave would otherwise loop as long as its tallest record).
+constexpr uint32_t PE_ROWS_SELF = 4;
+
+__device__ __forceinline__ float readlane_f(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Position of the k-th (from 0) set bit of x (k < popcount(x)), by halving.
+__device__ __forceinline__ int nth_set_bit(uint32_t x, uint32_t k) {
+    int pos = 0;
+#pragma unroll
+    for (int h = 16; h > 0; h >>= 1) {
+        const uint32_t c = (uint32_t)__popc(x & ((1u << h) - 1u));
+        const bool up = k >= c;
+        k = up ? k - c : k;
+        x = up ? x >> h : x;
+        pos += up ? h : 0;
+    }
+    return pos;
+}
 
 __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
                                                              int words, SetDev st, int tws, int ths,
@@ -966,69 +987,103 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         if (shared_pre && threadIdx.x < ng) pre_gauss(g, lo + threadIdx.x, st, s_pre[threadIdx.x]);
         __syncthreads();
         const uint32_t pos = k0 + threadIdx.x;
-        if (pos >= k1) continue;
-        // owner Gaussian: the last one whose first record is at or before pos
-        const uint32_t i = lo + (staged ? last_le(s_off, ng, pos) : last_le(rec_off + lo, ng, pos));
-        // its (pos - rec_off[i])-th visible view
-        uint32_t kk = pos - rec_off[i];
-        int v = 0;
-        for (int w = 0; w < words; w++) {
-            uint32_t vis = mask[(int64_t)w * n + i];
-            const uint32_t c = (uint32_t)__popc(vis);
-            if (kk < c) {
-                for (; kk; kk--) vis &= vis - 1;
-                v = 32 * w + __ffs(vis) - 1;
-                break;
+        const bool valid = pos < k1;
+        // the record's support rows: a record with few tile rows counts its
+        // own; the wave counts the rows of the others together below
+        SupportRows S{};
+        uint32_t nt = 0, ty0 = 0, ny = 0;
+        if (valid) {
+            // owner Gaussian: the last one whose first record is at or before pos
+            const uint32_t i = lo + (staged ? last_le(s_off, ng, pos) : last_le(rec_off + lo, ng, pos));
+            // its (pos - rec_off[i])-th visible view
+            uint32_t kk = pos - rec_off[i];
+            int v = 0;
+            for (int w = 0; w < words; w++) {
+                const uint32_t vis = mask[(int64_t)w * n + i];
+                const uint32_t c = (uint32_t)__popc(vis);
+                if (kk < c) {
+                    v = 32 * w + nth_set_bit(vis, kk);
+                    break;
+                }
+                kk -= c;
             }
-            kk -= c;
+            GPre P;
+            if (shared_pre) P = s_pre[i - lo];
+            else pre_gauss(g, i, st, P);
+            const ViewDev& V = views[v];
+            GProj q;
+            project_exact(P, V, st, q);
+            float mxh = (float)q.mx, myh = (float)q.my;
+            const float4 g0 = make_float4(mxh, myh, (float)(q.mx - (double)mxh), (float)(q.my - (double)myh));
+            double det = q.cxx * q.cyy - q.cxy * q.cxy;
+            // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
+            double c00 = sqrt(q.cxx);
+            double c10 = q.cxy / c00;
+            double c11 = sqrt(det / q.cxx);
+            double sl = sqrt(0.5 * LOG2E);
+            const float4 g1 = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
+                                          (float)P.o);
+            rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
+            float depth = (float)q.t[2];
+            const int64_t gi = i;
+            if (write_attr) {
+                if (g.colors)
+                    rec.attr[pos] = make_float4(g.colors[gi], g.colors[g.n + gi], g.colors[2 * g.n + gi], depth);
+                else
+                    rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
+            }
+            uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
+            ty0 = (uint32_t)q.v0 >> ths;
+            const uint32_t ty1 = (uint32_t)q.v1 >> ths;
+            ny = ty1 - ty0 + 1;
+            const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
+                                        (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
+            sortkey[pos] = __float_as_uint(depth);
+            S = support_setup(g0, g1, pb, st.log2_amin);
+            if (ny <= PE_ROWS_SELF)
+                for (uint32_t ty = ty0; ty <= ty1; ty++) nt += support_row(S, ty, tws, ths).y;
+            EmitRec e;
+            e.g0 = g0;
+            e.g1 = g1;
+            e.pbox = pb;
+            e.rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+            e.ntiles = 0;  // written below
+            e.view = (uint32_t)v;
+            e.unc = __float_as_uint(g.uncert ? g.uncert[gi] : 0.0f);
+            e.gid = i;
+            rec.emit[pos] = e;
+            order[pos] = pos;
         }
-        GPre P;
-        if (shared_pre) P = s_pre[i - lo];
-        else pre_gauss(g, i, st, P);
-        const ViewDev& V = views[v];
-        GProj q;
-        project_exact(P, V, st, q);
-        float mxh = (float)q.mx, myh = (float)q.my;
-        const float4 g0 = make_float4(mxh, myh, (float)(q.mx - (double)mxh), (float)(q.my - (double)myh));
-        double det = q.cxx * q.cyy - q.cxy * q.cxy;
-        // Sigma_2D = C C^T (Cholesky); M = sqrt(log2e / 2) C^-1
-        double c00 = sqrt(q.cxx);
-        double c10 = q.cxy / c00;
-        double c11 = sqrt(det / q.cxx);
-        double sl = sqrt(0.5 * LOG2E);
-        const float4 g1 = make_float4((float)(sl / c00), (float)(-sl * c10 / (c00 * c11)), (float)(sl / c11),
-                                      (float)P.o);
-        rec.q64[pos] = make_double4(q.cyy / det, -q.cxy / det, q.cxx / det, 0.0);
-        float depth = (float)q.t[2];
-        const int64_t gi = i;
-        if (write_attr) {
-            if (g.colors)
-                rec.attr[pos] = make_float4(g.colors[gi], g.colors[g.n + gi], g.colors[2 * g.n + gi], depth);
-            else
-                rec.attr[pos] = make_float4(0.0f, 0.0f, 0.0f, depth);
+        // every lane takes one row of the record at a time; the per-row
+        // counts are integers, so their sum does not depend on the split
+        uint64_t big = __ballot(valid && ny > PE_ROWS_SELF);
+        while (big) {
+            const int src = __builtin_ctzll(big);
+            big &= big - 1;
+            SupportRows B;
+            B.mx = readlane_f(S.mx, src);
+            B.my = readlane_f(S.my, src);
+            B.dyr = readlane_f(S.dyr, src);
+            B.P = readlane_f(S.P, src);
+            B.Qc = readlane_f(S.Qc, src);
+            B.Bc = readlane_f(S.Bc, src);
+            B.pb_x = (uint32_t)__builtin_amdgcn_readlane((int)S.pb_x, src);
+            B.pb_y = (uint32_t)__builtin_amdgcn_readlane((int)S.pb_y, src);
+            B.all = __builtin_amdgcn_readlane(S.all, src);
+            const uint32_t bty0 = (uint32_t)__builtin_amdgcn_readlane((int)ty0, src);
+            const uint32_t bny = (uint32_t)__builtin_amdgcn_readlane((int)ny, src);
+            uint32_t part = 0;
+            for (uint32_t r = lane_id(); r < bny; r += 64) part += support_row(B, bty0 + r, tws, ths).y;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) part += (uint32_t)__shfl_xor((int)part, o, 64);
+            if ((int)lane_id() == src) nt = part;
         }
-        uint32_t tx0 = (uint32_t)q.u0 >> tws, tx1 = (uint32_t)q.u1 >> tws;
-        uint32_t ty0 = (uint32_t)q.v0 >> ths, ty1 = (uint32_t)q.v1 >> ths;
-        const uint2 pb = make_uint2((uint32_t)q.u0 | ((uint32_t)q.u1 << 16),
-                                    (uint32_t)q.v0 | ((uint32_t)q.v1 << 16));
-        sortkey[pos] = __float_as_uint(depth);
-        // pairs: the tiles the support meets (a subset of the box's
-        // tiles); at least one, so that every record owns a pair
-        uint32_t nt = 0;
-        const SupportRows S = support_setup(g0, g1, pb, st.log2_amin);
-        for (uint32_t ty = ty0; ty <= ty1; ty++) nt += support_row(S, ty, tws, ths).y;
-        rec.ntiles[pos] = max(nt, 1u);
-        EmitRec e;
-        e.g0 = g0;
-        e.g1 = g1;
-        e.pbox = pb;
-        e.rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-        e.ntiles = max(nt, 1u);
-        e.view = (uint32_t)v;
-        e.unc = __float_as_uint(g.uncert ? g.uncert[gi] : 0.0f);
-        e.gid = i;
-        rec.emit[pos] = e;
-        order[pos] = pos;
+        if (valid) {
+            // pairs: the tiles the support meets (a subset of the box's
+            // tiles); at least one, so that every record owns a pair
+            rec.ntiles[pos] = max(nt, 1u);
+            rec.emit[pos].ntiles = max(nt, 1u);
+        }
     }
 }
 
