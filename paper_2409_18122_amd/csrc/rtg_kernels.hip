@@ -3127,7 +3127,8 @@ void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, i
                    uint32_t* cnt, uint32_t* mask, hipStream_t s) {
     if (g.n == 0) return;
     int words = (n_views_cap + 31) / 32;
-    k_project_count<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
+    // one thread per Gaussian: the grid covers every n below 2^31
+    k_project_count<<<grid_for(g.n, 256, 0xffffffffu), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
 }
 
 // log2 of a power-of-two tile side (8, 16 or 32)
@@ -3327,7 +3328,7 @@ void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const 
                       float* d_log_scales, float* d_quats, float* d_opacity, float* d_colors, const uint32_t* flags,
                       hipStream_t s) {
     if (g.n == 0) return;
-    k_project_bwd<<<grid_for(g.n, 256), 256, 0, s>>>(g, views, st, rec_off, cnt, emit, g2d, d_means,
+    k_project_bwd<<<grid_for(g.n, 256, 0xffffffffu), 256, 0, s>>>(g, views, st, rec_off, cnt, emit, g2d, d_means,
                                                      d_log_scales, d_quats, d_opacity, d_colors, flags);
 }
 
