@@ -1449,6 +1449,10 @@ constexpr int BWD_STEP = 2;
 // in binary64 (far wider than the binary32 error of alpha).
 constexpr float REFINE = 2e-3f;
 
+// Whether binary32 alpha a lies in that band: |a - alpha_min| <= band, with
+// band = REFINE alpha_min (a subtraction and a compare of the magnitude).
+__device__ __forceinline__ bool near_amin(float a, float amin, float band) { return fabsf(a - amin) <= band; }
+
 // The alpha_min test: a splat with alpha < alpha_min at a pixel is skipped
 // there.  Where binary32 alpha lies in [alpha_min (1 - REFINE), alpha_min
 // (1 + REFINE)] the decision is re-taken in binary64 from the binary64 conic
@@ -1568,7 +1572,7 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
     const bool inside = u < W && v < H;
     const float lx = (float)(u - ox), ly = (float)(v - oy);
     const float amin = st.alpha_min, amax = st.alpha_max, tmin = st.T_min;
-    const float nlo = amin - REFINE * amin, nhi = amin + REFINE * amin;
+    const float band = REFINE * amin;
     const char* sp = reinterpret_cast<const char*>(s_p);
     const char* sq = reinterpret_cast<const char*>(s_q);
     const char* sa = reinterpret_cast<const char*>(s_at);
@@ -1608,12 +1612,12 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
                 float G, dx, dy, w1, w2;
                 as[q] = splat_alpha(pp.x, pp.y, make_float4(pp.z, pp.w, qq.x, qq.y), lx, ly, amax, G, dx, dy, w1,
                                     w2);
-                need = need | ((as[q] >= nlo) & (as[q] <= nhi));
+                need = need | near_amin(as[q], amin, band);
             }
             if (__ballot(need)) {
 #pragma unroll
                 for (int q = 0; q < FWD_STEP; q++)
-                    if ((as[q] >= nlo) & (as[q] <= nhi) & (ko[q] < B * sizeof(float4)))
+                    if (near_amin(as[q], amin, band) & (ko[q] < B * sizeof(float4)))
                         as[q] = redecide(as[q], rec, s_r[ko[q] / sizeof(float4)], u, v, st);
             }
 #pragma unroll
@@ -1832,10 +1836,12 @@ __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
 // (within 1 ulp) stands in for the correctly rounded division; T only scales
 // gradient terms here and decides nothing.
 // Per-lane sums acc (the record's gradient slots, in this order):
-//   0, 1: sum dpow dx, sum dpow dy, with dpow = dL/dpower, power = d^T Q d
-//         (G = exp(-power / 2)), d = pixel - mean; the mean's gradient
-//         -2 Q (sum dpow d) is formed from them in binary64 per record;
-//   2, 3, 4: sum dpow dx^2, sum dpow dx dy, sum dpow dy^2 (dL/dQ);
+//   0, 1: sum t dx, sum t dy, with t = dL/da G and d = pixel - mean; the
+//         splat's factor -o / 2 turns them into sum dpow dx, sum dpow dy
+//         (dpow = dL/dpower, power = d^T Q d, G = exp(-power / 2)) once per
+//         splat after the wave reduction; the mean's gradient -2 Q (sum dpow
+//         d) is formed from them in binary64 per record;
+//   2, 3, 4: sum t dx^2, sum t dx dy, sum t dy^2, likewise (dL/dQ);
 //   5: sum dL/da G (the opacity's gradient: a = o G below alpha_max);
 //   6..9: sum g_ch w (colour and depth).
 // G is 0 where alpha is clamped at alpha_max (no gradient flows through
@@ -1845,9 +1851,9 @@ __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
 // AU: the alpha and uncertainty images carry gradients too (colour 1 and u
 // in GA; otherwise their terms are left out altogether).
 template <bool AU, bool FIRST = false>
-__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 at, float ui, float nho,
-                                          float gr, float gg, float gb, float gd, float ga, float gu, float& T,
-                                          float& D, float* acc) {
+__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 at, float ui, float gr,
+                                          float gg, float gb, float gd, float ga, float gu, float& T, float& D,
+                                          float* acc) {
     const float inv = __builtin_amdgcn_rcpf(1.0f - a);
     const float Ti = T * inv;
     const float w = a * Ti;
@@ -1863,9 +1869,7 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
     D = fmaf(w, GA, D);
     T = Ti;
     const float t0 = da * G;
-    // nho = -o / 2: dpow = dL/da * o * dG/dpower
-    const float dpow = t0 * nho;
-    const float t1 = dpow * dx, t2 = dpow * dy;
+    const float t1 = t0 * dx, t2 = t0 * dy;
     if constexpr (FIRST) {
         acc[6] = gr * w;
         acc[7] = gg * w;
@@ -1980,7 +1984,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     const float amax = st.alpha_max;
-    const float nlo = st.alpha_min - REFINE * st.alpha_min, nhi = st.alpha_min + REFINE * st.alpha_min;
+    const float band = REFINE * st.alpha_min;
 
     for (int64_t bend = maxlast; bend > 0; bend -= B) {
         const int64_t bstart = bend - B > 0 ? bend - B : 0;
@@ -2042,13 +2046,13 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 for (int q = 0; q < BWD_STEP; q++) {
                     a[q] = splat_alpha(sg0[q].x, sg0[q].y, sg1[q], px0 + bx(j), py0 + by(j), amax, G[q], dx[q],
                                        dy[q], w1[q], w2[q]);
-                    need = need | ((spos[q] < last[j]) & (a[q] >= nlo) & (a[q] <= nhi));
+                    need = need | near_amin(a[q], st.alpha_min, band);
                 }
                 // the forward's binary64 re-decision, taken the same way
                 if (__ballot(need)) {
 #pragma unroll
                     for (int q = 0; q < BWD_STEP; q++)
-                        if ((spos[q] < last[j]) & (a[q] >= nlo) & (a[q] <= nhi))
+                        if ((spos[q] < last[j]) & near_amin(a[q], st.alpha_min, band))
                             a[q] = redecide(a[q], rec, sr[q], ux(j), vy(j), st);
                 }
                 // predicated, not branched: a splat the pixel does not take
@@ -2060,7 +2064,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                     any[q] = any[q] | ok;
                     const float a0 = ok ? a[q] : 0.0f;
                     const float G0 = (ok & (sg1[q].w * G[q] <= amax)) ? G[q] : 0.0f;
-                    bwd_pixel<AU>(a0, G0, dx[q], dy[q], sat[q], su[q], nho[q], gr[j], gg[j], gb[j], gd[j], ga[j],
+                    bwd_pixel<AU>(a0, G0, dx[q], dy[q], sat[q], su[q], gr[j], gg[j], gb[j], gd[j], ga[j],
                                   gu[j], T[j], D[j], acc[q]);
                 }
             }
@@ -2078,8 +2082,10 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 const float tot = wave_sum_halving20(&acc[0][0], lane, v);
                 if (lane < 32 && v >= 0) {
                     const int q = v >= 10 ? 1 : 0;
+                    const int slot = v - 10 * q;
+                    const double f = slot < 5 ? (double)(q ? nho[1] : nho[0]) : 1.0;
                     if (q ? t[1] : t[0])
-                        unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + (v - 10 * q), (double)tot);
+                        unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + slot, (double)tot * f);
                 }
             }
         }
@@ -2168,7 +2174,7 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
     for (int o = 32; o > 0; o >>= 1) mylast = max(mylast, (uint32_t)__shfl_xor((int)mylast, o, 64));
     const uint32_t maxlast = mylast;
     const float amax = st.alpha_max;
-    const float nlo = st.alpha_min - REFINE * st.alpha_min, nhi = st.alpha_min + REFINE * st.alpha_min;
+    const float band = REFINE * st.alpha_min;
 
     for (int64_t bend = maxlast; bend > 0; bend -= B) {
         const int64_t bstart = bend - B > 0 ? bend - B : 0;
@@ -2234,14 +2240,14 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
                     float w1, w2;
                     a[j][q] = splat_alpha(cp[q].x, cp[q].y, cg[q], px0 + bx(j), py0 + by(j), amax, G[j][q],
                                           dx[j][q], dy[j][q], w1, w2);
-                    need = need | ((spos[q] < last[j]) & (a[j][q] >= nlo) & (a[j][q] <= nhi));
+                    need = need | near_amin(a[j][q], st.alpha_min, band);
                 }
             if (__ballot(need)) {
 #pragma unroll
                 for (int j = 0; j < PPT; j++)
 #pragma unroll
                     for (int q = 0; q < 2; q++)
-                        if ((spos[q] < last[j]) & (a[j][q] >= nlo) & (a[j][q] <= nhi))
+                        if ((spos[q] < last[j]) & near_amin(a[j][q], st.alpha_min, band))
                             a[j][q] = redecide(a[j][q], rec, sr[q], ux(j), vy(j), st);
             }
 #pragma unroll
@@ -2253,10 +2259,10 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
                     const float a0 = ok ? a[j][q] : 0.0f;
                     const float G0 = (ok & (cg[q].w * G[j][q] <= amax)) ? G[j][q] : 0.0f;
                     if (j == 0)
-                        bwd_pixel<AU, true>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], nho[q], gr[j], gg[j], gb[j],
+                        bwd_pixel<AU, true>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], gr[j], gg[j], gb[j],
                                             gd[j], ga[j], gu[j], T[j], D[j], acc[q]);
                     else
-                        bwd_pixel<AU>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], nho[q], gr[j], gg[j], gb[j], gd[j],
+                        bwd_pixel<AU>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], gr[j], gg[j], gb[j], gd[j],
                                       ga[j], gu[j], T[j], D[j], acc[q]);
                 }
             }
@@ -2270,8 +2276,10 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
             const float tot = wave_sum_halving20(&acc[0][0], lane, v);
             if (lane < 32 && v >= 0) {
                 const int q = v >= 10 ? 1 : 0;
+                const int slot = v - 10 * q;
+                const double f = slot < 5 ? (double)(q ? nho[1] : nho[0]) : 1.0;
                 if (q ? t[1] : t[0])
-                    unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + (v - 10 * q), (double)tot);
+                    unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + slot, (double)tot * f);
             }
         }
     }
@@ -2479,7 +2487,7 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
     const bool inside = u < V.W && v < V.H;
     const float lx = (float)(u - ox), ly = (float)(v - oy);
     const float amin = st.alpha_min, amax = st.alpha_max, tmin = st.T_min;
-    const float nlo = amin - REFINE * amin, nhi = amin + REFINE * amin;
+    const float band = REFINE * amin;
     const uint2 rg = ranges[tile];
     const char* sp = reinterpret_cast<const char*>(s_p);
     const char* sq = reinterpret_cast<const char*>(s_q);
@@ -2517,12 +2525,12 @@ __device__ __forceinline__ void score_one_tile(const ViewDev* __restrict__ views
                 const float a = __builtin_amdgcn_fmed3f(fast_exp2(-ex), 0.0f, amax);
                 as[q] = a;
                 us[q] = g.z;
-                need = need | ((a >= nlo) & (a <= nhi));
+                need = need | near_amin(a, amin, band);
             }
             if (__ballot(need)) {
 #pragma unroll
                 for (int q = 0; q < SCORE_STEP; q++)
-                    if ((as[q] >= nlo) & (as[q] <= nhi) & (ko[q] < B * sizeof(float4)))
+                    if (near_amin(as[q], amin, band) & (ko[q] < B * sizeof(float4)))
                         as[q] = redecide(as[q], rec, s_r[ko[q] / sizeof(float4)], u, v, st);
             }
 #pragma unroll
@@ -3282,6 +3290,31 @@ static int backward_waves(int tw, int th, uint32_t tiles) {
     return nw;
 }
 
+// One wave per tile runs the compacted form; two or four the masked one.
+template <int TW, int TH, int NW>
+static void launch_bwd(bool au, uint32_t tiles_total, hipStream_t s, const ViewDev* views, int n_views,
+                       const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, const float* T_final,
+                       const uint32_t* n_last, const float* d_rgb, const float* d_depth, const float* d_alpha,
+                       const float* d_unc, double* g2d, const uint32_t* flags) {
+    if constexpr (NW == 1) {
+        if (au)
+            k_render_bwd1<TW, TH, true><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st, T_final,
+                                                                   n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
+        else
+            k_render_bwd1<TW, TH, false><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st, T_final,
+                                                                    n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
+    } else {
+        if (au)
+            k_render_bwd<TW, TH, NW, true><<<tiles_total, 64 * NW, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
+                                                                          T_final, n_last, d_rgb, d_depth, d_alpha,
+                                                                          d_unc, g2d, flags);
+        else
+            k_render_bwd<TW, TH, NW, false><<<tiles_total, 64 * NW, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
+                                                                           T_final, n_last, d_rgb, d_depth, d_alpha,
+                                                                           d_unc, g2d, flags);
+    }
+}
+
 void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views, uint32_t tiles_total,
                      const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, const float* T_final,
                      const uint32_t* n_last, const float* d_rgb, const float* d_depth, const float* d_alpha,
@@ -3290,37 +3323,30 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
     if (tiles_total == 0) return;
     const int nw = backward_waves(tw, th, tiles_total);
     const bool au = d_alpha != nullptr || d_unc != nullptr;
-#define RTG_BWD_LAUNCH(TW_, TH_, NW_)                                                                          \
-    do {                                                                                                       \
-        if (NW_ == 1 && au)                                                                                    \
-            k_render_bwd1<TW_, TH_, true><<<tiles_total, 64, 0, s>>>(                                          \
-                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
-                flags);                                                                                        \
-        else if (NW_ == 1)                                                                                     \
-            k_render_bwd1<TW_, TH_, false><<<tiles_total, 64, 0, s>>>(                                         \
-                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
-                flags);                                                                                        \
-        else if (au)                                                                                           \
-            k_render_bwd<TW_, TH_, NW_, true><<<tiles_total, 64 * NW_, 0, s>>>(                                \
-                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
-                flags);                                                                                        \
-        else                                                                                                   \
-            k_render_bwd<TW_, TH_, NW_, false><<<tiles_total, 64 * NW_, 0, s>>>(                               \
-                views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, \
-                flags);                                                                                        \
-    } while (0)
     if (tw == 8 && th == 8) {
-        RTG_BWD_LAUNCH(8, 8, 1);
+        launch_bwd<8, 8, 1>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb,
+                            d_depth, d_alpha, d_unc, g2d, flags);
     } else if (tw == 32 && th == 8) {
-        if (nw == 4) RTG_BWD_LAUNCH(32, 8, 4);
-        else if (nw == 2) RTG_BWD_LAUNCH(32, 8, 2);
-        else RTG_BWD_LAUNCH(32, 8, 1);
+        if (nw == 4)
+            launch_bwd<32, 8, 4>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+                                 d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
+        else if (nw == 2)
+            launch_bwd<32, 8, 2>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+                                 d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
+        else
+            launch_bwd<32, 8, 1>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+                                 d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
     } else {
-        if (nw == 4) RTG_BWD_LAUNCH(16, 16, 4);
-        else if (nw == 2) RTG_BWD_LAUNCH(16, 16, 2);
-        else RTG_BWD_LAUNCH(16, 16, 1);
+        if (nw == 4)
+            launch_bwd<16, 16, 4>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+                                  d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
+        else if (nw == 2)
+            launch_bwd<16, 16, 2>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+                                  d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
+        else
+            launch_bwd<16, 16, 1>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+                                  d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
     }
-#undef RTG_BWD_LAUNCH
 }
 
 void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const uint32_t* rec_off,
