@@ -365,7 +365,7 @@ struct rtg_frame {
 
     Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist;
     Buf emit, q64, attr, ntiles, skey, skey2, order, order2;
-    Buf inst_off, tkey, tkey2, irec, irec2, ranges;
+    Buf inst_off, tkey, tkey2, irec, irec2, ranges, tile_ord, tile_ord_ws;
     Buf T_final, n_last, g2d, loss_part, score_part, ssim_maps;
 
     Records records() const {
@@ -446,6 +446,8 @@ rtg_status alloc_instances(rtg_frame* f, uint32_t kc, uint32_t tiles_cap) {
     RTG_TRY(f->irec.ensure(ctx, 4 * k));
     RTG_TRY(f->irec2.ensure(ctx, 4 * k));
     RTG_TRY(f->ranges.ensure(ctx, 8 * (size_t)std::max<uint32_t>(tiles_cap, 1)));
+    RTG_TRY(f->tile_ord.ensure(ctx, 4 * (size_t)std::max<uint32_t>(tiles_cap, 1)));
+    RTG_TRY(f->tile_ord_ws.ensure(ctx, 4 * (size_t)TILE_ORDER_WS));
     uint64_t big = std::max<uint64_t>(std::max<uint64_t>(kc, f->rec_cap), 1);
     RTG_TRY(f->sort_hist.ensure(ctx, sizeof(uint32_t) * sort_hist_words(big)));
     f->inst_cap = kc;
@@ -527,6 +529,8 @@ rtg_status enqueue_bin(rtg_frame* f, bool eager, hipStream_t s) {
     f->inst_in_alt = radix_sort(f->tkey.as<uint32_t>(), f->irec.as<uint32_t>(), f->tkey2.as<uint32_t>(),
                                 f->irec2.as<uint32_t>(), f->ctr(C_INST), kc, tbits, TILE_SORT_DIGIT, ws, s);
     tile_ranges(f->sorted_tkey(), f->ctr(C_INST), kc, f->ranges.as<uint2>(), f->tiles_cap, f->ctr(C_FLAGS), s);
+    tile_order(f->ranges.as<uint2>(), f->hdr.as<Header>(), f->tiles_cap, f->tile_ord_ws.as<uint32_t>(),
+               f->tile_ord.as<uint32_t>(), s);
     return check_launch("tile binning");
 }
 
@@ -735,7 +739,7 @@ rtg_status rtg_render(rtg_ctx* ctx, rtg_frame* f, float* rgb, float* depth, floa
                 f->n_contrib.as<uint32_t>()};
     Timer tm(ctx, 3, s);
     render_forward(f->st.tile_w, f->st.tile_h, f->st.batch, f->views.as<ViewDev>(), f->n_views,
-                   f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st), o,
+                   f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(), to_dev(f->st), o,
                    f->ctr(C_FLAGS), s);
     RTG_TRY(check_launch("render"));
     f->rendered = true;
@@ -797,7 +801,7 @@ rtg_status rtg_render_backward(rtg_ctx* ctx, rtg_frame* f, const float* d_rgb, c
     {
     Timer tm(ctx, 5, s);
     render_backward(f->st.tile_w, f->st.tile_h, f->st.batch, f->views.as<ViewDev>(), f->n_views,
-                    f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
+                    f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(), to_dev(f->st),
                     f->T_final.as<float>(), f->n_last.as<uint32_t>(), d_rgb, d_depth, d_alpha, d_unc,
                     f->g2d.as<double>(), f->ctr(C_FLAGS), s);
     }
@@ -914,7 +918,7 @@ rtg_status score_batched(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera*
     int grid = score_persistent_blocks(f->st.tile_w, f->st.tile_h, f->st.batch);
     Timer tm(ctx, 7, s);
     score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, mode, true, grid, f->views.as<ViewDev>(), f->n_views,
-                f->hdr.as<Header>(), 0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(),
+                f->hdr.as<Header>(), 0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(),
                 to_dev(f->st), f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
     score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), n_views, f->score_part.as<double>(), scores,
                  f->ctr(C_FLAGS), s);
@@ -934,7 +938,7 @@ rtg_status score_plain(rtg_ctx* ctx, const rtg_gaussians* g, const rtg_camera* c
         Timer tm(ctx, 7, s);
         score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, mode, false, 0, f->views.as<ViewDev>(), 1,
                     f->hdr.as<Header>(),
-                    0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
+                    0, f->L.hdr.tiles_total, f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(), to_dev(f->st),
                     f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
         score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), 1, f->score_part.as<double>(), scores + v,
                      f->ctr(C_FLAGS), s);
@@ -1047,7 +1051,7 @@ rtg_status enqueue_graph_body(rtg_graph* gr, hipStream_t s) {
     RTG_TRY(enqueue_bin(f, false, s));
     score_tiles(f->st.tile_w, f->st.tile_h, f->st.batch, gr->mode, true, gr->grid, f->views.as<ViewDev>(),
                 gr->max_views,
-                f->hdr.as<Header>(), 0, 0, f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(f->st),
+                f->hdr.as<Header>(), 0, 0, f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(), to_dev(f->st),
                 f->score_part.as<double>(), f->ctr(C_QUEUE), f->ctr(C_FLAGS), s);
     score_reduce(f->views.as<ViewDev>(), f->hdr.as<Header>(), gr->max_views, f->score_part.as<double>(),
                  gr->scores.as<double>(), f->ctr(C_FLAGS), s);
@@ -1304,7 +1308,7 @@ static rtg_status map_graph_build(rtg_ctx* ctx, const rtg_gaussians* g, const rt
         RenderOut o{rgb, depth, nullptr, nullptr, f->T_final.as<float>(), f->n_last.as<uint32_t>(),
                     f->n_contrib.as<uint32_t>()};
         render_forward(st.tile_w, st.tile_h, st.batch, f->views.as<ViewDev>(), n_views, f->L.hdr.tiles_total,
-                       f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(st), o, f->ctr(C_FLAGS), cs);
+                       f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(), to_dev(st), o, f->ctr(C_FLAGS), cs);
         if (eq4)
             loss_ssim(f->views.as<ViewDev>(), n_views, bpv, P, rgb, depth, target_rgb, target_depth, w_depth,
                       lambda_1, lambda_2, f->ssim_maps.as<float>(), f->loss_part.as<double>(), d_rgb, d_dep, loss,
@@ -1314,7 +1318,7 @@ static rtg_status map_graph_build(rtg_ctx* ctx, const rtg_gaussians* g, const rt
                     d_rgb, d_dep, f->loss_part.as<double>(), bx * n_views, loss, cs);
         fill_u32(f->g2d.as<uint32_t>(), 0u, (uint64_t)2 * G2D_STRIDE * rec_cap, cs);
         render_backward(st.tile_w, st.tile_h, st.batch, f->views.as<ViewDev>(), n_views, f->L.hdr.tiles_total,
-                        f->ranges.as<uint2>(), f->sorted_irec(), f->records(), to_dev(st), f->T_final.as<float>(),
+                        f->ranges.as<uint2>(), f->tile_ord.as<uint32_t>(), f->sorted_irec(), f->records(), to_dev(st), f->T_final.as<float>(),
                         f->n_last.as<uint32_t>(), d_rgb, d_dep, nullptr, nullptr, f->g2d.as<double>(), f->ctr(C_FLAGS),
                         cs);
         project_backward(to_dev(f->g), f->views.as<ViewDev>(), to_dev(st), f->rec_off.as<uint32_t>(),

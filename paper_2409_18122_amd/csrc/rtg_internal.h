@@ -148,6 +148,12 @@ void emit_instances(const uint32_t* order, const uint32_t* R_dev, uint32_t rec_c
 // emit_instances has emptied them all.
 void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_cap,
                  uint2* ranges, uint32_t tiles_cap, const uint32_t* flags, hipStream_t s);
+// order[0 .. tiles_total) = the tiles in descending order of their pair
+// counts (by powers of two; any order within one); ws: TILE_ORDER_WS words
+// of scratch.  The compositing kernels take their tiles through it.
+constexpr int TILE_ORDER_WS = 66;
+void tile_order(const uint2* ranges, const Header* hdr, uint32_t tiles_cap, uint32_t* ws, uint32_t* order,
+                hipStream_t s);
 
 struct RenderOut {
     float *rgb, *depth, *alpha, *unc;
@@ -159,15 +165,16 @@ struct RenderOut {
 // out[0] += sum a[i], out[1] += sum b[i] over i < n (64-bit).
 void sum_u32_pair(const uint32_t* a, const uint32_t* b, uint64_t n, unsigned long long* out, hipStream_t s);
 void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
-                    uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec,
-                    Records rec, SetDev st, RenderOut out, const uint32_t* flags, hipStream_t s);
+                    uint32_t tiles_total, const uint2* ranges, const uint32_t* tile_order,
+                    const uint32_t* inst_rec, Records rec, SetDev st, RenderOut out, const uint32_t* flags,
+                    hipStream_t s);
 
 void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, const float* depth,
              const float* trgb, const float* tdepth, float w_depth, float* d_rgb, float* d_depth,
              double* partial, int partial_cap, double* loss, hipStream_t s);
 
 void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views,
-                     uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec,
+                     uint32_t tiles_total, const uint2* ranges, const uint32_t* tile_order, const uint32_t* inst_rec,
                      Records rec, SetDev st, const float* T_final, const uint32_t* n_last,
                      const float* d_rgb, const float* d_depth, const float* d_alpha,
                      const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s);
@@ -184,7 +191,7 @@ void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const 
 // tile_begin + n_tiles).
 void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_persistent,
                  const ViewDev* views, int n_views, const Header* hdr,
-                 uint32_t tile_begin, uint32_t n_tiles, const uint2* ranges,
+                 uint32_t tile_begin, uint32_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
                  const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
                  uint32_t* queue, const uint32_t* flags, hipStream_t s);
 int score_persistent_blocks(int tw, int th, int batch);

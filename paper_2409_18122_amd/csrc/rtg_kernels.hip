@@ -1334,6 +1334,69 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
     if (i < K) range_edges(i, key[i], i > 0 ? key[i - 1] : 0u, i + 1 < K ? key[i + 1] : 0u, K, ranges, tiles_cap);
 }
 
+// ---------------------------------------------------------- tile order
+// The compositing kernels take the tiles in descending order of their pair
+// counts, bucketed by powers of two, so that long tiles start first and no
+// long tile is left for the end of a launch.  A counting sort over 33
+// buckets: bucket 0 holds the tiles with 2^31 or more pairs, bucket 31 those
+// with one, bucket 32 the empty ones; within a bucket the order is
+// arbitrary, since every tile's result is independent of when it runs.
+constexpr int TO_BUCKETS = 33;
+static_assert(TILE_ORDER_WS == 2 * TO_BUCKETS, "the scratch holds the bucket sizes and the cursors");
+
+__device__ __forceinline__ int tile_bucket(uint2 rg) {
+    const uint32_t c = rg.y - rg.x;
+    return c ? __clz((int)c) : 32;
+}
+
+__global__ __launch_bounds__(256) void k_tile_order_count(const uint2* __restrict__ ranges,
+                                                          const Header* __restrict__ hdr, uint32_t tiles_cap,
+                                                          uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[TO_BUCKETS];
+    for (int i = threadIdx.x; i < TO_BUCKETS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const uint32_t n = min(hdr->tiles_total, tiles_cap);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+        atomicAdd(&h[tile_bucket(ranges[t])], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < TO_BUCKETS; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// hist: the bucket sizes; cursor: per bucket, the places already taken
+// (zero before the launch).
+__global__ __launch_bounds__(256) void k_tile_order_place(const uint2* __restrict__ ranges,
+                                                          const Header* __restrict__ hdr, uint32_t tiles_cap,
+                                                          const uint32_t* __restrict__ hist,
+                                                          uint32_t* __restrict__ cursor,
+                                                          uint32_t* __restrict__ order) {
+    __shared__ uint32_t start[TO_BUCKETS], h[TO_BUCKETS], base[TO_BUCKETS];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < TO_BUCKETS; i++) {
+            start[i] = run;
+            run += hist[i];
+        }
+    }
+    const uint32_t n = min(hdr->tiles_total, tiles_cap);
+    for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < n; t0 += gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < TO_BUCKETS; i += blockDim.x) h[i] = 0;
+        __syncthreads();
+        const uint32_t t = t0 + threadIdx.x;
+        int b = 0;
+        uint32_t rank = 0;
+        if (t < n) {
+            b = tile_bucket(ranges[t]);
+            rank = atomicAdd(&h[b], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < TO_BUCKETS && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+        if (t < n) order[start[b] + base[b] + rank] = t;
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ compositing
 // Sec. III: C(p) = sum_i c_i a_i T_i with T_i = prod_{j<i} (1 - a_j); the
 // depth image replaces c_i by d_i; the uncertainty image by u_i (Sec. IV-A).
@@ -1543,6 +1606,7 @@ __device__ __forceinline__ float redecide(float a, const Records& rec, uint32_t 
 template <int TW, int TH, int B, bool UNC>
 __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ tile_order,
                                                         const uint32_t* __restrict__ inst_rec,
                                                         Records rec, SetDev st, RenderOut out,
                                                         const uint32_t* __restrict__ flags) {
@@ -1557,7 +1621,7 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
     __shared__ __align__(8) uint32_t s_list[NT / 64 * (B + 2)];
     stage_null_splat<B>(s_p, s_q);
     if (threadIdx.x == 0) s_at[B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
     const int W = V.W, H = V.H;
@@ -1904,6 +1968,7 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
 template <int TW, int TH, int NW, bool AU>
 __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ tile_order,
                                                         const uint32_t* __restrict__ inst_rec, Records rec,
                                                         SetDev st, const float* __restrict__ T_final,
                                                         const uint32_t* __restrict__ n_last,
@@ -1922,7 +1987,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
     __shared__ uint32_t s_r[B];
     __shared__ uint2 s_pb[B];
     __shared__ uint32_t s_max;
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
     const int W = V.W, H = V.H;
@@ -2104,6 +2169,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 template <int TW, int TH, bool AU>
 __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* __restrict__ views, int n_views,
                                                         const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ tile_order,
                                                         const uint32_t* __restrict__ inst_rec, Records rec,
                                                         SetDev st, const float* __restrict__ T_final,
                                                         const uint32_t* __restrict__ n_last,
@@ -2119,7 +2185,7 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
     // s_p = (mean x, mean y relative to the origin, record id bits, position bits)
     __shared__ float4 s_p[B + 1], s_g1[B + 1], s_at[B + 1];
     __shared__ float s_u[B + 1];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
     const uint32_t vi = view_of_tile(views, n_views, tile);
     const ViewDev& V = views[vi];
     const int W = V.W, H = V.H;
@@ -2581,6 +2647,7 @@ template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) void k_score_persistent(const ViewDev* __restrict__ views,
                                                               const Header* __restrict__ hdr,
                                                               const uint2* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ tile_order,
                                                               const uint32_t* __restrict__ inst_rec, Records rec,
                                                               SetDev st, int mode, double* __restrict__ partial,
                                                               uint32_t* __restrict__ queue,
@@ -2603,11 +2670,12 @@ __global__ __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(6))) vo
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= total) break;
+        const uint32_t tile = tile_order ? tile_order[item] : item;
         if (mode)
-            score_one_tile<TW, TH, B, 1>(views, nv, item, ranges, inst_rec, rec, st, partial, s_p, s_q, s_r, s_pb,
+            score_one_tile<TW, TH, B, 1>(views, nv, tile, ranges, inst_rec, rec, st, partial, s_p, s_q, s_r, s_pb,
                                          ws, s_list);
         else
-            score_one_tile<TW, TH, B, 0>(views, nv, item, ranges, inst_rec, rec, st, partial, s_p, s_q, s_r, s_pb,
+            score_one_tile<TW, TH, B, 0>(views, nv, tile, ranges, inst_rec, rec, st, partial, s_p, s_q, s_r, s_pb,
                                          ws, s_list);
     }
 }
@@ -3248,16 +3316,25 @@ void tile_ranges(const uint32_t* tile_key, const uint32_t* K_dev, uint32_t inst_
                                                                            tiles_cap, flags);
 }
 
+void tile_order(const uint2* ranges, const Header* hdr, uint32_t tiles_cap, uint32_t* ws, uint32_t* order,
+                hipStream_t s) {
+    if (tiles_cap == 0) return;
+    fill_u32(ws, 0u, 2 * TO_BUCKETS, s);
+    const unsigned grid = grid_for(tiles_cap, 256, 1024);
+    k_tile_order_count<<<grid, 256, 0, s>>>(ranges, hdr, tiles_cap, ws);
+    k_tile_order_place<<<grid, 256, 0, s>>>(ranges, hdr, tiles_cap, ws, ws + TO_BUCKETS, order);
+}
+
 void render_forward(int tw, int th, int batch, const ViewDev* views, int n_views,
-                    uint32_t tiles_total, const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st,
-                    RenderOut out, const uint32_t* flags, hipStream_t s) {
+                    uint32_t tiles_total, const uint2* ranges, const uint32_t* tile_order, const uint32_t* inst_rec,
+                    Records rec, SetDev st, RenderOut out, const uint32_t* flags, hipStream_t s) {
     if (tiles_total == 0) return;
     if (out.unc) {
         RTG_BATCH_DISPATCH(TW, TH, B, (k_render_fwd<TW, TH, B, true><<<tiles_total, TW * TH, 0, s>>>(
-                                          views, n_views, ranges, inst_rec, rec, st, out, flags)));
+                                          views, n_views, ranges, tile_order, inst_rec, rec, st, out, flags)));
     } else {
         RTG_BATCH_DISPATCH(TW, TH, B, (k_render_fwd<TW, TH, B, false><<<tiles_total, TW * TH, 0, s>>>(
-                                          views, n_views, ranges, inst_rec, rec, st, out, flags)));
+                                          views, n_views, ranges, tile_order, inst_rec, rec, st, out, flags)));
     }
 }
 
@@ -3293,30 +3370,32 @@ static int backward_waves(int tw, int th, uint32_t tiles) {
 // One wave per tile runs the compacted form; two or four the masked one.
 template <int TW, int TH, int NW>
 static void launch_bwd(bool au, uint32_t tiles_total, hipStream_t s, const ViewDev* views, int n_views,
-                       const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, const float* T_final,
+                       const uint2* ranges, const uint32_t* tile_order, const uint32_t* inst_rec, Records rec,
+                       SetDev st, const float* T_final,
                        const uint32_t* n_last, const float* d_rgb, const float* d_depth, const float* d_alpha,
                        const float* d_unc, double* g2d, const uint32_t* flags) {
     if constexpr (NW == 1) {
         if (au)
-            k_render_bwd1<TW, TH, true><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st, T_final,
+            k_render_bwd1<TW, TH, true><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, tile_order, inst_rec, rec, st, T_final,
                                                                    n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
         else
-            k_render_bwd1<TW, TH, false><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, inst_rec, rec, st, T_final,
+            k_render_bwd1<TW, TH, false><<<tiles_total, 64, 0, s>>>(views, n_views, ranges, tile_order, inst_rec, rec, st, T_final,
                                                                     n_last, d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
     } else {
         if (au)
-            k_render_bwd<TW, TH, NW, true><<<tiles_total, 64 * NW, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
+            k_render_bwd<TW, TH, NW, true><<<tiles_total, 64 * NW, 0, s>>>(views, n_views, ranges, tile_order, inst_rec, rec, st,
                                                                           T_final, n_last, d_rgb, d_depth, d_alpha,
                                                                           d_unc, g2d, flags);
         else
-            k_render_bwd<TW, TH, NW, false><<<tiles_total, 64 * NW, 0, s>>>(views, n_views, ranges, inst_rec, rec, st,
+            k_render_bwd<TW, TH, NW, false><<<tiles_total, 64 * NW, 0, s>>>(views, n_views, ranges, tile_order, inst_rec, rec, st,
                                                                            T_final, n_last, d_rgb, d_depth, d_alpha,
                                                                            d_unc, g2d, flags);
     }
 }
 
 void render_backward(int tw, int th, int batch, const ViewDev* views, int n_views, uint32_t tiles_total,
-                     const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, const float* T_final,
+                     const uint2* ranges, const uint32_t* tile_order, const uint32_t* inst_rec, Records rec,
+                     SetDev st, const float* T_final,
                      const uint32_t* n_last, const float* d_rgb, const float* d_depth, const float* d_alpha,
                      const float* d_unc, double* g2d, const uint32_t* flags, hipStream_t s) {
     (void)batch;  // the backward stages 64 splats per wave of the tile
@@ -3324,27 +3403,27 @@ void render_backward(int tw, int th, int batch, const ViewDev* views, int n_view
     const int nw = backward_waves(tw, th, tiles_total);
     const bool au = d_alpha != nullptr || d_unc != nullptr;
     if (tw == 8 && th == 8) {
-        launch_bwd<8, 8, 1>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last, d_rgb,
+        launch_bwd<8, 8, 1>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last, d_rgb,
                             d_depth, d_alpha, d_unc, g2d, flags);
     } else if (tw == 32 && th == 8) {
         if (nw == 4)
-            launch_bwd<32, 8, 4>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+            launch_bwd<32, 8, 4>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last,
                                  d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
         else if (nw == 2)
-            launch_bwd<32, 8, 2>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+            launch_bwd<32, 8, 2>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last,
                                  d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
         else
-            launch_bwd<32, 8, 1>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+            launch_bwd<32, 8, 1>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last,
                                  d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
     } else {
         if (nw == 4)
-            launch_bwd<16, 16, 4>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+            launch_bwd<16, 16, 4>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last,
                                   d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
         else if (nw == 2)
-            launch_bwd<16, 16, 2>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+            launch_bwd<16, 16, 2>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last,
                                   d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
         else
-            launch_bwd<16, 16, 1>(au, tiles_total, s, views, n_views, ranges, inst_rec, rec, st, T_final, n_last,
+            launch_bwd<16, 16, 1>(au, tiles_total, s, views, n_views, ranges, tile_order, inst_rec, rec, st, T_final, n_last,
                                   d_rgb, d_depth, d_alpha, d_unc, g2d, flags);
     }
 }
@@ -3360,13 +3439,14 @@ void project_backward(const GaussDev& g, const ViewDev* views, SetDev st, const 
 
 void score_tiles(int tw, int th, int batch, int mode, bool persistent, int grid_persistent, const ViewDev* views,
                  int n_views, const Header* hdr, uint32_t tile_begin, uint32_t n_tiles,
-                 const uint2* ranges, const uint32_t* inst_rec, Records rec, SetDev st, double* partial,
-                 uint32_t* queue, const uint32_t* flags, hipStream_t s) {
+                 const uint2* ranges, const uint32_t* tile_order, const uint32_t* inst_rec, Records rec, SetDev st,
+                 double* partial, uint32_t* queue, const uint32_t* flags, hipStream_t s) {
     if (persistent) {
         fill_u32(queue, 0u, 1, s);
         RTG_BATCH_DISPATCH(TW, TH, B,
                            (k_score_persistent<TW, TH, B><<<grid_persistent, TW * TH, 0, s>>>(views, hdr, ranges,
-                                                                                             inst_rec, rec, st,
+                                                                                             tile_order, inst_rec,
+                                                                                             rec, st,
                                                                                              mode, partial, queue,
                                                                                              flags)));
     } else {
