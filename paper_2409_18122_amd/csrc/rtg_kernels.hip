@@ -571,10 +571,15 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
                                                            int shift, int bits, uint32_t* __restrict__ hist,
                                                            int block_major) {
     constexpr int NB = 1 << DB;
-    __shared__ uint32_t h[RS_WAVES][NB];
+    // each wave counts into CP copies of its table (lane l into copy l % CP),
+    // so that a skewed digit (few tiles or views dominating a pass) does not
+    // serialise a whole wave's atomics on one LDS word
+    constexpr int CP = DB <= 8 ? 4 : 1;
+    __shared__ uint32_t h[RS_WAVES * CP][NB];
     const int tid = threadIdx.x, wv = tid >> 6;
+    const int cp = wv * CP + (int)(lane_id() % CP);
     const uint32_t mask = (1u << bits) - 1u;
-    for (int i = tid; i < RS_WAVES * NB; i += RS_THREADS) (&h[0][0])[i] = 0;
+    for (int i = tid; i < RS_WAVES * CP * NB; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
@@ -592,14 +597,14 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
 #pragma unroll
         for (int j = 0; j < RS_IPT; j++) {
             const uint32_t idx = seg + j * 64 + lane_id();
-            if (idx < end) atomicAdd(&h[wv][(k[j] >> shift) & mask], 1u);
+            if (idx < end) atomicAdd(&h[cp][(k[j] >> shift) & mask], 1u);
         }
     }
     __syncthreads();
     for (int d = tid; d < NB; d += RS_THREADS) {
         uint32_t c = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; w++) c += h[w][d];
+        for (int w = 0; w < RS_WAVES * CP; w++) c += h[w][d];
         if (block_major)
             hist[(uint64_t)blockIdx.x * NB + d] = c;
         else
