@@ -1696,15 +1696,18 @@ __global__ __launch_bounds__(TW * TH, 6) void k_render_fwd(const ViewDev* __rest
                 const float Tn = fmaf(-a0, T, T);
                 const bool live = Tn >= tmin;
                 const bool use = ok & live;
-                const float w = a0 * T;
+                // weight 0 where the splat is skipped (a0 = 0) or the pixel
+                // stops: fmaf(x, 0, c) = c for the finite staged attributes,
+                // so the sums need no per-channel select
+                const float w = live ? a0 * T : 0.0f;
                 const float4 at = *reinterpret_cast<const float4*>(sa + ko[q]);
-                c0 = use ? fmaf(at.x, w, c0) : c0;
-                c1 = use ? fmaf(at.y, w, c1) : c1;
-                c2 = use ? fmaf(at.z, w, c2) : c2;
-                dd = use ? fmaf(at.w, w, dd) : dd;
+                c0 = fmaf(at.x, w, c0);
+                c1 = fmaf(at.y, w, c1);
+                c2 = fmaf(at.z, w, c2);
+                dd = fmaf(at.w, w, dd);
                 if (UNC) {
                     const float uk = *reinterpret_cast<const float*>(sq + ko[q] + 8);
-                    uu = use ? fmaf(uk, w, uu) : uu;
+                    uu = fmaf(uk, w, uu);
                 }
                 lastoff = use ? ko[q] : lastoff;
                 ncontrib += use ? 1u : 0u;
