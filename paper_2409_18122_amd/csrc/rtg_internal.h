@@ -76,8 +76,11 @@ struct Records {
 };
 
 // Screen-space gradient per record, binary64, 16 entries (one 128-byte line):
-// [0,1] d mean_2D, [2..4] d conic (xx, xy counted as one parameter, yy),
-// [5] d opacity, [6..8] d colour, [9] d depth, rest unused.  Per-tile partial
+// [0,1] sums toward d mean_2D, [2..4] toward d conic (xx, xy counted as one
+// parameter, yy), [5] toward d opacity, [6..8] d colour, [9] d depth, rest
+// unused.  Slots 0..5 hold pixel sums of dL/da times the unclamped alpha
+// o G (times the pixel offsets for 0..4); the projection backward scales
+// 0..4 by -1/2 and divides 5 by the opacity.  Per-tile partial
 // sums are added in binary64 because a splat's mean / conic gradient is a sum
 // of terms of both signs over its footprint that cancel to a small total.
 constexpr int G2D_STRIDE = 16;

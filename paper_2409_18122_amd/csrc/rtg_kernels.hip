@@ -1430,6 +1430,10 @@ __device__ __forceinline__ float4 rel_mean(float4 g0, int ox, int oy) {
 
 // alpha of one splat at the pixel (lx, ly) of the block whose origin the
 // staged mean (mx, my) is relative to: G = exp2(-|M d|^2), d = p - mean.
+// CLAMP = false leaves out the clamp at alpha_max, for splats whose opacity
+// is at most alpha_max: G <= 1, so their rounded o G never exceeds it and
+// the result is the same.
+template <bool CLAMP = true>
 __device__ __forceinline__ float splat_alpha(float mx, float my, float4 g1, float lx, float ly, float amax, float& G,
                                              float& dx, float& dy, float& w1, float& w2) {
     dx = lx - mx;
@@ -1438,8 +1442,13 @@ __device__ __forceinline__ float splat_alpha(float mx, float my, float4 g1, floa
     w2 = fmaf(g1.y, dx, g1.z * dy);
     float pw = fmaf(w1, w1, w2 * w2);
     G = fast_exp2(-pw);
-    return fminf(amax, g1.w * G);
+    return CLAMP ? fminf(amax, g1.w * G) : g1.w * G;
 }
+
+template <bool V>
+struct BoolC {
+    static constexpr bool value = V;
+};
 
 // Splat box meets the pixel rectangle [c0, c1] x [r0, r1].
 __device__ __forceinline__ bool box_meets(uint2 b, int c0, int c1, int r0, int r1) {
@@ -1907,23 +1916,23 @@ __device__ __forceinline__ int pop_high(uint64_t (&m)[NW]) {
 // 1 - a_i is a normal number well away from zero and the hardware reciprocal
 // (within 1 ulp) stands in for the correctly rounded division; T only scales
 // gradient terms here and decides nothing.
-// Per-lane sums acc (the record's gradient slots, in this order):
-//   0, 1: sum t dx, sum t dy, with t = dL/da G and d = pixel - mean; the
-//         splat's factor -o / 2 turns them into sum dpow dx, sum dpow dy
-//         (dpow = dL/dpower, power = d^T Q d, G = exp(-power / 2)) once per
-//         splat after the wave reduction; the mean's gradient -2 Q (sum dpow
-//         d) is formed from them in binary64 per record;
+// Per-lane sums acc (the record's gradient slots, in this order), with
+// t = dL/da a_g, where a_g = o G is the splat's alpha where it is not clamped
+// at alpha_max (then da/dpower = -a_g / 2 and da/do = a_g / o) and 0 where it
+// is (no gradient flows through the clamp):
+//   0, 1: sum t dx, sum t dy, with d = pixel - mean; the projection backward
+//         scales them by -1/2 into sum dpow dx, sum dpow dy (dpow = dL/dpower,
+//         power = d^T Q d, G = exp(-power / 2)) and forms the mean's gradient
+//         -2 Q (sum dpow d) per record in binary64;
 //   2, 3, 4: sum t dx^2, sum t dx dy, sum t dy^2, likewise (dL/dQ);
-//   5: sum dL/da G (the opacity's gradient: a = o G below alpha_max);
+//   5: sum t, which the projection backward divides by o (dL/do);
 //   6..9: sum g_ch w (colour and depth).
-// G is 0 where alpha is clamped at alpha_max (no gradient flows through
-// the clamp).  A splat with a = 0 and G = 0 leaves T (1 / (1 - 0) = 1
-// exactly), D and every sum unchanged, for finite pixel gradients and
-// colours.
+// A splat with a = 0 and a_g = 0 leaves T (1 / (1 - 0) = 1 exactly), D and
+// every sum unchanged, for finite pixel gradients and colours.
 // AU: the alpha and uncertainty images carry gradients too (colour 1 and u
 // in GA; otherwise their terms are left out altogether).
 template <bool AU, bool FIRST = false>
-__device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, float4 at, float ui, float gr,
+__device__ __forceinline__ void bwd_pixel(float a, float ag, float dx, float dy, float4 at, float ui, float gr,
                                           float gg, float gb, float gd, float ga, float gu, float& T, float& D,
                                           float* acc) {
     const float inv = __builtin_amdgcn_rcpf(1.0f - a);
@@ -1940,7 +1949,7 @@ __device__ __forceinline__ void bwd_pixel(float a, float G, float dx, float dy, 
     const float da = fmaf(Ti, GA, -(D * inv));
     D = fmaf(w, GA, D);
     T = Ti;
-    const float t0 = da * G;
+    const float t0 = da * ag;
     const float t1 = t0 * dx, t2 = t0 * dy;
     if constexpr (FIRST) {
         acc[6] = gr * w;
@@ -2090,7 +2099,7 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
 #pragma unroll
             for (int q = 1; q < BWD_STEP; q++) ks[q] = pop_high<NW>(m);
             float4 sg0[BWD_STEP], sg1[BWD_STEP], sat[BWD_STEP];
-            float su[BWD_STEP], nho[BWD_STEP];
+            float su[BWD_STEP];
             uint32_t sr[BWD_STEP], spos[BWD_STEP];
 #pragma unroll
             for (int q = 0; q < BWD_STEP; q++) {
@@ -2100,7 +2109,6 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 sat[q] = s_at[k];
                 su[q] = AU ? s_u[k] : 0.0f;
                 sr[q] = s_r[k];
-                nho[q] = -0.5f * sg1[q].w;
                 spos[q] = ks[q] < 0 ? 0xffffffffu : (uint32_t)(bstart + ks[q]);
             }
             float acc[BWD_STEP][10];
@@ -2129,15 +2137,15 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                             a[q] = redecide(a[q], rec, sr[q], ux(j), vy(j), st);
                 }
                 // predicated, not branched: a splat the pixel does not take
-                // enters with alpha 0 and G 0, which leaves T, D and the sums
-                // unchanged
+                // enters with alpha 0 and a_g 0, which leaves T, D and the
+                // sums unchanged
 #pragma unroll
                 for (int q = 0; q < BWD_STEP; q++) {
                     const bool ok = (spos[q] < last[j]) & (a[q] >= st.alpha_min);
                     any[q] = any[q] | ok;
                     const float a0 = ok ? a[q] : 0.0f;
-                    const float G0 = (ok & (sg1[q].w * G[q] <= amax)) ? G[q] : 0.0f;
-                    bwd_pixel<AU>(a0, G0, dx[q], dy[q], sat[q], su[q], gr[j], gg[j], gb[j], gd[j], ga[j],
+                    const float ag = sg1[q].w * G[q] <= amax ? a0 : 0.0f;
+                    bwd_pixel<AU>(a0, ag, dx[q], dy[q], sat[q], su[q], gr[j], gg[j], gb[j], gd[j], ga[j],
                                   gu[j], T[j], D[j], acc[q]);
                 }
             }
@@ -2156,9 +2164,8 @@ __global__ __launch_bounds__(64 * NW, AU ? 1 : 3) void k_render_bwd(const ViewDe
                 if (lane < 32 && v >= 0) {
                     const int q = v >= 10 ? 1 : 0;
                     const int slot = v - 10 * q;
-                    const double f = slot < 5 ? (double)(q ? nho[1] : nho[0]) : 1.0;
                     if (q ? t[1] : t[0])
-                        unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + slot, (double)tot * f);
+                        unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + slot, (double)tot);
                 }
             }
         }
@@ -2291,55 +2298,65 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
                 ca[q] = s_at[k];
                 cu[q] = AU ? s_u[k] : 0.0f;
             }
-            float nho[2];
             uint32_t sr[2], spos[2];
 #pragma unroll
             for (int q = 0; q < 2; q++) {
                 sr[q] = __float_as_uint(cp[q].z);
                 spos[q] = __float_as_uint(cp[q].w);
-                nho[q] = -0.5f * cg[q].w;
             }
             float acc[2][10];
             bool any[2];
 #pragma unroll
             for (int q = 0; q < 2; q++) any[q] = false;
             // every alpha of the step first (one block of independent work),
-            // then the rare binary64 re-decisions, then the ordered updates
-            float a[PPT][2], G[PPT][2], dx[PPT][2], dy[PPT][2];
-            bool need = false;
-#pragma unroll
-            for (int j = 0; j < PPT; j++)
-#pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    float w1, w2;
-                    a[j][q] = splat_alpha(cp[q].x, cp[q].y, cg[q], px0 + bx(j), py0 + by(j), amax, G[j][q],
-                                          dx[j][q], dy[j][q], w1, w2);
-                    need = need | near_amin(a[j][q], st.alpha_min, band);
-                }
-            if (__ballot(need)) {
+            // then the rare binary64 re-decisions, then the ordered updates.
+            // CL: a splat of the step is more opaque than alpha_max, so its
+            // alpha may be clamped and then carries no gradient; otherwise
+            // alpha = o G carries it at every pixel (a_g = a)
+            auto step = [&](auto clamp) {
+                constexpr bool CL = decltype(clamp)::value;
+                float a[PPT][2], G[PPT][2], dx[PPT][2], dy[PPT][2];
+                bool need = false;
 #pragma unroll
                 for (int j = 0; j < PPT; j++)
 #pragma unroll
-                    for (int q = 0; q < 2; q++)
-                        if ((spos[q] < last[j]) & near_amin(a[j][q], st.alpha_min, band))
-                            a[j][q] = redecide(a[j][q], rec, sr[q], ux(j), vy(j), st);
-            }
+                    for (int q = 0; q < 2; q++) {
+                        float w1, w2;
+                        a[j][q] = splat_alpha<CL>(cp[q].x, cp[q].y, cg[q], px0 + bx(j), py0 + by(j), amax, G[j][q],
+                                                  dx[j][q], dy[j][q], w1, w2);
+                        need = need | near_amin(a[j][q], st.alpha_min, band);
+                    }
+                if (__ballot(need)) {
 #pragma unroll
-            for (int j = 0; j < PPT; j++) {
+                    for (int j = 0; j < PPT; j++)
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    const bool ok = (spos[q] < last[j]) & (a[j][q] >= st.alpha_min);
-                    any[q] = any[q] | ok;
-                    const float a0 = ok ? a[j][q] : 0.0f;
-                    const float G0 = (ok & (cg[q].w * G[j][q] <= amax)) ? G[j][q] : 0.0f;
-                    if (j == 0)
-                        bwd_pixel<AU, true>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], gr[j], gg[j], gb[j],
-                                            gd[j], ga[j], gu[j], T[j], D[j], acc[q]);
-                    else
-                        bwd_pixel<AU>(a0, G0, dx[j][q], dy[j][q], ca[q], cu[q], gr[j], gg[j], gb[j], gd[j],
-                                      ga[j], gu[j], T[j], D[j], acc[q]);
+                        for (int q = 0; q < 2; q++)
+                            if ((spos[q] < last[j]) & near_amin(a[j][q], st.alpha_min, band))
+                                a[j][q] = redecide(a[j][q], rec, sr[q], ux(j), vy(j), st);
                 }
-            }
+#pragma unroll
+                for (int j = 0; j < PPT; j++) {
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        const bool ok = (spos[q] < last[j]) & (a[j][q] >= st.alpha_min);
+                        any[q] = any[q] | ok;
+                        const float a0 = ok ? a[j][q] : 0.0f;
+                        const float ag = CL ? (cg[q].w * G[j][q] <= amax ? a0 : 0.0f) : a0;
+                        if (j == 0)
+                            bwd_pixel<AU, true>(a0, ag, dx[j][q], dy[j][q], ca[q], cu[q], gr[j], gg[j], gb[j],
+                                                gd[j], ga[j], gu[j], T[j], D[j], acc[q]);
+                        else
+                            bwd_pixel<AU>(a0, ag, dx[j][q], dy[j][q], ca[q], cu[q], gr[j], gg[j], gb[j], gd[j],
+                                          ga[j], gu[j], T[j], D[j], acc[q]);
+                    }
+                }
+            };
+            // opacities and alpha_max are positive: their bits order as they do
+            const uint32_t amax_bits = __float_as_uint(amax);
+            if (__ballot((__float_as_uint(cg[0].w) > amax_bits) | (__float_as_uint(cg[1].w) > amax_bits)))
+                step(BoolC<true>{});
+            else
+                step(BoolC<false>{});
             bool t[2];
 #pragma unroll
             for (int q = 0; q < 2; q++) t[q] = __ballot(any[q]) != 0;
@@ -2351,9 +2368,8 @@ __global__ __launch_bounds__(64, AU ? 1 : 3) void k_render_bwd1(const ViewDev* _
             if (lane < 32 && v >= 0) {
                 const int q = v >= 10 ? 1 : 0;
                 const int slot = v - 10 * q;
-                const double f = slot < 5 ? (double)(q ? nho[1] : nho[0]) : 1.0;
                 if (q ? t[1] : t[0])
-                    unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + slot, (double)tot * f);
+                    unsafeAtomicAdd(g2d + (uint64_t)(q ? sr[1] : sr[0]) * G2D_STRIDE + slot, (double)tot);
             }
         }
     }
@@ -2385,7 +2401,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
         GProj q;
         project_exact(P, V, st, q);
         const double* G2 = g2d + (uint64_t)r * G2D_STRIDE;
-        go += G2[5];
+        go += G2[5];  // divided by the opacity below
         gc[0] += G2[6];
         gc[1] += G2[7];
         gc[2] += G2[8];
@@ -2393,12 +2409,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
         double det = q.cxx * q.cyy - q.cxy * q.cxy;
         double Qxx = q.cyy / det, Qxy = -q.cxy / det, Qyy = q.cxx / det;
         // the 2D mean: power = d^T Q d with d = pixel - mean, so
-        // dL/dmean = -2 Q sum_p dpow d (slots 0 and 1 hold the sum)
-        double gmx = -2.0 * (Qxx * G2[0] + Qxy * G2[1]);
-        double gmy = -2.0 * (Qxy * G2[0] + Qyy * G2[1]);
-        // conic gradient (slots 2..4: dL/dQxx, dL/dQxy of the xy term taken
-        // once, dL/dQyy) -> symmetric matrix gradient
-        double Gq00 = G2[2], Gq01 = G2[3], Gq11 = G2[4];
+        // dL/dmean = -2 Q sum_p dpow d, and slots 0 and 1 hold -2 times that
+        // sum (dpow = -t / 2)
+        double gmx = Qxx * G2[0] + Qxy * G2[1];
+        double gmy = Qxy * G2[0] + Qyy * G2[1];
+        // conic gradient (slots 2..4 times -1/2: dL/dQxx, dL/dQxy of the xy
+        // term taken once, dL/dQyy) -> symmetric matrix gradient
+        double Gq00 = -0.5 * G2[2], Gq01 = -0.5 * G2[3], Gq11 = -0.5 * G2[4];
         // G_cov = -Q G_Q Q
         double m00 = Gq00 * Qxx + Gq01 * Qxy, m01 = Gq00 * Qxy + Gq01 * Qyy;
         double m10 = Gq01 * Qxx + Gq11 * Qxy, m11 = Gq01 * Qxy + Gq11 * Qyy;
@@ -2463,6 +2480,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussDev g, const ViewDev* 
 #pragma unroll
         for (int a = 0; a < 3; a++) gm[a] += R[a * 3 + 0] * gtx + R[a * 3 + 1] * gty + R[a * 3 + 2] * gtz;
     }
+    // slot 5 summed dL/da a_g = o dL/do over the pixels (o >= alpha_min > 0)
+    go /= P.o;
     if (st.isotropic) {
         // one radius for the three axes; no rotation
         if (d_means) {
