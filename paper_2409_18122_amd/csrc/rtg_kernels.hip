@@ -1793,15 +1793,27 @@ __global__ __launch_bounds__(256) void k_loss(const ViewDev* __restrict__ views,
     if (threadIdx.x == 0) partial[(uint64_t)blockIdx.y * gridDim.x + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int n,
-                                                      double* __restrict__ out) {
-    __shared__ double ws[4];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
-    s = wave_sum_d(s);
+// One block; each thread keeps four running sums over entries 4096 apart, so
+// that four loads are in flight per step (the order is fixed: the total is
+// the same on every run).
+constexpr int SP_THREADS = 1024;
+__global__ __launch_bounds__(SP_THREADS) void k_sum_partials(const double* __restrict__ partial, int n,
+                                                             double* __restrict__ out) {
+    __shared__ double ws[SP_THREADS / 64];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 4 * SP_THREADS) {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (i + k * SP_THREADS < n) a[k] += partial[i + k * SP_THREADS];
+    }
+    double s = wave_sum_d((a[0] + a[1]) + (a[2] + a[3]));
     if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) *out = ws[0] + ws[1] + ws[2] + ws[3];
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < SP_THREADS / 64; w++) t += ws[w];
+        *out = t;
+    }
 }
 
 // ------------------------------------------------------------ backward
@@ -3374,7 +3386,7 @@ void loss_l1(const ViewDev* views, int n_views, int max_pix, const float* rgb, c
     (void)partial_cap;
     dim3 grid(bx, n_views);
     k_loss<<<grid, 256, 0, s>>>(views, rgb, depth, trgb, tdepth, w_depth, d_rgb, d_depth, partial);
-    k_sum_partials<<<1, 256, 0, s>>>(partial, (int)(bx * n_views), loss);
+    k_sum_partials<<<1, SP_THREADS, 0, s>>>(partial, (int)(bx * n_views), loss);
 }
 
 // Waves per tile for the backward: enough workgroups to fill the chip on
