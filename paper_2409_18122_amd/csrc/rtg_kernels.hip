@@ -530,15 +530,19 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in,
 // the block-major histogram table; more blocks scan a digit-major table with
 // the multi-block scan.
 
-// 16 items per lane (a 4096-item tile per block step): each digit's run per
-// step is twice as long as with 8, so fewer of the scatter's writes are
-// partial cache lines (measured 3% faster on 192M pairs, 6% on 40M).
+// 16 items per lane (a 4096-item tile per block step of 256 threads): each
+// digit's run per step is twice as long as with 8, so fewer of the scatter's
+// writes are partial cache lines (measured 3% faster on 192M pairs, 6% on
+// 40M).  Inputs of at least RS_BIG_ITEMS take blocks of 512 threads (8192-item
+// tiles, runs twice as long again); smaller ones keep 256, which gives them
+// twice as many blocks.
 constexpr int RS_THREADS = 256;
-constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_THREADS_BIG = 512;
 constexpr int RS_IPT = 16;
 constexpr int RS_SEG = 64 * RS_IPT;         // items per wave per tile
-constexpr int RS_TILE = RS_THREADS * RS_IPT;  // items per block per tile
+constexpr int RS_TILE = RS_THREADS * RS_IPT;  // items per block per tile (256 threads)
 constexpr int RS_MAX_BLOCKS = 1024;
+constexpr uint64_t RS_BIG_ITEMS = (uint64_t)RS_MAX_BLOCKS * RS_THREADS_BIG * RS_IPT;
 constexpr int RS_FUSED_BLOCKS = 128;
 constexpr int RS_MAX_DB = 11;
 
@@ -554,9 +558,10 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid) {
     return m;
 }
 
+template <int TILE>
 __device__ __forceinline__ void rs_chunk(uint32_t n, uint32_t& begin, uint32_t& end) {
     uint32_t per = (uint32_t)(((uint64_t)n + gridDim.x - 1) / gridDim.x);
-    per = (per + RS_TILE - 1) / RS_TILE * RS_TILE;
+    per = (per + TILE - 1) / TILE * TILE;
     uint64_t b = (uint64_t)blockIdx.x * per;
     begin = (uint32_t)min<uint64_t>(b, n);
     end = (uint32_t)min<uint64_t>(b + per, n);
@@ -565,28 +570,29 @@ __device__ __forceinline__ void rs_chunk(uint32_t n, uint32_t& begin, uint32_t& 
 // Digit of this pass: `bits` (<= DB) bits from `shift`.
 // hist layout: digit-major [d][block] when block_major == 0 (scanned as a
 // whole), block-major [block][d] otherwise (read directly by the scatter).
-template <int DB>
-__global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __restrict__ keys,
+template <int DB, int NT>
+__global__ __launch_bounds__(NT) void k_rs_upsweep(const uint32_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ n_dev, uint32_t cap,
                                                            int shift, int bits, uint32_t* __restrict__ hist,
                                                            int block_major) {
     constexpr int NB = 1 << DB;
+    constexpr int WAVES = NT / 64, TILE = NT * RS_IPT;
     // each wave counts into CP copies of its table (lane l into copy l % CP),
     // so that a skewed digit (few tiles or views dominating a pass) does not
     // serialise a whole wave's atomics on one LDS word
     constexpr int CP = DB <= 8 ? 4 : 1;
-    __shared__ uint32_t h[RS_WAVES * CP][NB];
+    __shared__ uint32_t h[WAVES * CP][NB];
     const int tid = threadIdx.x, wv = tid >> 6;
     const int cp = wv * CP + (int)(lane_id() % CP);
     const uint32_t mask = (1u << bits) - 1u;
-    for (int i = tid; i < RS_WAVES * CP * NB; i += RS_THREADS) (&h[0][0])[i] = 0;
+    for (int i = tid; i < WAVES * CP * NB; i += NT) (&h[0][0])[i] = 0;
     __syncthreads();
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
-    rs_chunk(n, begin, end);
+    rs_chunk<TILE>(n, begin, end);
     // the scatter's tiling: RS_IPT coalesced loads per lane in flight, then
     // their RS_IPT additions to the wave's table
-    for (uint32_t t0 = begin; t0 < end; t0 += RS_TILE) {
+    for (uint32_t t0 = begin; t0 < end; t0 += TILE) {
         const uint32_t seg = t0 + wv * RS_SEG;
         uint32_t k[RS_IPT];
 #pragma unroll
@@ -601,10 +607,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
         }
     }
     __syncthreads();
-    for (int d = tid; d < NB; d += RS_THREADS) {
+    for (int d = tid; d < NB; d += NT) {
         uint32_t c = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES * CP; w++) c += h[w][d];
+        for (int w = 0; w < WAVES * CP; w++) c += h[w][d];
         if (block_major)
             hist[(uint64_t)blockIdx.x * NB + d] = c;
         else
@@ -616,8 +622,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_upsweep(const uint32_t* __res
 // in LDS and written out in that order, so that consecutive lanes write the
 // consecutive addresses of a digit's run; otherwise each item is written from
 // where its wave ranked it.
-template <int DB, bool STAGE>
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
+template <int DB, bool STAGE, int NT>
+__global__ __launch_bounds__(NT) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            uint32_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout,
@@ -626,11 +632,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                                                            int block_major, const uint32_t* __restrict__ gsrc,
                                                            uint32_t* __restrict__ gout) {
     constexpr int NB = 1 << DB;
-    constexpr int DPT = NB / RS_THREADS > 0 ? NB / RS_THREADS : 1;  // digits per thread
-    __shared__ uint32_t wh[RS_WAVES][NB];
+    constexpr int WAVES = NT / 64, TILE = NT * RS_IPT;
+    constexpr int DPT = NB / NT > 0 ? NB / NT : 1;  // digits per thread
+    __shared__ uint32_t wh[WAVES][NB];
     __shared__ uint32_t bbase[NB];
-    __shared__ uint32_t ws[RS_WAVES];
-    constexpr int SB = STAGE ? NB : 1, ST = STAGE ? RS_TILE : 1;
+    __shared__ uint32_t ws[WAVES];
+    constexpr int SB = STAGE ? NB : 1, ST = STAGE ? TILE : 1;
     __shared__ uint32_t lst[SB], tcnt[SB];
     __shared__ uint32_t s_k[ST], s_v[ST];
     const int tid = threadIdx.x, wv = tid >> 6;
@@ -638,7 +645,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     const uint32_t mask = (1u << bits) - 1u;
     uint32_t n = min(*n_dev, cap);
     uint32_t begin, end;
-    rs_chunk(n, begin, end);
+    rs_chunk<TILE>(n, begin, end);
     if (block_major) {
         // offset of digit d for this block = count of smaller digits in all
         // blocks + count of digit d in earlier blocks; thread tid owns the
@@ -680,7 +687,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
         __syncthreads();
         uint32_t base = inc - mine;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; w++)
+        for (int w = 0; w < WAVES; w++)
             if (w < wv) base += ws[w];
         if (tid * DPT < NB) {
 #pragma unroll
@@ -690,10 +697,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
             }
         }
     } else {
-        for (int d = tid; d < NB; d += RS_THREADS) bbase[d] = hist[(uint64_t)d * gridDim.x + blockIdx.x];
+        for (int d = tid; d < NB; d += NT) bbase[d] = hist[(uint64_t)d * gridDim.x + blockIdx.x];
     }
-    for (uint32_t t0 = begin; t0 < end; t0 += RS_TILE) {
-        for (int i = tid; i < RS_WAVES * NB; i += RS_THREADS) (&wh[0][0])[i] = 0;
+    for (uint32_t t0 = begin; t0 < end; t0 += TILE) {
+        for (int i = tid; i < WAVES * NB; i += NT) (&wh[0][0])[i] = 0;
         __syncthreads();
         uint32_t seg = t0 + wv * RS_SEG;
         uint32_t k[RS_IPT], v[RS_IPT], pos[RS_IPT];
@@ -717,10 +724,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
         }
         __syncthreads();
         if constexpr (!STAGE) {
-            for (int d = tid; d < NB; d += RS_THREADS) {
+            for (int d = tid; d < NB; d += NT) {
                 uint32_t run = bbase[d];
 #pragma unroll
-                for (int w = 0; w < RS_WAVES; w++) {
+                for (int w = 0; w < WAVES; w++) {
                     uint32_t c = wh[w][d];
                     wh[w][d] = run;
                     run += c;
@@ -741,10 +748,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
             }
         } else {
             // per digit: the waves' offsets inside the tile's run of the digit, and the run length
-            for (int d = tid; d < NB; d += RS_THREADS) {
+            for (int d = tid; d < NB; d += NT) {
                 uint32_t run = 0;
 #pragma unroll
-                for (int w = 0; w < RS_WAVES; w++) {
+                for (int w = 0; w < WAVES; w++) {
                     uint32_t c = wh[w][d];
                     wh[w][d] = run;
                     run += c;
@@ -767,7 +774,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                 __syncthreads();
                 uint32_t base = inc - mine;
 #pragma unroll
-                for (int w = 0; w < RS_WAVES; w++)
+                for (int w = 0; w < WAVES; w++)
                     if (w < wv) base += ws[w];
                 if (tid * DPT < NB) {
 #pragma unroll
@@ -789,8 +796,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                 }
             }
             __syncthreads();
-            const uint32_t tn = min<uint32_t>(RS_TILE, end - t0);
-            for (uint32_t i = tid; i < tn; i += RS_THREADS) {
+            const uint32_t tn = min<uint32_t>(TILE, end - t0);
+            for (uint32_t i = tid; i < tn; i += NT) {
                 const uint32_t kk = s_k[i];
                 const uint32_t d = (kk >> shift) & mask;
                 const uint32_t dst = bbase[d] + (i - lst[d]);
@@ -800,7 +807,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
                 if (gsrc) gout[dst] = gsrc[vv];
             }
             __syncthreads();
-            for (int d = tid; d < NB; d += RS_THREADS) bbase[d] += tcnt[d];
+            for (int d = tid; d < NB; d += NT) bbase[d] += tcnt[d];
         }
         __syncthreads();
     }
@@ -3286,22 +3293,26 @@ void scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const u
 // 2^db x blocks loads per block, so for them inputs of up to
 // RS_FUSED_BLOCKS * 8 tiles use at most RS_FUSED_BLOCKS blocks, each walking
 // several tiles, and need no separate offset scan.
-int sort_blocks(uint64_t cap, int db) {
-    uint64_t t = (cap + RS_TILE - 1) / RS_TILE;
+static int sort_blocks_tile(uint64_t cap, int db, int tile) {
+    uint64_t t = (cap + tile - 1) / tile;
     if (t < 1) t = 1;
     if (db > 8 && t <= (uint64_t)RS_FUSED_BLOCKS * 8) return (int)std::min<uint64_t>(t, RS_FUSED_BLOCKS);
     return (int)std::min<uint64_t>(t, RS_MAX_BLOCKS);
 }
 
+// The block count of the 256-thread form (at least that of the 512-thread one).
+int sort_blocks(uint64_t cap, int db) { return sort_blocks_tile(cap, db, RS_TILE); }
+
 size_t sort_hist_words(uint64_t cap) {
     return (size_t)(1u << RS_MAX_DB) * (size_t)std::max(sort_blocks(cap, 8), sort_blocks(cap, RS_MAX_DB));
 }
 
-template <int DB>
+template <int DB, int NT>
 static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, const uint32_t* n_dev, uint32_t cap,
-                    int nb, int shift, int bits, SortWs ws, const uint32_t* gsrc, uint32_t* gout, hipStream_t s) {
+                    int shift, int bits, SortWs ws, const uint32_t* gsrc, uint32_t* gout, hipStream_t s) {
+    const int nb = sort_blocks_tile(cap, DB, NT * RS_IPT);
     const int fused = nb <= RS_FUSED_BLOCKS;
-    k_rs_upsweep<DB><<<nb, RS_THREADS, 0, s>>>(ki, n_dev, cap, shift, bits, ws.hist, fused);
+    k_rs_upsweep<DB, NT><<<nb, NT, 0, s>>>(ki, n_dev, cap, shift, bits, ws.hist, fused);
     if (!fused) {
         // table of 2^DB * nb counts, a size known here: the multi-block scan,
         // in place
@@ -3313,8 +3324,8 @@ static void rs_pass(uint32_t* ki, uint32_t* vi, uint32_t* ko, uint32_t* vo, cons
     }
     // 8-bit passes stage their scatter in LDS; the 11-bit one writes directly (its
     // per-wave tables already take 32 KB of LDS)
-    k_rs_scatter<DB, DB == 8><<<nb, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused,
-                                                         gsrc, gout);
+    k_rs_scatter<DB, DB == 8, NT><<<nb, NT, 0, s>>>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws.hist, fused,
+                                                     gsrc, gout);
 }
 
 // The nbits are split into the fewest passes of at most max_db bits, as
@@ -3330,10 +3341,12 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uin
         const bool last = p + 1 == passes;
         const uint32_t* gs = last ? gsrc : nullptr;
         uint32_t* go = last ? gout : nullptr;
-        if (bits <= 8)
-            rs_pass<8>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, 8), shift, std::max(bits, 1), ws, gs, go, s);
+        if (bits <= 8 && cap >= RS_BIG_ITEMS)
+            rs_pass<8, RS_THREADS_BIG>(ki, vi, ko, vo, n_dev, cap, shift, std::max(bits, 1), ws, gs, go, s);
+        else if (bits <= 8)
+            rs_pass<8, RS_THREADS>(ki, vi, ko, vo, n_dev, cap, shift, std::max(bits, 1), ws, gs, go, s);
         else
-            rs_pass<RS_MAX_DB>(ki, vi, ko, vo, n_dev, cap, sort_blocks(cap, RS_MAX_DB), shift, bits, ws, gs, go, s);
+            rs_pass<RS_MAX_DB, RS_THREADS>(ki, vi, ko, vo, n_dev, cap, shift, bits, ws, gs, go, s);
         shift += bits;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
