@@ -944,6 +944,8 @@ constexpr uint32_t PE_PRE = 64;
 // Records with more tile rows than this have their rows counted by the
 // whole wave (a wave would otherwise loop as long as its tallest record).
 constexpr uint32_t PE_ROWS_SELF = 4;
+// Visibility mask words a record's view search loads at once.
+constexpr int PE_MASK_WORDS = 8;
 
 __device__ __forceinline__ float readlane_f(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -1006,18 +1008,31 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
         uint32_t nt = 0, ty0 = 0, ny = 0;
         if (valid) {
             // owner Gaussian: the last one whose first record is at or before pos
-            const uint32_t i = lo + (staged ? last_le(s_off, ng, pos) : last_le(rec_off + lo, ng, pos));
-            // its (pos - rec_off[i])-th visible view
-            uint32_t kk = pos - rec_off[i];
+            const uint32_t ii = staged ? last_le(s_off, ng, pos) : last_le(rec_off + lo, ng, pos);
+            const uint32_t i = lo + ii;
+            // its (pos - rec_off[i])-th visible view; the mask words are
+            // loaded eight at a time (256 views), all in flight together,
+            // then scanned for the word that holds it
+            uint32_t kk = pos - (staged ? s_off[ii] : rec_off[i]);
             int v = 0;
-            for (int w = 0; w < words; w++) {
-                const uint32_t vis = mask[(int64_t)w * n + i];
-                const uint32_t c = (uint32_t)__popc(vis);
-                if (kk < c) {
-                    v = 32 * w + nth_set_bit(vis, kk);
-                    break;
+            bool found = false;
+            for (int w0 = 0; w0 < words && !found; w0 += PE_MASK_WORDS) {
+                uint32_t vis[PE_MASK_WORDS];
+#pragma unroll
+                for (int q = 0; q < PE_MASK_WORDS; q++)
+                    vis[q] = w0 + q < words ? mask[(int64_t)(w0 + q) * n + i] : 0u;
+                uint32_t word = 0;
+                int wsel = 0;
+#pragma unroll
+                for (int q = 0; q < PE_MASK_WORDS; q++) {
+                    const uint32_t c = (uint32_t)__popc(vis[q]);
+                    const bool here = !found && kk < c;
+                    word = here ? vis[q] : word;
+                    wsel = here ? w0 + q : wsel;
+                    kk = !found && !here ? kk - c : kk;
+                    found = found || here;
                 }
-                kk -= c;
+                if (found) v = 32 * wsel + nth_set_bit(word, kk);
             }
             GPre P;
             if (shared_pre) P = s_pre[i - lo];
