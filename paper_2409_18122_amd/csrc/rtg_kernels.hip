@@ -120,34 +120,50 @@ __device__ inline bool pre_gauss(const GaussDev& g, int64_t i, const SetDev& st,
 // certain to be culled (behind the near plane, or its support box cannot meet
 // the image).  The half extent of the support box is bounded through
 // Sigma_xx <= s_max^2 |J_row0|^2 = s_max^2 fx^2 / t_z^2 (1 + t_x^2 / t_z^2).
-__device__ inline bool may_be_visible(const GPre& P, const ViewDev& V, const SetDev& st) {
-    float dx = P.mu_f[0] - V.Tf[0];
-    float dy = P.mu_f[1] - V.Tf[1];
-    float dz = P.mu_f[2] - V.Tf[2];
+// The binary32 camera values the test reads, packed in five 16-byte words:
+// the columns of R with the camera centre, (fx, fy, cx, cy), (W - 1, H - 1).
+struct CullView {
+    float4 c0, c1, c2, k, wh;
+};
+
+__device__ __forceinline__ CullView cull_view(const ViewDev& V) {
+    CullView f;
+    f.c0 = make_float4(V.Rf[0], V.Rf[3], V.Rf[6], V.Tf[0]);
+    f.c1 = make_float4(V.Rf[1], V.Rf[4], V.Rf[7], V.Tf[1]);
+    f.c2 = make_float4(V.Rf[2], V.Rf[5], V.Rf[8], V.Tf[2]);
+    f.k = make_float4(V.fxf, V.fyf, V.cxf, V.cyf);
+    f.wh = make_float4((float)(V.W - 1), (float)(V.H - 1), 0.0f, 0.0f);
+    return f;
+}
+
+__device__ inline bool may_be_visible(const GPre& P, const CullView& V, const SetDev& st) {
+    float dx = P.mu_f[0] - V.c0.w;
+    float dy = P.mu_f[1] - V.c1.w;
+    float dz = P.mu_f[2] - V.c2.w;
     float mag = fabsf(dx) + fabsf(dy) + fabsf(dz) + 1.0f;
-    float tz = dx * V.Rf[2] + dy * V.Rf[5] + dz * V.Rf[8];
+    float tz = dx * V.c2.x + dy * V.c2.y + dz * V.c2.z;
     float err = 1e-5f * mag;
     if (tz + err <= st.z_near) return false;
     if (tz <= 0.5f * st.z_near) return true;  // let the exact test decide
-    float tx = dx * V.Rf[0] + dy * V.Rf[3] + dz * V.Rf[6];
-    float ty = dx * V.Rf[1] + dy * V.Rf[4] + dz * V.Rf[7];
+    float tx = dx * V.c0.x + dy * V.c0.y + dz * V.c0.z;
+    float ty = dx * V.c1.x + dy * V.c1.y + dz * V.c1.z;
     // hardware reciprocal and square root (within an ulp or two): the slack
     // below is a relative 1e-3 plus a pixel
     float iz = __builtin_amdgcn_rcpf(tz);
     float ux = tx * iz, uy = ty * iz;
-    float fx = V.fxf, fy = V.fyf;
-    float ax = fx * ux + V.cxf;
-    float ay = fy * uy + V.cyf;
+    float fx = V.k.x, fy = V.k.y;
+    float ax = fx * ux + V.k.z;
+    float ay = fy * uy + V.k.w;
     float rx = P.reach * fx * iz, ry = P.reach * fy * iz;
     const float ep = 2.0f * P.rho_f * st.eps2d + st.eps2d * P.rho2_f;
     float hx = __builtin_amdgcn_sqrtf(rx * rx * (1.0f + ux * ux) + ep);
     float hy = __builtin_amdgcn_sqrtf(ry * ry * (1.0f + uy * uy) + ep);
-    float slack_x = 1e-3f * (fabsf(ax - V.cxf) + hx) + 1.0f + err * fx * iz * 4.0f;
-    float slack_y = 1e-3f * (fabsf(ay - V.cyf) + hy) + 1.0f + err * fy * iz * 4.0f;
+    float slack_x = 1e-3f * (fabsf(ax - V.k.z) + hx) + 1.0f + err * fx * iz * 4.0f;
+    float slack_y = 1e-3f * (fabsf(ay - V.k.w) + hy) + 1.0f + err * fy * iz * 4.0f;
     if (ax + hx + slack_x < 0.0f) return false;
-    if (ax - hx - slack_x > (float)(V.W - 1)) return false;
+    if (ax - hx - slack_x > V.wh.x) return false;
     if (ay + hy + slack_y < 0.0f) return false;
-    if (ay - hy - slack_y > (float)(V.H - 1)) return false;
+    if (ay - hy - slack_y > V.wh.y) return false;
     return true;
 }
 
@@ -349,15 +365,28 @@ __device__ __noinline__ uint2 support_row(SupportRows S, uint32_t ty, int tws, i
     return make_uint2(first, ((uint32_t)cr >> tws) - first + 1);
 }
 
+constexpr int PC_VIEWS = 256;
+
+// STAGED (batches of at most PC_VIEWS views): the cameras' test values are
+// read from LDS; otherwise from the view table in global memory.
+template <bool STAGED>
 __global__ __launch_bounds__(256) void k_project_count(GaussDev g, const ViewDev* __restrict__ views,
                                                        const Header* __restrict__ hdr, int words,
                                                        SetDev st, uint32_t* __restrict__ cnt,
                                                        uint32_t* __restrict__ mask) {
+    // the cameras' test values, staged in LDS (every thread reads the same
+    // camera at a time; from LDS it waits less than from the scalar cache,
+    // which the cameras of a large batch overflow)
+    __shared__ CullView s_vf[STAGED ? PC_VIEWS : 1];
+    int nv = (int)hdr->n_views;
+    if (STAGED) {
+        for (int t = threadIdx.x; t < min(nv, PC_VIEWS); t += blockDim.x) s_vf[t] = cull_view(views[t]);
+        __syncthreads();
+    }
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     GPre P;
     bool ok = pre_gauss(g, i, st, P);
-    int nv = (int)hdr->n_views;
     uint32_t c = 0;
     for (int w = 0; w < words; w++) {
         uint32_t vis = 0;
@@ -365,8 +394,11 @@ __global__ __launch_bounds__(256) void k_project_count(GaussDev g, const ViewDev
         if (ok && base < nv) {
             uint32_t cand = 0;
             int lim = min(32, nv - base);
-            for (int b = 0; b < lim; b++)
-                if (may_be_visible(P, views[base + b], st)) cand |= 1u << b;
+            for (int b = 0; b < lim; b++) {
+                const int vb = base + b;
+                const CullView V = STAGED ? s_vf[vb] : cull_view(views[vb]);
+                if (may_be_visible(P, V, st)) cand |= 1u << b;
+            }
             while (cand) {
                 int b = __ffs(cand) - 1;
                 cand &= cand - 1;
@@ -3267,7 +3299,10 @@ void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, i
     if (g.n == 0) return;
     int words = (n_views_cap + 31) / 32;
     // one thread per Gaussian: the grid covers every n below 2^31
-    k_project_count<<<grid_for(g.n, 256, 0xffffffffu), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
+    if (n_views_cap <= PC_VIEWS)
+        k_project_count<true><<<grid_for(g.n, 256, 0xffffffffu), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
+    else
+        k_project_count<false><<<grid_for(g.n, 256, 0xffffffffu), 256, 0, s>>>(g, views, hdr, words, st, cnt, mask);
 }
 
 // log2 of a power-of-two tile side (8, 16 or 32)
