@@ -1146,7 +1146,29 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
     }
 }
 
-__global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* __restrict__ order,
+// Record offsets per thread for one chunk's EM_ITEMS + 1 entries.
+constexpr int EM_OFF_PT = (EM_ITEMS + 1 + EM_THREADS - 1) / EM_THREADS;
+
+// Loads (issues) a chunk's record offsets from its first record lo and the
+// ids of the records the thread sets up; entries past the last record read as
+// "after every pair" (offsets) and 0 (ids).
+__device__ __forceinline__ void em_load_chunk(const uint32_t* __restrict__ inst_off,
+                                              const uint32_t* __restrict__ order, uint32_t R, uint32_t lo,
+                                              uint32_t (&off)[EM_OFF_PT], uint32_t (&rid)[EM_RUN]) {
+    const uint32_t navail = min<uint32_t>(EM_ITEMS + 1, R - lo);
+#pragma unroll
+    for (int m = 0; m < EM_OFF_PT; m++) {
+        const uint32_t q = threadIdx.x + m * EM_THREADS;
+        off[m] = q < navail ? inst_off[lo + q] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int q = 0; q < EM_RUN; q++) {
+        const uint32_t jr = threadIdx.x * EM_RUN + q;
+        rid[q] = jr < R - lo ? order[lo + jr] : 0u;
+    }
+}
+
+__global__ __launch_bounds__(EM_THREADS, 4) void k_emit_instances(const uint32_t* __restrict__ order,
                                                                const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
                                                                const uint32_t* __restrict__ K_dev, Records rec,
                                                                const ViewDev* __restrict__ views,
@@ -1189,20 +1211,33 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
         const uint32_t lo0 = wave_last_le(inst_off, R, kbeg);
         if (threadIdx.x == 0) s_lo = lo0;
     }
+    __syncthreads();
+    uint32_t lo_chunk = s_lo;
+    // the first chunk's record offsets and ids; every chunk then issues the
+    // next one's loads before it sets up its own records, so that they arrive
+    // while it works
+    uint32_t pf_off[EM_OFF_PT], pf_rid[EM_RUN];
+    em_load_chunk(inst_off, order, R, lo_chunk, pf_off, pf_rid);
     for (uint32_t k0 = kbeg; k0 < kend; k0 += EM_ITEMS) {
         const uint32_t k1 = min(k0 + EM_ITEMS, kend);  // exclusive
+        const uint32_t lo = lo_chunk;
         __syncthreads();
         // the offsets of the records from the first one spanning the chunk
         // (every record owns at least one pair, so at most EM_ITEMS records
         // span it); entries past the last record read as "after every pair"
-        const uint32_t lo = s_lo;
         const uint32_t navail = min<uint32_t>(EM_ITEMS + 1, R - lo);
-        for (uint32_t q = threadIdx.x; q < EM_ITEMS + 1; q += EM_THREADS)
-            s_off[q] = q < navail ? inst_off[lo + q] : 0xffffffffu;
+#pragma unroll
+        for (int m = 0; m < EM_OFF_PT; m++) {
+            const uint32_t q = threadIdx.x + m * EM_THREADS;
+            if (q < EM_ITEMS + 1) s_off[q] = pf_off[m];
+        }
         __syncthreads();
         const uint32_t nrec = last_le(s_off, navail, k1 - 1) + 1;
-        __syncthreads();
-        if (threadIdx.x == 0) s_lo = lo + last_le(s_off, navail, k1);  // the next chunk's first record
+        lo_chunk = lo + last_le(s_off, navail, k1);  // the next chunk's first record
+        uint32_t rids[EM_RUN];
+#pragma unroll
+        for (int q = 0; q < EM_RUN; q++) rids[q] = pf_rid[q];
+        if (k1 < kend) em_load_chunk(inst_off, order, R, lo_chunk, pf_off, pf_rid);
         // table rows of the records (EM_RUN records per thread): every tile
         // row of a record that is not enumerated directly
         uint32_t nr[EM_RUN];
@@ -1212,7 +1247,7 @@ __global__ __launch_bounds__(EM_THREADS) void k_emit_instances(const uint32_t* _
             const uint32_t jr = threadIdx.x * EM_RUN + q;
             nr[q] = 0;
             if (jr < nrec) {
-                const uint32_t rid = order[lo + jr];
+                const uint32_t rid = rids[q];
                 const EmitRec e = rec.emit[rid];
                 const uint32_t tx0 = e.rect.x & 0xffffu, ty0 = e.rect.y & 0xffffu;
                 const uint32_t nx = (e.rect.x >> 16) - tx0 + 1;
