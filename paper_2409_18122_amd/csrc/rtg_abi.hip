@@ -363,7 +363,7 @@ struct rtg_frame {
     bool scoring = false;  // only scored: records carry no colour / depth attributes
     int order_in_alt = 0, inst_in_alt = 0;
 
-    Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist;
+    Buf views, hdr, counters, cnt, mask, rec_off, scan_ws, sort_hist, chunk_g;
     Buf emit, q64, attr, ntiles, skey, skey2, order, order2;
     Buf inst_off, tkey, tkey2, irec, irec2, ranges, tile_ord, tile_ord_ws;
     Buf T_final, n_last, g2d, loss_part, score_part, ssim_maps;
@@ -434,6 +434,7 @@ rtg_status alloc_records(rtg_frame* f, uint32_t rc) {
     RTG_TRY(f->order.ensure(ctx, 4 * r));
     RTG_TRY(f->order2.ensure(ctx, 4 * r));
     RTG_TRY(f->inst_off.ensure(ctx, 4 * r));
+    RTG_TRY(f->chunk_g.ensure(ctx, 4 * pe_chunk_words((uint32_t)r)));
     f->rec_cap = rc;
     return RTG_OK;
 }
@@ -480,8 +481,9 @@ rtg_status enqueue_project(rtg_frame* f, bool eager, hipStream_t s) {
         RTG_TRY(alloc_records(f, f->R));
     }
     project_emit(gd, views, hdr, f->views_cap, sd, f->st.tile_w, f->st.tile_h, f->mask.as<uint32_t>(),
-                 f->rec_off.as<uint32_t>(), f->ctr(C_REC), f->rec_cap, f->records(), f->skey.as<uint32_t>(),
-                 f->order.as<uint32_t>(), !f->scoring, f->ctr(C_FLAGS), s);
+                 f->cnt.as<uint32_t>(), f->rec_off.as<uint32_t>(), f->ctr(C_REC), f->rec_cap, f->records(),
+                 f->skey.as<uint32_t>(), f->order.as<uint32_t>(), !f->scoring, f->chunk_g.as<uint32_t>(),
+                 f->ctr(C_FLAGS), s);
     return check_launch("projection emit");
 }
 

@@ -109,10 +109,14 @@ void project_count(const GaussDev& g, const ViewDev* views, const Header* hdr, i
                    SetDev st, uint32_t* cnt, uint32_t* mask, hipStream_t s);
 // Writes records at rec_off[i] .. for the visible views of Gaussian i (attr
 // only when write_attr).
+// chunk_g: workspace of pe_chunk_words(rec_cap) entries (the owners of each
+// chunk's first and last records, found before the records are written).
+constexpr int PE_CHUNK = 256;  // records per block step of the record emission
+inline size_t pe_chunk_words(uint32_t rec_cap) { return 2 * ((size_t)rec_cap / PE_CHUNK + 2); }
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap,
-                  SetDev st, int tw, int th, const uint32_t* mask, const uint32_t* rec_off,
+                  SetDev st, int tw, int th, const uint32_t* mask, const uint32_t* cnt, const uint32_t* rec_off,
                   const uint32_t* R_dev, uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order,
-                  bool write_attr, uint32_t* flags, hipStream_t s);
+                  bool write_attr, uint32_t* chunk_g, uint32_t* flags, hipStream_t s);
 
 // Exclusive prefix sum of in[0..n) (n = min(*n_dev, cap)) into out; *total =
 // the full sum.  If gather != NULL the input is in[gather[i]].  A sum of 2^31

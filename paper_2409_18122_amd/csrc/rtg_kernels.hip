@@ -997,6 +997,32 @@ __device__ __forceinline__ int nth_set_bit(uint32_t x, uint32_t k) {
     return pos;
 }
 
+static_assert(PE_THREADS == PE_CHUNK, "a block step of the record emission is one chunk");
+
+// The Gaussians that own the first and the last record of every chunk of
+// PE_CHUNK records (chunk_g[2c], chunk_g[2c + 1]): each Gaussian writes the
+// chunk ends that fall among its records, so every entry has one writer.
+// Record p is owned by the Gaussian i with rec_off[i] <= p < rec_off[i] +
+// cnt[i], which is the last Gaussian whose first record is at or before p.
+__global__ __launch_bounds__(256) void k_chunk_owners(const uint32_t* __restrict__ cnt,
+                                                      const uint32_t* __restrict__ rec_off, int64_t n,
+                                                      const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
+                                                      uint32_t* __restrict__ chunk_g) {
+    const uint32_t R = min(*R_dev, rec_cap);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cnt[i];
+        const uint32_t a = rec_off[i];
+        if (c == 0 || a >= R) continue;
+        const uint32_t b = (uint32_t)min<uint64_t>((uint64_t)a + c, R);  // records [a, b)
+        for (uint32_t k = a / PE_CHUNK; k <= (b - 1) / PE_CHUNK; k++) {
+            const uint32_t first = k * PE_CHUNK;
+            const uint32_t last = (uint32_t)min<uint64_t>((uint64_t)first + PE_CHUNK - 1, R - 1);
+            if (first >= a) chunk_g[2 * k] = (uint32_t)i;
+            if (last < b) chunk_g[2 * k + 1] = (uint32_t)i;
+        }
+    }
+}
+
 __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const ViewDev* __restrict__ views,
                                                              int words, SetDev st, int tws, int ths,
                                                              const uint32_t* __restrict__ mask,
@@ -1004,10 +1030,10 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
                                                              const uint32_t* __restrict__ R_dev, uint32_t rec_cap,
                                                              Records rec, uint32_t* __restrict__ sortkey,
                                                              uint32_t* __restrict__ order, int write_attr,
+                                                             const uint32_t* __restrict__ chunk_g,
                                                              uint32_t* __restrict__ flags) {
     __shared__ uint32_t s_off[PE_LDS];
     __shared__ GPre s_pre[PE_PRE];
-    __shared__ uint32_t s_lo, s_hi;
     const uint32_t Rall = *R_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0 && Rall > rec_cap) atomicOr(flags, FLAG_REC_OVERFLOW);
     const uint32_t R = min(Rall, rec_cap);
@@ -1015,15 +1041,8 @@ __global__ __launch_bounds__(PE_THREADS) void k_project_emit(GaussDev g, const V
     for (uint32_t k0 = blockIdx.x * PE_THREADS; k0 < R; k0 += gridDim.x * PE_THREADS) {
         const uint32_t k1 = min(k0 + PE_THREADS, R);  // exclusive
         __syncthreads();
-        if (threadIdx.x < 64) {
-            const uint32_t lo = wave_last_le(rec_off, n, k0);
-            if (threadIdx.x == 0) s_lo = lo;
-        } else if (threadIdx.x < 128) {
-            const uint32_t hi = wave_last_le(rec_off, n, k1 - 1);
-            if (threadIdx.x == 64) s_hi = hi;
-        }
-        __syncthreads();
-        const uint32_t lo = s_lo, ng = s_hi - s_lo + 1;
+        // the Gaussians owning the chunk's first and last records
+        const uint32_t lo = chunk_g[2 * (k0 / PE_CHUNK)], ng = chunk_g[2 * (k0 / PE_CHUNK) + 1] - lo + 1;
         const bool staged = ng <= PE_LDS;
         if (staged)
             for (uint32_t j = threadIdx.x; j < ng; j += PE_THREADS) s_off[j] = rec_off[lo + j];
@@ -3348,15 +3367,16 @@ static int ilog2(int x) {
 }
 
 void project_emit(const GaussDev& g, const ViewDev* views, const Header* hdr, int n_views_cap, SetDev st,
-                  int tw, int th, const uint32_t* mask, const uint32_t* rec_off, const uint32_t* R_dev,
-                  uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order, bool write_attr, uint32_t* flags,
-                  hipStream_t s) {
+                  int tw, int th, const uint32_t* mask, const uint32_t* cnt, const uint32_t* rec_off,
+                  const uint32_t* R_dev, uint32_t rec_cap, Records rec, uint32_t* sortkey, uint32_t* order,
+                  bool write_attr, uint32_t* chunk_g, uint32_t* flags, hipStream_t s) {
     (void)hdr;
     if (g.n == 0 || rec_cap == 0) return;
     int words = (n_views_cap + 31) / 32;
+    k_chunk_owners<<<grid_for(g.n, 256, 16384), 256, 0, s>>>(cnt, rec_off, g.n, R_dev, rec_cap, chunk_g);
     k_project_emit<<<grid_for(rec_cap, PE_THREADS, 32768), PE_THREADS, 0, s>>>(
         g, views, words, st, ilog2(tw), ilog2(th), mask, rec_off, R_dev, rec_cap, rec, sortkey, order,
-        write_attr ? 1 : 0, flags);
+        write_attr ? 1 : 0, chunk_g, flags);
 }
 
 int scan_blocks(uint64_t cap) {
